@@ -1,0 +1,200 @@
+"""Explicit assembly of the frozen transport operator (oracle; test infrastructure).
+
+Follows Section 3.1 (face-based upwinding, eq. (discrete-row) and
+eq. (transport-system)) and Section 3.2 (scale-consistent right-hand side).
+Readings where the paper defers to an uncited reference or is silent:
+
+  * face averages (the paper points to an external discretisation): for the face
+    between p and p+e_d, G_f = (G_p + G_{p+e_d})/2, the normal derivative is the
+    compact difference g_d = T_{p+e_d} - T_p, and each tangential derivative is
+    the mean of the nodal central differences at p and p+e_d (one-sided on the
+    first and last node of an axis); a_f = sum_{d'} (G_f)_{d d'} g_{d'} summed in
+    axis order;
+  * coupling: the minus face of p contributes c = max(a_f, 0) from p-e_d, the
+    plus face contributes c = max(-a_f, 0) from p+e_d; an edge exists iff the
+    normalised weight is strictly positive (Section 3.3);
+  * the source row and rows without inflow are identity rows; the calibration
+    c_i = l_i / s_i with l = A T then gives c_src = 0 (T_src = 0) and
+    c_i = T_i / s_i on inflow-less rows.
+
+All sums are evaluated left to right in a fixed order (axis order for a_f,
+slot order minus/plus per axis for d_p and for (W T)_p), with no fused
+multiply-add, so the sign of every a_f is a deterministic FP64 decision.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import scipy.sparse as sp
+
+
+def _grid_shape(dim, n1, n2, n3):
+    return (n3, n2, n1) if dim == 3 else (n3, n1)
+
+
+def _metric_full(G, dim, shape):
+    """Per-node symmetric metric as a dim x dim nested list of grid arrays."""
+    if dim == 3:
+        gxx, gyy, gzz, gxy, gxz, gyz = (G[:, c].reshape(shape) for c in range(6))
+        return [[gxx, gxy, gxz], [gxy, gyy, gyz], [gxz, gyz, gzz]]
+    gxx, gzz, gxz = (G[:, c].reshape(shape) for c in range(3))
+    return [[gxx, gxz], [gxz, gzz]]
+
+
+def _sl(ndim, ax, s):
+    idx = [slice(None)] * ndim
+    idx[ax] = s
+    return tuple(idx)
+
+
+def _central(T, ax):
+    """Nodal derivative along array axis ax: central in the interior, one-sided
+    at the first and last node; zero if the axis has a single node."""
+    n = T.shape[ax]
+    D = np.zeros_like(T)
+    if n == 1:
+        return D
+    nd = T.ndim
+    D[_sl(nd, ax, 0)] = T[_sl(nd, ax, 1)] - T[_sl(nd, ax, 0)]
+    D[_sl(nd, ax, n - 1)] = T[_sl(nd, ax, n - 1)] - T[_sl(nd, ax, n - 2)]
+    if n > 2:
+        D[_sl(nd, ax, slice(1, n - 1))] = 0.5 * (T[_sl(nd, ax, slice(2, n))]
+                                                 - T[_sl(nd, ax, slice(0, n - 2))])
+    return D
+
+
+def face_coefficients(dim, n1, n2, n3, G, T):
+    """a_f for every interior face, per logical axis d.
+
+    Returns a list over d of arrays shaped like the grid with n_d - 1 entries
+    along that axis: entry at p is the face between p and p + e_d.  Also
+    returns the face derivative vectors g (list over d of lists over d').
+    Section 3.1: the signed coefficient -a_f selects the upstream side.
+    """
+    shape = _grid_shape(dim, n1, n2, n3)
+    Tg = np.asarray(T, dtype=np.float64).reshape(shape)
+    Gm = _metric_full(np.asarray(G, dtype=np.float64), dim, shape)
+    nd = len(shape)
+    D = [_central(Tg, nd - 1 - dd) for dd in range(dim)]
+    a_faces, g_faces = [], []
+    for d in range(dim):
+        ax = nd - 1 - d
+        n = shape[ax]
+        lo = _sl(nd, ax, slice(0, n - 1))
+        hi = _sl(nd, ax, slice(1, n))
+        g = []
+        for dp in range(dim):
+            if dp == d:
+                g.append(Tg[hi] - Tg[lo])
+            else:
+                g.append(0.5 * (D[dp][lo] + D[dp][hi]))
+        a = None
+        for dp in range(dim):
+            Gf = 0.5 * (Gm[d][dp][lo] + Gm[d][dp][hi])
+            term = Gf * g[dp]
+            a = term if a is None else a + term
+        a_faces.append(a)
+        g_faces.append(g)
+    return a_faces, g_faces
+
+
+@dataclass
+class OracleOperator:
+    """A = I - W (CSR, natural node order, row i holds w_ij for edges j -> i),
+    calibration c, receivers, and the grid description."""
+    dim: int
+    n1: int
+    n2: int
+    n3: int
+    W: sp.csr_matrix
+    c: np.ndarray
+    src: int
+    rcv: np.ndarray
+    T: np.ndarray
+    s: np.ndarray
+
+    @property
+    def N(self):
+        return self.n1 * self.n2 * self.n3
+
+    def A(self):
+        return (sp.identity(self.N, format="csr") - self.W).tocsr()
+
+    def WT(self):
+        return self.W.T.tocsr()
+
+
+def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None) -> OracleOperator:
+    """Assemble W and c (Section 3.1 eq. (discrete-row), Section 3.2).
+
+    parity: pinned by the manufactured tangent test (first-order convergence to
+    eq. (test-dT), Table 1), the flat-grid causal-order case, the 1-D closed
+    form, the exact scaling identity and the reversal criterion.
+    """
+    shape = _grid_shape(dim, n1, n2, n3)
+    N = n1 * n2 * n3
+    T = np.asarray(T, dtype=np.float64).reshape(N)
+    s = np.asarray(s, dtype=np.float64).reshape(N)
+    a_faces, _ = face_coefficients(dim, n1, n2, n3, G, T)
+    nd = len(shape)
+    ids = np.arange(N, dtype=np.int64).reshape(shape)
+    # slot order: axis 0 minus, axis 0 plus, axis 1 minus, ...
+    slot_c, slot_j = [], []
+    for d in range(dim):
+        ax = nd - 1 - d
+        n = shape[ax]
+        a = a_faces[d]
+        # minus face of node p (p = lo+1): coupling from p - e_d
+        cm = np.zeros(shape)
+        jm = np.full(shape, -1, dtype=np.int64)
+        cm[_sl(nd, ax, slice(1, n))] = np.maximum(a, 0.0)
+        jm[_sl(nd, ax, slice(1, n))] = ids[_sl(nd, ax, slice(0, n - 1))]
+        # plus face of node p (p = lo): coupling from p + e_d
+        cp = np.zeros(shape)
+        jp = np.full(shape, -1, dtype=np.int64)
+        cp[_sl(nd, ax, slice(0, n - 1))] = np.maximum(-a, 0.0)
+        jp[_sl(nd, ax, slice(0, n - 1))] = ids[_sl(nd, ax, slice(1, n))]
+        slot_c += [cm.reshape(N), cp.reshape(N)]
+        slot_j += [jm.reshape(N), jp.reshape(N)]
+    dsum = np.zeros(N)
+    for cs in slot_c:
+        dsum = dsum + cs
+    active = dsum > 0.0
+    active[src] = False
+    rows, cols, vals = [], [], []
+    wslots = []
+    for cs, js in zip(slot_c, slot_j):
+        w = np.zeros(N)
+        m = active & (cs > 0.0)
+        w[m] = cs[m] / dsum[m]
+        wslots.append((w, js))
+        sel = np.nonzero(w > 0.0)[0]
+        rows.append(sel)
+        cols.append(js[sel])
+        vals.append(w[sel])
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    vals = np.concatenate(vals)
+    W = sp.csr_matrix((vals, (rows, cols)), shape=(N, N))
+    W.sum_duplicates()
+    W.sort_indices()
+    # l = A T = T - W T, slot order; c = l / s (Section 3.2)
+    acc = np.zeros(N)
+    for w, js in wslots:
+        contrib = np.zeros(N)
+        m = w > 0.0
+        contrib[m] = w[m] * T[js[m]]
+        acc = acc + contrib
+    ell = T - acc
+    c = ell / s
+    if rcv is None:
+        rcv = np.zeros(0, dtype=np.int64)
+    return OracleOperator(dim=dim, n1=n1, n2=n2, n3=n3, W=W, c=c, src=int(src),
+                          rcv=np.asarray(rcv, dtype=np.int64), T=T, s=s)
+
+
+def assemble_workload(wl, alpha: int) -> OracleOperator:
+    """Assemble the operator of source alpha of a workloads.Workload."""
+    return assemble(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T[alpha], wl.s, int(wl.src[alpha]),
+                    wl.rcv)
