@@ -1,0 +1,219 @@
+"""Benchmark: paired J + J^T applications per second over sources x right-hand
+sides, the primal and transpose frozen full-metric tangent transport through
+the SCC condensation graph (Algorithm 1, Phase III), on one MI355X.
+
+One step = one paired application over the whole batch: J from a broadcast
+model-space block p [N][B] to receiver data [S][R][B], then J^T from receiver
+data to the source-summed model-space gradient [N][B] (Section 4.4).  Inputs
+are resident in HBM before the timed region.  Setup (Phase I) runs once before
+timing and is reported separately.
+
+Prints one JSON line.  Default workload: the 201 x 201 x 101 deformed 3-D grid,
+64 sources x 16 right-hand sides, 400 surface receivers, FP64.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(stats_list, B, vbytes, wbytes, direction):
+    """Bytes one launch of the dominant sweep kernel must move, summed over
+    sources: the input and output vectors once per (source, rhs)
+    (2 * vbytes * N * B), plus the source's packed state read once: 8 B of
+    meta per node, the value records (1 + edges per node) * wbytes and the
+    FP64 SCC block matrices 8 * sum k^2.  Predecessor re-reads are counted as
+    cache hits."""
+    total = 0
+    for st in stats_list:
+        N, E, k2 = st["N"], st["E"], st["sum_k2"]
+        total += 2 * vbytes * N * B + 8 * N + wbytes * (N + E) + 8 * k2
+    return total
+
+
+def cpu_baseline(wl, n_src, B, seed):
+    """The CPU oracle (explicit assembly + Gauss-Seidel directional sweeping to
+    convergence, plain C, OpenMP over right-hand sides) on a bounded sample."""
+    import oracle as O
+    from oracle.assembly import assemble_workload
+
+    threads = min(16, os.cpu_count() or 1)
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal((wl.N, B))
+    y = rng.standard_normal((wl.rcv.shape[0], B))
+    t0 = time.perf_counter()
+    cycles = []
+    for a in range(n_src):
+        op = assemble_workload(wl, a)
+        q = op.c[:, None] * p
+        x, cy1 = O.gs_solve(op, op.W, q, nthreads=threads, return_cycles=True)
+        r = O.solve.scatter_receivers(op, y)
+        lam, cy2 = O.gs_solve(op, op.WT(), r, nthreads=threads, return_cycles=True)
+        cycles += list(cy1) + list(cy2)
+    dt = time.perf_counter() - t0
+    pairs = n_src * B
+    return {"value": pairs / dt, "unit": "paired applies/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_src} source(s) x {B} rhs of the same workload, J (broadcast p -> nodes) + "
+                      f"J^T (receivers -> nodes), Gauss-Seidel sweeping to convergence "
+                      f"(mean {np.mean(cycles):.1f} cycles of {2 ** wl.dim} sweeps), assembly included; "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c4", choices=["c2", "c3", "c4"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--sources", type=int, default=0, help="use only the first S sources (0: all)")
+    ap.add_argument("--rhs-per-group", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sources", type=int, default=1)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2609_14982_amd as fm
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+
+    t0 = time.perf_counter()
+    wl = W.config(args.config, with_T=False)
+    if args.sources:
+        wl.src = wl.src[: args.sources]
+    log(f"workload {args.config}: grid {wl.n1}x{wl.n2}x{wl.n3} N={wl.N} S={wl.S} B={wl.B} "
+        f"R={wl.rcv.shape[0]} ({time.perf_counter() - t0:.1f}s)")
+    t1 = time.perf_counter()
+    W.eikonal(wl)
+    log(f"first-arrival traveltimes for {wl.S} sources: {time.perf_counter() - t1:.1f}s")
+    t1 = time.perf_counter()
+    states = fm.build_frozen_states(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T, wl.s, wl.src, wl.rcv)
+    setup_wall = time.perf_counter() - t1
+    stats = [st.stats() for st in states]
+    log(f"setup (host, {min(16, os.cpu_count() or 1)} threads): {setup_wall:.1f}s; "
+        f"levels fwd max {max(s['levels_fwd'] for s in stats)}, SCCs {sum(s['n_scc'] for s in stats)}, "
+        f"largest {max(s['largest_scc'] for s in stats)}")
+
+    prec = fm.FM_FP64 if args.precision == "fp64" else fm.FM_FP32
+    dt = torch.float64 if prec == fm.FM_FP64 else torch.float32
+    vbytes = 8 if prec == fm.FM_FP64 else 4
+    tuning = {}
+    if args.rhs_per_group:
+        tuning["rhs_per_group"] = args.rhs_per_group
+    if args.threads:
+        tuning["threads"] = args.threads
+    S, N, B, R = wl.S, wl.N, wl.B, wl.rcv.shape[0]
+    stream = torch.cuda.current_stream()
+    t1 = time.perf_counter()
+    batch = fm.Batch(states, B, prec, tuning=tuning or None, stream=stream)
+    torch.cuda.synchronize()
+    log(f"batch create + upload: {time.perf_counter() - t1:.1f}s, tuning {batch.tuning()}")
+
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(4000)
+    p = torch.randn((N, B), device=dev, dtype=dt, generator=gen)
+    y = torch.randn((S, R, B), device=dev, dtype=dt, generator=gen)
+    d = torch.empty((S, R, B), device=dev, dtype=dt)
+    g = torch.empty((N, B), device=dev, dtype=dt)
+
+    def step(evs=None):
+        if evs is not None:
+            evs[0].record(stream)
+        batch.apply_J(p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS)
+        if evs is not None:
+            evs[1].record(stream)
+        batch.apply_JT(y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED)
+        if evs is not None:
+            evs[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup {args.warmup} steps done")
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    tJ = np.array([e[0].elapsed_time(e[1]) for e in events])
+    tT = np.array([e[1].elapsed_time(e[2]) for e in events])
+    ms_per_step = wall * 1e3 / args.steps
+    log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; J {tJ.mean():.3f} ms, J^T {tT.mean():.3f} ms")
+
+    bytes_J = algorithmic_bytes(stats, B, vbytes, vbytes, "J")
+    bytes_T = algorithmic_bytes(stats, B, vbytes, vbytes, "JT")
+    gbs_J = bytes_J / (tJ.mean() * 1e-3) / 1e9
+    gbs_T = bytes_T / (tT.mean() * 1e-3) / 1e9
+    dom = "J" if tJ.mean() >= tT.mean() else "JT"
+    ach = gbs_J if dom == "J" else gbs_T
+    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": "k_forward (apply_J)" if dom == "J" else "k_reverse (apply_JT)",
+            "bytes_per_launch": bytes_J if dom == "J" else bytes_T,
+            "launch_ms": round(float(tJ.mean() if dom == "J" else tT.mean()), 4),
+            "other": {"J_GBs": round(gbs_J, 1), "JT_GBs": round(gbs_T, 1)}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {args.cpu_sources} source(s) x {B} rhs")
+        W.eikonal(wl) if wl.T is None else None
+        cpu = cpu_baseline(wl, args.cpu_sources, B, 4001)
+        log(f"cpu baseline: {cpu['value']:.3f} paired applies/s")
+
+    value = S * B / (ms_per_step * 1e-3)
+    res = {
+        "metric": "J+J^T paired applies/s (source x rhs) on a 3-D deformed grid",
+        "value": round(value, 2),
+        "unit": "paired applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == fm.FM_FP64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {wl.n1}x{wl.n2}x{wl.n3} deformed grid, "
+                               f"{S} sources x {B} rhs, {R} receivers",
+                   "grid": [wl.n1, wl.n2, wl.n3], "sources": S, "rhs": B, "receivers": R,
+                   "setup_s": round(setup_wall, 2),
+                   "levels_fwd_max": max(s["levels_fwd"] for s in stats),
+                   "n_scc_total": sum(s["n_scc"] for s in stats),
+                   "largest_scc": max(s["largest_scc"] for s in stats),
+                   "J_ms": round(float(tJ.mean()), 4), "JT_ms": round(float(tT.mean()), 4)},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * fmbtf: frozen full-metric Eikonal tangent transport through its SCC
+ * condensation graph (block-triangular form), applied on an MI355X (gfx950).
+ *
+ * The operation (paper: "Efficient Matrix-Free Gauss-Newton Traveltime
+ * Tomography on Full-Metric Deformed Grids"):
+ *
+ *   A = I - W                    face-upwind frozen transport, Section 3.1,
+ *                                eq. (discrete-row) and eq. (transport-system)
+ *   C = diag(c), c_i = l_i / s_i with l = A T    Section 3.2
+ *   J_alpha   = P_alpha A^{-1} C                 eq. (source-jacobian), M = I, D = 0
+ *   J_alpha^T = C A^{-T} P_alpha^T               eq. (source-transpose)
+ *   J^T y     = sum_alpha J_alpha^T y_alpha       Section 4.4 (multi-source stacking)
+ *
+ * A^{-1} and A^{-T} are applied exactly (up to rounding) by traversing the
+ * condensation DAG of the dependency graph (edge j -> i iff w_ij > 0,
+ * Section 3.3) in topological order: scalar substitution on singleton
+ * components and a local block solve on every nontrivial strongly connected
+ * component (Section 4.1, Proposition 3; Section 4.3).  The state built once
+ * per frozen source (Section 4.3, the setup S_alpha) is reused for every
+ * right-hand side in both directions (Algorithm 1, Phases I and III).
+ *
+ * Conventions shared by every call
+ *   node id      n = i + n1*(j + n2*k), i fastest; 2-D grids use (i, k), n2 = 1
+ *   metric G     [N][6] = (Gxx,Gyy,Gzz,Gxy,Gxz,Gyz) in 3-D, [N][3] = (Gxx,Gzz,Gxz)
+ *                in 2-D, in logical index units (Section 2.2, eq. (metric-eikonal))
+ *   batches      vectors are [N][B] with the right-hand-side index fastest;
+ *                per-source vectors are [S][N][B]; receiver data [S][R][B]
+ *   ownership    every pointer argument is owned by the caller.  Host inputs of
+ *                the build calls are copied and may be freed on return.  Device
+ *                pointers of the apply calls must stay valid until the work
+ *                enqueued on the batch stream has finished.
+ *   errors       every int-returning call returns FM_OK (0) or a negative code;
+ *                fm_last_error() then describes the failure (thread-local).
+ *   threads      states and batches may be used from one thread at a time.
+ */
+#ifndef FMBTF_H
+#define FMBTF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FM_OK 0
+#define FM_EINVAL (-1)     /* bad shape, index, non-finite input, s <= 0, T_src != 0, mode */
+#define FM_ESINGULAR (-2)  /* an SCC block has a pivot below 1e-14 * ||A_C||_inf (Section 4.2) */
+#define FM_ENOMEM (-3)     /* host or device allocation failed */
+#define FM_EHIP (-4)       /* a HIP runtime call failed */
+#define FM_ESTATE (-5)     /* object used in a state that does not allow the call */
+
+/* precision of a batch (Section 4.3 factors are always formed in FP64) */
+#define FM_FP64 64
+#define FM_FP32 32
+
+/* input / output layouts of the apply calls */
+#define FM_DS_PER_PAIR 0    /* ds [S][N][B]: one slowness perturbation per (source, rhs) */
+#define FM_DS_BROADCAST 1   /* ds [N][B]: one model-space vector shared by all sources */
+#define FM_OUT_NODES 0      /* J: dT at every node, [S][N][B] */
+#define FM_OUT_RECEIVERS 1  /* J: dT sampled at the receivers, [S][R][B] */
+#define FM_W_NODES 0        /* J^T input: nodal weights [S][N][B] */
+#define FM_W_RECEIVERS 1    /* J^T input: receiver data [S][R][B], scattered by P^T */
+#define FM_JT_PER_SOURCE 0  /* J^T output: c_alpha * lambda_alpha per source, [S][N][B] */
+#define FM_JT_SUMMED 1      /* J^T output: sum over sources in source order, [N][B] */
+
+typedef struct fm_grid {
+    int32_t dim;            /* 2 or 3 */
+    int64_t n1, n2, n3;     /* nodes per logical axis; n2 = 1 in 2-D */
+    const double* G;        /* host pointer, metric as described above */
+} fm_grid;
+
+typedef struct fm_state fm_state;   /* one frozen source: W, c, graph, levels, SCC factors */
+typedef struct fm_batch fm_batch;   /* S states + preallocated device scratch for B rhs */
+
+typedef struct fm_stats {
+    int64_t N;              /* transport unknowns */
+    int64_t E;              /* dependency edges (w_ij > 0) */
+    int32_t levels_fwd;     /* levels of the condensation DAG (primal traversal) */
+    int32_t levels_rev;     /* levels of the reverse traversal (transpose) */
+    int32_t n_scc;          /* nontrivial SCCs (size > 1) */
+    int32_t largest_scc;
+    int64_t n_cyc;          /* nodes in nontrivial SCCs */
+    int64_t sum_k2;         /* sum of squared SCC sizes (dense block storage) */
+    int64_t n_vio;          /* edges j -> i with T_j > T_i (Section 3.4) */
+    int64_t n_unr;          /* nodes left by scalar Kahn elimination (Section 3.5) */
+    double f_vio, f_cyc, f_unr;   /* eq. (graph-fractions) */
+    double setup_seconds;   /* host time of the build */
+    int64_t state_bytes;    /* bytes of the packed per-source state (one precision) */
+} fm_stats;
+
+/* Launch schedule of a batch; zero fields take the library default. */
+typedef struct fm_tuning {
+    int32_t rhs_per_group;  /* right-hand sides handled by one workgroup: 1,2,4,8,16 */
+    int32_t threads;        /* workgroup size: 256, 512 or 1024 */
+    int32_t min_lds_bytes;  /* LDS reserved per workgroup (limits workgroups per CU) */
+    int32_t xcd_aware;      /* 1 or 0 (default): keep the groups of one source on one XCD; -1: off */
+} fm_tuning;
+
+/*
+ * Build the frozen state of one source (Algorithm 1, Phase I, lines 7-10):
+ * face-upwind coefficients and row normalisation (Section 3.1), calibration
+ * c = (A T) / s (Section 3.2), dependency graph (Section 3.3), SCCs and a
+ * topological level schedule of the condensation DAG (Section 4.1), and a
+ * partially pivoted LU of every nontrivial SCC block (Section 4.3).
+ *   g         grid and host metric
+ *   T, s      host [N] background traveltime (T[src_node] must be 0) and slowness (> 0)
+ *   src_node  on-grid source node; its row is an identity row with c = 0
+ *   rcv_nodes host [n_rcv] receiver nodes (P_alpha is the selection; duplicates allowed)
+ *   out       receives the new state (host-side only until a batch uses it)
+ * Errors: FM_EINVAL, FM_ESINGULAR, FM_ENOMEM.
+ */
+int fm_build_frozen_state(const fm_grid* g, const double* T, const double* s, int64_t src_node,
+                          const int64_t* rcv_nodes, int32_t n_rcv, fm_state** out);
+
+/*
+ * Build S states at once on up to nthreads host threads (sources are
+ * independent, Section 4.4).  T is [S][N], rcv_nodes is [S][n_rcv]; out[S]
+ * receives the states.  On error no state is returned (all are freed).
+ */
+int fm_build_frozen_states(const fm_grid* g, int32_t S, const double* T, const double* s,
+                           const int64_t* src_nodes, const int64_t* rcv_nodes, int32_t n_rcv,
+                           int32_t nthreads, fm_state** out);
+
+/* Structural statistics of a state (Section 5.2, eq. (graph-fractions)). */
+int fm_state_stats(const fm_state* st, fm_stats* out);
+
+/*
+ * Copy the assembled operator out, in natural node order, for host-side
+ * checks: rowptr [N+1], col [E] (predecessor j of row i, ascending), w [E],
+ * c [N].  Any pointer may be NULL to skip that array.
+ */
+int fm_state_export_operator(const fm_state* st, int64_t* rowptr, int32_t* col, double* w,
+                             double* c);
+
+/*
+ * Copy the graph analysis out: comp [N] SCC id (ids number the components in
+ * a topological order of the condensation DAG), level_fwd [N] and level_rev [N]
+ * (longest-path level of the node's component from the sources / towards the
+ * sinks of the condensation DAG).  Any pointer may be NULL.
+ */
+int fm_state_export_graph(const fm_state* st, int32_t* comp, int32_t* level_fwd,
+                          int32_t* level_rev);
+
+/* Free a state and its device copy.  Free every batch that uses it first. */
+void fm_state_free(fm_state* st);
+
+/*
+ * Create a batch over S states for B right-hand sides in FM_FP64 or FM_FP32
+ * on the current HIP device.  Uploads the states that are not yet on the
+ * device and allocates all scratch ([S][N][B] of the batch precision) so that
+ * the apply calls allocate nothing.  tuning may be NULL.  hip_stream is a
+ * hipStream_t (NULL: the null stream).  All states must share one grid shape.
+ * Errors: FM_EINVAL, FM_ENOMEM, FM_EHIP.
+ */
+int fm_batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precision,
+                    const fm_tuning* tuning, void* hip_stream, fm_batch** out);
+
+/* Change the stream later applies are enqueued on. */
+int fm_batch_set_stream(fm_batch* b, void* hip_stream);
+
+/* The schedule the batch resolved (defaults filled in). */
+int fm_batch_tuning(const fm_batch* b, fm_tuning* out);
+
+/*
+ * Primal action dT = J ds for every (source, rhs) pair (Algorithm 1, lines
+ * 15-16): q = c * ds, forward traversal of the condensation DAG, then P.
+ *   ds   device, layout per ds_mode (FM_DS_PER_PAIR or FM_DS_BROADCAST)
+ *   out  device, layout per out_mode (FM_OUT_NODES or FM_OUT_RECEIVERS),
+ *        fully overwritten
+ * Enqueued on the batch stream; no allocation, no synchronisation, so the
+ * call may be captured in a HIP graph.  Errors: FM_EINVAL, FM_EHIP.
+ */
+int fm_apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode);
+
+/*
+ * Transpose action (Algorithm 1, lines 17-18): r = w (FM_W_NODES) or P^T w
+ * (FM_W_RECEIVERS), reverse traversal solving A^T lambda = r (singletons by
+ * transposed substitution, SCC blocks with the transpose of the same
+ * factors), then c * lambda per source (FM_JT_PER_SOURCE) or summed over the
+ * sources in source order (FM_JT_SUMMED).  Same stream and capture rules as
+ * fm_apply_J.  Errors: FM_EINVAL, FM_EHIP.
+ */
+int fm_apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode);
+
+/* Free a batch (its scratch); the states stay valid. */
+void fm_batch_free(fm_batch* b);
+
+/* Message for the last nonzero return on this thread ("" if none). */
+const char* fm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMBTF_H */

@@ -1,0 +1,281 @@
+"""ctypes marshalling for include/fmbtf.h (same names as the C calls)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_PKG, "libfmbtf.so")
+
+FM_OK, FM_EINVAL, FM_ESINGULAR, FM_ENOMEM, FM_EHIP, FM_ESTATE = 0, -1, -2, -3, -4, -5
+FM_FP64, FM_FP32 = 64, 32
+FM_DS_PER_PAIR, FM_DS_BROADCAST = 0, 1
+FM_OUT_NODES, FM_OUT_RECEIVERS = 0, 1
+FM_W_NODES, FM_W_RECEIVERS = 0, 1
+FM_JT_PER_SOURCE, FM_JT_SUMMED = 0, 1
+
+_ERRNAMES = {FM_EINVAL: "FM_EINVAL", FM_ESINGULAR: "FM_ESINGULAR", FM_ENOMEM: "FM_ENOMEM",
+             FM_EHIP: "FM_EHIP", FM_ESTATE: "FM_ESTATE"}
+
+SYMBOLS = (
+    "fm_build_frozen_state", "fm_build_frozen_states", "fm_state_stats",
+    "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
+    "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_apply_J",
+    "fm_apply_JT", "fm_batch_free", "fm_last_error",
+)
+
+
+class FmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class fm_grid(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n1", C.c_int64), ("n2", C.c_int64), ("n3", C.c_int64),
+                ("G", C.c_void_p)]
+
+
+class fm_stats(C.Structure):
+    _fields_ = [("N", C.c_int64), ("E", C.c_int64), ("levels_fwd", C.c_int32),
+                ("levels_rev", C.c_int32), ("n_scc", C.c_int32), ("largest_scc", C.c_int32),
+                ("n_cyc", C.c_int64), ("sum_k2", C.c_int64), ("n_vio", C.c_int64),
+                ("n_unr", C.c_int64), ("f_vio", C.c_double), ("f_cyc", C.c_double),
+                ("f_unr", C.c_double), ("setup_seconds", C.c_double), ("state_bytes", C.c_int64)]
+
+
+class fm_tuning(C.Structure):
+    _fields_ = [("rhs_per_group", C.c_int32), ("threads", C.c_int32),
+                ("min_lds_bytes", C.c_int32), ("xcd_aware", C.c_int32)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libfmbtf.so (raises if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is not built: run __graft_entry__.build()")
+    lib = C.CDLL(_LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "fm_build_frozen_state": (C.c_int, [vp, vp, vp, i64, vp, i32, vp]),
+        "fm_build_frozen_states": (C.c_int, [vp, i32, vp, vp, vp, vp, i32, i32, vp]),
+        "fm_state_stats": (C.c_int, [vp, vp]),
+        "fm_state_export_operator": (C.c_int, [vp, vp, vp, vp, vp]),
+        "fm_state_export_graph": (C.c_int, [vp, vp, vp, vp]),
+        "fm_state_free": (None, [vp]),
+        "fm_batch_create": (C.c_int, [vp, i32, i32, i32, vp, vp, vp]),
+        "fm_batch_set_stream": (C.c_int, [vp, vp]),
+        "fm_batch_tuning": (C.c_int, [vp, vp]),
+        "fm_apply_J": (C.c_int, [vp, vp, i32, vp, i32]),
+        "fm_apply_JT": (C.c_int, [vp, vp, i32, vp, i32]),
+        "fm_batch_free": (None, [vp]),
+        "fm_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    lib = load()
+    return [s for s in SYMBOLS if hasattr(lib, s)]
+
+
+def _check(rc):
+    if rc != FM_OK:
+        msg = load().fm_last_error().decode(errors="replace")
+        raise FmError(rc, msg)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _grid(dim, n1, n2, n3, G):
+    g = fm_grid()
+    g.dim, g.n1, g.n2, g.n3 = int(dim), int(n1), int(n2), int(n3)
+    g.G = G.ctypes.data
+    return g
+
+
+class State:
+    """One frozen source state (fm_state*)."""
+
+    def __init__(self, ptr, N, dim, n, R):
+        self._ptr = C.c_void_p(ptr)
+        self.N = N
+        self.dim = dim
+        self.n = n
+        self.R = R
+
+    @property
+    def ptr(self):
+        return self._ptr
+
+    def stats(self) -> dict:
+        st = fm_stats()
+        _check(load().fm_state_stats(self._ptr, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in fm_stats._fields_}
+
+    def export_operator(self):
+        """(rowptr [N+1], col [E], w [E], c [N]) of W in natural node order."""
+        lib = load()
+        rowptr = np.empty(self.N + 1, dtype=np.int64)
+        _check(lib.fm_state_export_operator(self._ptr, rowptr.ctypes.data, None, None, None))
+        E = int(rowptr[-1])
+        col = np.empty(E, dtype=np.int32)
+        w = np.empty(E, dtype=np.float64)
+        c = np.empty(self.N, dtype=np.float64)
+        _check(lib.fm_state_export_operator(self._ptr, rowptr.ctypes.data, col.ctypes.data,
+                                            w.ctypes.data, c.ctypes.data))
+        return rowptr, col, w, c
+
+    def export_graph(self):
+        comp = np.empty(self.N, dtype=np.int32)
+        lf = np.empty(self.N, dtype=np.int32)
+        lr = np.empty(self.N, dtype=np.int32)
+        _check(load().fm_state_export_graph(self._ptr, comp.ctypes.data, lf.ctypes.data, lr.ctypes.data))
+        return comp, lf, lr
+
+    def free(self):
+        if self._ptr and self._ptr.value:
+            load().fm_state_free(self._ptr)
+            self._ptr = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build_frozen_state(dim, n1, n2, n3, G, T, s, src_node, rcv_nodes=()) -> State:
+    """fm_build_frozen_state with numpy host inputs."""
+    lib = load()
+    G, T, s = _f64(G), _f64(T), _f64(s)
+    rcv = _i64(rcv_nodes)
+    g = _grid(dim, n1, n2, n3, G)
+    out = C.c_void_p()
+    _check(lib.fm_build_frozen_state(C.byref(g), T.ctypes.data, s.ctypes.data, int(src_node),
+                                     rcv.ctypes.data if rcv.size else None, int(rcv.size), C.byref(out)))
+    return State(out.value, int(n1) * int(n2) * int(n3), dim, (n1, n2, n3), int(rcv.size))
+
+
+def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nthreads=None):
+    """fm_build_frozen_states: T [S][N]; rcv_nodes [R] (shared) or [S][R]."""
+    lib = load()
+    G, T, s = _f64(G), _f64(T), _f64(s)
+    src = _i64(src_nodes)
+    S = int(src.shape[0])
+    if rcv_nodes is None:
+        rcv = np.zeros((S, 0), dtype=np.int64)
+    else:
+        rcv = np.asarray(rcv_nodes, dtype=np.int64)
+        if rcv.ndim == 1:
+            rcv = np.broadcast_to(rcv[None, :], (S, rcv.shape[0]))
+        rcv = np.ascontiguousarray(rcv)
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
+    g = _grid(dim, n1, n2, n3, G)
+    outs = (C.c_void_p * S)()
+    _check(lib.fm_build_frozen_states(C.byref(g), S, T.ctypes.data, s.ctypes.data, src.ctypes.data,
+                                      rcv.ctypes.data if rcv.size else None, int(rcv.shape[1]),
+                                      int(nthreads), outs))
+    N = int(n1) * int(n2) * int(n3)
+    return [State(outs[a], N, dim, (n1, n2, n3), int(rcv.shape[1])) for a in range(S)]
+
+
+def _dptr(t, dtype, shape, what):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Batch:
+    """fm_batch*: S states, B right-hand sides, preallocated scratch."""
+
+    def __init__(self, states, B, precision=FM_FP64, tuning=None, stream=None):
+        import torch
+        lib = load()
+        self.states = list(states)
+        self.S = len(self.states)
+        self.B = int(B)
+        self.precision = precision
+        self.N = self.states[0].N
+        self.dtype = torch.float64 if precision == FM_FP64 else torch.float32
+        arr = (C.c_void_p * self.S)(*[st.ptr.value for st in self.states])
+        tun = None
+        if tuning is not None:
+            tun = fm_tuning()
+            for k, v in tuning.items():
+                setattr(tun, k, int(v))
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        out = C.c_void_p()
+        _check(lib.fm_batch_create(arr, self.S, self.B, int(precision),
+                                   C.byref(tun) if tun is not None else None,
+                                   C.c_void_p(stream.cuda_stream), C.byref(out)))
+        self._ptr = out
+        self.R = self.states[0].R
+
+    def tuning(self) -> dict:
+        t = fm_tuning()
+        _check(load().fm_batch_tuning(self._ptr, C.byref(t)))
+        return {k: getattr(t, k) for k, _ in fm_tuning._fields_}
+
+    def set_stream(self, stream):
+        _check(load().fm_batch_set_stream(self._ptr, C.c_void_p(stream.cuda_stream)))
+        self._stream = stream
+
+    def apply_J(self, ds, ds_mode, out, out_mode):
+        S, N, B = self.S, self.N, self.B
+        ds_shape = (S, N, B) if ds_mode == FM_DS_PER_PAIR else (N, B)
+        out_shape = (S, N, B) if out_mode == FM_OUT_NODES else (S, self.R, B)
+        _check(load().fm_apply_J(self._ptr, _dptr(ds, self.dtype, ds_shape, "ds"), int(ds_mode),
+                                 _dptr(out, self.dtype, out_shape, "out"), int(out_mode)))
+        return out
+
+    def apply_JT(self, w, w_mode, out, out_mode):
+        S, N, B = self.S, self.N, self.B
+        w_shape = (S, N, B) if w_mode == FM_W_NODES else (S, self.R, B)
+        out_shape = (S, N, B) if out_mode == FM_JT_PER_SOURCE else (N, B)
+        _check(load().fm_apply_JT(self._ptr, _dptr(w, self.dtype, w_shape, "w"), int(w_mode),
+                                  _dptr(out, self.dtype, out_shape, "out"), int(out_mode)))
+        return out
+
+    def free(self):
+        if getattr(self, "_ptr", None) is not None and self._ptr.value:
+            load().fm_batch_free(self._ptr)
+            self._ptr = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -1,0 +1,168 @@
+// extern "C" boundary of fmbtf (declared in include/fmbtf.h).
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+#include <vector>
+
+#include "internal.h"
+
+namespace fm {
+
+static thread_local char g_err[1024] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+// device.hip
+int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precision, const fm_tuning* tuning,
+                 void* stream, fm_batch** out);
+void batch_free(fm_batch* b);
+int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode);
+int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode);
+int batch_set_stream(fm_batch* b, void* stream);
+int batch_tuning(const fm_batch* b, fm_tuning* out);
+
+}  // namespace fm
+
+using fm::HostState;
+
+extern "C" {
+
+int fm_build_frozen_state(const fm_grid* g, const double* T, const double* s, int64_t src_node,
+                          const int64_t* rcv_nodes, int32_t n_rcv, fm_state** out) {
+    fm::clear_error();
+    if (!out) { fm::set_error("null output pointer"); return FM_EINVAL; }
+    *out = nullptr;
+    return fm::build_state(g, T, s, src_node, rcv_nodes, n_rcv, out);
+}
+
+int fm_build_frozen_states(const fm_grid* g, int32_t S, const double* T, const double* s,
+                           const int64_t* src_nodes, const int64_t* rcv_nodes, int32_t n_rcv,
+                           int32_t nthreads, fm_state** out) {
+    fm::clear_error();
+    if (!g || !T || !s || !src_nodes || !out || S < 1) { fm::set_error("bad arguments"); return FM_EINVAL; }
+    if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) { fm::set_error("grid sizes must be >= 1"); return FM_EINVAL; }
+    const int64_t N = g->n1 * g->n2 * g->n3;
+    std::vector<fm_state*> res(S, nullptr);
+    std::vector<int> rcs(S, FM_OK);
+    std::vector<std::string> msgs(S);
+    std::atomic<int32_t> next{0};
+    int nt = std::max(1, std::min<int32_t>(nthreads > 0 ? nthreads : 1, S));
+    auto worker = [&]() {
+        for (;;) {
+            int32_t a = next.fetch_add(1);
+            if (a >= S) break;
+            fm_state* st = nullptr;
+            int rc = fm_build_frozen_state(g, T + (size_t)a * N, s, src_nodes[a],
+                                           n_rcv > 0 ? rcv_nodes + (size_t)a * n_rcv : nullptr, n_rcv, &st);
+            rcs[a] = rc;
+            res[a] = st;
+            if (rc != FM_OK) msgs[a] = fm_last_error();
+        }
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; i++) th.emplace_back(worker);
+    worker();
+    for (auto& t : th) t.join();
+    for (int32_t a = 0; a < S; a++) {
+        if (rcs[a] != FM_OK) {
+            for (auto* p : res) fm_state_free(p);
+            fm::set_error("source %d: %s", a, msgs[a].c_str());
+            return rcs[a];
+        }
+    }
+    std::copy(res.begin(), res.end(), out);
+    return FM_OK;
+}
+
+int fm_state_stats(const fm_state* st, fm_stats* out) {
+    fm::clear_error();
+    if (!st || !out) { fm::set_error("null argument"); return FM_EINVAL; }
+    *out = st->stats;
+    return FM_OK;
+}
+
+int fm_state_export_operator(const fm_state* st, int64_t* rowptr, int32_t* col, double* w, double* c) {
+    fm::clear_error();
+    if (!st) { fm::set_error("null state"); return FM_EINVAL; }
+    const int nslot = 2 * st->dim;
+    int64_t e = 0;
+    for (int64_t p = 0; p < st->N; p++) {
+        if (rowptr) rowptr[p] = e;
+        // neighbours in ascending node id: -z, -y, -x, +x, +y, +z
+        static const int order3[6] = {4, 2, 0, 1, 3, 5};
+        static const int order2[4] = {2, 0, 1, 3};
+        const int* order = st->dim == 3 ? order3 : order2;
+        for (int q = 0; q < nslot; q++) {
+            int slot = order[q];
+            if (!(st->pmask[p] & (1u << slot))) continue;
+            int axis = slot >> 1;
+            int64_t j = (slot & 1) ? p + st->stride[axis] : p - st->stride[axis];
+            if (col) col[e] = (int32_t)j;
+            if (w) w[e] = st->w6[(size_t)p * 6 + slot];
+            e++;
+        }
+    }
+    if (rowptr) rowptr[st->N] = e;
+    if (c) std::memcpy(c, st->cal.data(), sizeof(double) * st->N);
+    return FM_OK;
+}
+
+int fm_state_export_graph(const fm_state* st, int32_t* comp, int32_t* level_fwd, int32_t* level_rev) {
+    fm::clear_error();
+    if (!st) { fm::set_error("null state"); return FM_EINVAL; }
+    for (int64_t p = 0; p < st->N; p++) {
+        int32_t c = st->comp[p];
+        if (comp) comp[p] = c;
+        if (level_fwd) level_fwd[p] = st->clev_f[c];
+        if (level_rev) level_rev[p] = st->clev_r[c];
+    }
+    return FM_OK;
+}
+
+void fm_state_free(fm_state* st) {
+    if (!st) return;
+    fm::free_device_state(st);
+    delete st;
+}
+
+int fm_batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precision, const fm_tuning* tuning,
+                    void* hip_stream, fm_batch** out) {
+    fm::clear_error();
+    return fm::batch_create(states, S, B, precision, tuning, hip_stream, out);
+}
+
+int fm_batch_set_stream(fm_batch* b, void* hip_stream) {
+    fm::clear_error();
+    return fm::batch_set_stream(b, hip_stream);
+}
+
+int fm_batch_tuning(const fm_batch* b, fm_tuning* out) {
+    fm::clear_error();
+    return fm::batch_tuning(b, out);
+}
+
+int fm_apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode) {
+    fm::clear_error();
+    return fm::apply_J(b, ds, ds_mode, out, out_mode);
+}
+
+int fm_apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode) {
+    fm::clear_error();
+    return fm::apply_JT(b, w, w_mode, out, out_mode);
+}
+
+void fm_batch_free(fm_batch* b) { fm::batch_free(b); }
+
+const char* fm_last_error(void) { return fm::g_err; }
+
+}  // extern "C"

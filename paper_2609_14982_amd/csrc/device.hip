@@ -1,0 +1,717 @@
+// Device side of fmbtf for gfx950 (CDNA4): state upload, batches and the
+// apply kernels.
+//
+// Work decomposition.  One workgroup owns one (source, group of RG
+// right-hand sides) pair and walks that source's condensation levels in
+// order (primal: Section 4.1, Proposition 3; transpose: Section 4.3).  Inside
+// a level every singleton is independent, so the workgroup's threads take the
+// level's nodes RG lanes per node (one lane per right-hand side, so a node's
+// RG values are one contiguous segment of the [N][B] vectors), and every
+// nontrivial SCC block of the level is solved cooperatively with its
+// right-hand sides staged in LDS.  A workgroup barrier separates levels; no
+// workgroup ever waits on another, so the launch needs no global
+// synchronisation, no atomics and no cross-XCD cache maintenance.  The
+// workgroups of one source are placed on one XCD so that they share that
+// XCD's L2 copy of the source's records.
+//
+// SCC blocks apply A_C^{-1}, formed once on the host from the pivoted LU
+// P_C A_C = L_C U_C of Section 4.3, as a dense matvec; the transpose solve
+// uses the same matrix read transposed (no second factorisation).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace fm {
+
+struct SrcDev {
+    const uint64_t* fmeta;
+    const void* fwts;
+    const int32_t* flvl_ptr;
+    const int32_t* flvl_nsc;
+    const int32_t* fblk_ptr;
+    const int32_t* fblk_id;
+    const uint64_t* rmeta;
+    const void* rwts;
+    const int32_t* rlvl_ptr;
+    const int32_t* rlvl_nsc;
+    const int32_t* rblk_ptr;
+    const int32_t* rblk_id;
+    const int32_t* blk_k;
+    const int32_t* blk_fpos;
+    const int32_t* blk_rpos;
+    const int64_t* blk_inv;
+    const double* inv;
+    const void* cal_nat;
+    const int32_t* rcv_node;
+    const int32_t* rcvlvl_ptr;
+    const int32_t* rcv_pos;
+    const int32_t* rcv_idx;
+    int32_t L_f, L_r, n_rcv, pad;
+};
+
+struct DeviceState {
+    void* blob = nullptr;        // all FP64 arrays and integer tables
+    void* blob32 = nullptr;      // FP32 copies of the records and calibration
+    SrcDev d{};                  // pointers into blob (FP64 records)
+    const void* fwts32 = nullptr;
+    const void* rwts32 = nullptr;
+    const void* cal32 = nullptr;
+    int device = -1;
+};
+
+}  // namespace fm
+
+struct fm_batch {
+    std::vector<fm::HostState*> states;
+    int32_t S = 0, B = 0, prec = 64, R = 0;
+    fm_tuning tun{};
+    hipStream_t stream = nullptr;
+    fm::SrcDev* d_src = nullptr;     // [S]
+    void* scratch = nullptr;         // [S][N][B] of the batch precision
+    int64_t N = 0;
+    int64_t st1 = 1, st2 = 1;
+    int device = -1;
+    size_t lds_bytes = 0;
+    int32_t grid = 0, per_xcd = 0, items = 0;
+};
+
+namespace fm {
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                    \
+            return FM_EHIP;                                                              \
+        }                                                                                \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// upload
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Arena {
+    size_t off = 0;
+    template <class T>
+    size_t add(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        size_t at = off;
+        off += count * sizeof(T);
+        return at;
+    }
+};
+
+template <class T>
+int put(char* base, size_t at, const std::vector<T>& v) {
+    if (v.empty()) return FM_OK;
+    hipError_t e = hipMemcpy(base + at, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        set_error("hipMemcpy of state arrays failed: %s", hipGetErrorString(e));
+        return FM_EHIP;
+    }
+    return FM_OK;
+}
+
+}  // namespace
+
+int upload_state(HostState* st) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (st->dev && st->dev->device == dev) return FM_OK;
+    if (st->dev) {
+        set_error("state already lives on device %d (current device %d)", st->dev->device, dev);
+        return FM_ESTATE;
+    }
+    const Packed& pk = st->pk;
+    Arena ar;
+    size_t o_fmeta = ar.add<uint64_t>(pk.fmeta.size());
+    size_t o_fwts = ar.add<double>(pk.fwts.size());
+    size_t o_flp = ar.add<int32_t>(pk.flvl_ptr.size());
+    size_t o_fln = ar.add<int32_t>(pk.flvl_nsc.size());
+    size_t o_fbp = ar.add<int32_t>(pk.fblk_ptr.size());
+    size_t o_fbi = ar.add<int32_t>(pk.fblk_id.size());
+    size_t o_rmeta = ar.add<uint64_t>(pk.rmeta.size());
+    size_t o_rwts = ar.add<double>(pk.rwts.size());
+    size_t o_rlp = ar.add<int32_t>(pk.rlvl_ptr.size());
+    size_t o_rln = ar.add<int32_t>(pk.rlvl_nsc.size());
+    size_t o_rbp = ar.add<int32_t>(pk.rblk_ptr.size());
+    size_t o_rbi = ar.add<int32_t>(pk.rblk_id.size());
+    size_t o_bk = ar.add<int32_t>(pk.blk_k.size());
+    size_t o_bfp = ar.add<int32_t>(pk.blk_fpos.size());
+    size_t o_brp = ar.add<int32_t>(pk.blk_rpos.size());
+    size_t o_binv = ar.add<int64_t>(pk.blk_inv.size());
+    size_t o_inv = ar.add<double>(pk.inv.size());
+    size_t o_cal = ar.add<double>(pk.cal_nat.size());
+    size_t o_rn = ar.add<int32_t>(pk.rcv_node.size());
+    size_t o_rlv = ar.add<int32_t>(pk.rcvlvl_ptr.size());
+    size_t o_rp = ar.add<int32_t>(pk.rcv_pos.size());
+    size_t o_ri = ar.add<int32_t>(pk.rcv_idx.size());
+    size_t total = ar.add<char>(0) + 256;
+    DeviceState* ds = new DeviceState();
+    hipError_t e = hipMalloc(&ds->blob, total);
+    if (e != hipSuccess) {
+        delete ds;
+        set_error("hipMalloc(%zu) for a state failed: %s", total, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    char* b = (char*)ds->blob;
+    int rc = FM_OK;
+    rc = rc ? rc : put(b, o_fmeta, pk.fmeta);
+    rc = rc ? rc : put(b, o_fwts, pk.fwts);
+    rc = rc ? rc : put(b, o_flp, pk.flvl_ptr);
+    rc = rc ? rc : put(b, o_fln, pk.flvl_nsc);
+    rc = rc ? rc : put(b, o_fbp, pk.fblk_ptr);
+    rc = rc ? rc : put(b, o_fbi, pk.fblk_id);
+    rc = rc ? rc : put(b, o_rmeta, pk.rmeta);
+    rc = rc ? rc : put(b, o_rwts, pk.rwts);
+    rc = rc ? rc : put(b, o_rlp, pk.rlvl_ptr);
+    rc = rc ? rc : put(b, o_rln, pk.rlvl_nsc);
+    rc = rc ? rc : put(b, o_rbp, pk.rblk_ptr);
+    rc = rc ? rc : put(b, o_rbi, pk.rblk_id);
+    rc = rc ? rc : put(b, o_bk, pk.blk_k);
+    rc = rc ? rc : put(b, o_bfp, pk.blk_fpos);
+    rc = rc ? rc : put(b, o_brp, pk.blk_rpos);
+    rc = rc ? rc : put(b, o_binv, pk.blk_inv);
+    rc = rc ? rc : put(b, o_inv, pk.inv);
+    rc = rc ? rc : put(b, o_cal, pk.cal_nat);
+    rc = rc ? rc : put(b, o_rn, pk.rcv_node);
+    rc = rc ? rc : put(b, o_rlv, pk.rcvlvl_ptr);
+    rc = rc ? rc : put(b, o_rp, pk.rcv_pos);
+    rc = rc ? rc : put(b, o_ri, pk.rcv_idx);
+    if (rc != FM_OK) {
+        (void)hipFree(ds->blob);
+        delete ds;
+        return rc;
+    }
+    SrcDev& d = ds->d;
+    d.fmeta = (const uint64_t*)(b + o_fmeta);
+    d.fwts = b + o_fwts;
+    d.flvl_ptr = (const int32_t*)(b + o_flp);
+    d.flvl_nsc = (const int32_t*)(b + o_fln);
+    d.fblk_ptr = (const int32_t*)(b + o_fbp);
+    d.fblk_id = (const int32_t*)(b + o_fbi);
+    d.rmeta = (const uint64_t*)(b + o_rmeta);
+    d.rwts = b + o_rwts;
+    d.rlvl_ptr = (const int32_t*)(b + o_rlp);
+    d.rlvl_nsc = (const int32_t*)(b + o_rln);
+    d.rblk_ptr = (const int32_t*)(b + o_rbp);
+    d.rblk_id = (const int32_t*)(b + o_rbi);
+    d.blk_k = (const int32_t*)(b + o_bk);
+    d.blk_fpos = (const int32_t*)(b + o_bfp);
+    d.blk_rpos = (const int32_t*)(b + o_brp);
+    d.blk_inv = (const int64_t*)(b + o_binv);
+    d.inv = (const double*)(b + o_inv);
+    d.cal_nat = b + o_cal;
+    d.rcv_node = (const int32_t*)(b + o_rn);
+    d.rcvlvl_ptr = (const int32_t*)(b + o_rlv);
+    d.rcv_pos = (const int32_t*)(b + o_rp);
+    d.rcv_idx = (const int32_t*)(b + o_ri);
+    d.L_f = pk.L_f;
+    d.L_r = pk.L_r;
+    d.n_rcv = (int32_t)pk.rcv_node.size();
+    ds->device = dev;
+    st->dev = ds;
+    return FM_OK;
+}
+
+static int upload_fp32(HostState* st) {
+    DeviceState* ds = st->dev;
+    if (ds->blob32) return FM_OK;
+    const Packed& pk = st->pk;
+    std::vector<float> f(pk.fwts.begin(), pk.fwts.end());
+    std::vector<float> r(pk.rwts.begin(), pk.rwts.end());
+    std::vector<float> c(pk.cal_nat.begin(), pk.cal_nat.end());
+    Arena ar;
+    size_t of = ar.add<float>(f.size()), orr = ar.add<float>(r.size()), oc = ar.add<float>(c.size());
+    size_t total = ar.add<char>(0) + 256;
+    hipError_t e = hipMalloc(&ds->blob32, total);
+    if (e != hipSuccess) {
+        ds->blob32 = nullptr;
+        set_error("hipMalloc(%zu) for FP32 records failed: %s", total, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    char* b = (char*)ds->blob32;
+    int rc = put(b, of, f);
+    rc = rc ? rc : put(b, orr, r);
+    rc = rc ? rc : put(b, oc, c);
+    if (rc) return rc;
+    ds->fwts32 = b + of;
+    ds->rwts32 = b + orr;
+    ds->cal32 = b + oc;
+    return FM_OK;
+}
+
+void free_device_state(HostState* st) {
+    if (!st->dev) return;
+    if (st->dev->blob) (void)hipFree(st->dev->blob);
+    if (st->dev->blob32) (void)hipFree(st->dev->blob32);
+    delete st->dev;
+    st->dev = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+struct ApplyArgs {
+    const SrcDev* src;
+    int32_t S, B, ngroups, items, per_xcd, xcd_aware;
+    int64_t N;
+    int64_t st1, st2;       // node strides of logical axes 1 and 2
+    int32_t R;              // receivers per source (receiver layouts)
+    int32_t in_mode, out_mode;
+    const void* in;         // J: ds ; J^T: w
+    void* out;              // J: nodes output (or unused) ; J^T: per-source output
+    void* work;             // J: X (out or scratch) ; J^T: lambda scratch
+};
+
+__device__ __forceinline__ int64_t nbr_off(int slot, int64_t st1, int64_t st2) {
+    int64_t st = (slot >> 1) == 0 ? 1 : ((slot >> 1) == 1 ? st1 : st2);
+    return (slot & 1) ? st : -st;
+}
+
+__device__ __forceinline__ bool item_of(const ApplyArgs& a, int& alpha, int& grp) {
+    int w = blockIdx.x;
+    int item = a.xcd_aware ? (w % 8) * a.per_xcd + (w / 8) : w;
+    if (item >= a.items) return false;
+    alpha = item / a.ngroups;
+    grp = item - alpha * a.ngroups;
+    return true;
+}
+
+// Primal traversal: x_i = c_i ds_i + sum_{j in U(i)} w_ij x_j in topological
+// level order (eq. (discrete-row)), blocks x_C = A_C^{-1} b_C.
+template <typename V, int RG, int NT>
+__global__ __launch_bounds__(NT) void k_forward(ApplyArgs a) {
+    int alpha, grp;
+    if (!item_of(a, alpha, grp)) return;
+    extern __shared__ double lds[];
+    const SrcDev sd = a.src[alpha];
+    const V* __restrict__ wts = (const V*)sd.fwts;
+    const int r = threadIdx.x % RG;
+    const int slot0 = threadIdx.x / RG;
+    constexpr int SLOTS = NT / RG;
+    const int rhs = grp * RG + r;
+    const int64_t NB = a.N * a.B;
+    V* __restrict__ X = (V*)a.work + (size_t)alpha * NB;
+    const V* __restrict__ ds = (const V*)a.in + (a.in_mode == FM_DS_PER_PAIR ? (size_t)alpha * NB : 0);
+    const int B = a.B;
+    for (int l = 0; l < sd.L_f; ++l) {
+        const int p0 = sd.flvl_ptr[l];
+        const int nsc = sd.flvl_nsc[l];
+        for (int u = slot0; u < nsc; u += SLOTS) {
+            const uint64_t m = sd.fmeta[p0 + u];
+            const int64_t node = (int64_t)(m & kNodeMask);
+            const V* rec = wts + ((m >> kOffShift) & kOffMask);
+            unsigned mask = (unsigned)(m >> kMaskShift);
+            V acc = rec[0] * ds[node * B + rhs];
+            int t = 1;
+            while (mask) {
+                int slot = __builtin_ctz(mask);
+                mask &= mask - 1;
+                acc += rec[t++] * X[(node + nbr_off(slot, a.st1, a.st2)) * B + rhs];
+            }
+            X[node * B + rhs] = acc;
+        }
+        const int b0 = sd.fblk_ptr[l], b1 = sd.fblk_ptr[l + 1];
+        for (int bi = b0; bi < b1; ++bi) {
+            const int blk = sd.fblk_id[bi];
+            const int k = sd.blk_k[blk];
+            const int fp = sd.blk_fpos[blk];
+            const double* __restrict__ M = sd.inv + sd.blk_inv[blk];
+            for (int mi = slot0; mi < k; mi += SLOTS) {
+                const uint64_t m = sd.fmeta[fp + mi];
+                const int64_t node = (int64_t)(m & kNodeMask);
+                const V* rec = wts + ((m >> kOffShift) & kOffMask);
+                unsigned mask = (unsigned)(m >> kMaskShift);
+                double acc = (double)rec[0] * (double)ds[node * B + rhs];
+                int t = 1;
+                while (mask) {
+                    int slot = __builtin_ctz(mask);
+                    mask &= mask - 1;
+                    acc += (double)rec[t++] * (double)X[(node + nbr_off(slot, a.st1, a.st2)) * B + rhs];
+                }
+                lds[mi * RG + r] = acc;
+            }
+            __syncthreads();
+            for (int i = slot0; i < k; i += SLOTS) {
+                double acc = 0.0;
+                for (int j = 0; j < k; ++j) acc += M[(size_t)j * k + i] * lds[j * RG + r];
+                const int64_t node = (int64_t)(sd.fmeta[fp + i] & kNodeMask);
+                X[node * B + rhs] = (V)acc;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+}
+
+// Transpose traversal: lambda_j = r_j + sum_{i in succ(j)} w_ij lambda_i in
+// reverse level order; blocks lambda_C = A_C^{-T} b_C.
+template <typename V, int RG, int NT>
+__global__ __launch_bounds__(NT) void k_reverse(ApplyArgs a) {
+    int alpha, grp;
+    if (!item_of(a, alpha, grp)) return;
+    extern __shared__ double lds[];
+    const SrcDev sd = a.src[alpha];
+    const V* __restrict__ wts = (const V*)sd.rwts;
+    const int r = threadIdx.x % RG;
+    const int slot0 = threadIdx.x / RG;
+    constexpr int SLOTS = NT / RG;
+    const int rhs = grp * RG + r;
+    const int64_t NB = a.N * a.B;
+    const int B = a.B;
+    V* __restrict__ Lam = (V*)a.work + (size_t)alpha * NB;
+    const bool rcv_in = a.in_mode == FM_W_RECEIVERS;
+    const V* __restrict__ win = (const V*)a.in + (rcv_in ? (size_t)alpha * a.R * B : (size_t)alpha * NB);
+    V* __restrict__ outp = a.out_mode == FM_JT_PER_SOURCE ? (V*)a.out + (size_t)alpha * NB : nullptr;
+    for (int l = 0; l < sd.L_r; ++l) {
+        const int p0 = sd.rlvl_ptr[l];
+        const int nsc = sd.rlvl_nsc[l];
+        const int e0 = sd.rcvlvl_ptr[l], e1 = sd.rcvlvl_ptr[l + 1];
+        for (int u = slot0; u < nsc; u += SLOTS) {
+            const int pos = p0 + u;
+            const uint64_t m = sd.rmeta[pos];
+            const int64_t node = (int64_t)(m & kNodeMask);
+            const V* rec = wts + ((m >> kOffShift) & kOffMask);
+            unsigned mask = (unsigned)(m >> kMaskShift);
+            V acc;
+            if (!rcv_in) {
+                acc = win[node * B + rhs];
+            } else {
+                acc = (V)0;
+                if (m & kRcvFlag)
+                    for (int e = e0; e < e1; ++e)
+                        if (sd.rcv_pos[e] == pos) acc += win[(int64_t)sd.rcv_idx[e] * B + rhs];
+            }
+            int t = 1;
+            while (mask) {
+                int slot = __builtin_ctz(mask);
+                mask &= mask - 1;
+                acc += rec[t++] * Lam[(node + nbr_off(slot, a.st1, a.st2)) * B + rhs];
+            }
+            Lam[node * B + rhs] = acc;
+            if (outp) outp[node * B + rhs] = rec[0] * acc;
+        }
+        const int b0 = sd.rblk_ptr[l], b1 = sd.rblk_ptr[l + 1];
+        for (int bi = b0; bi < b1; ++bi) {
+            const int blk = sd.rblk_id[bi];
+            const int k = sd.blk_k[blk];
+            const int rp = sd.blk_rpos[blk];
+            const double* __restrict__ M = sd.inv + sd.blk_inv[blk];
+            for (int mi = slot0; mi < k; mi += SLOTS) {
+                const int pos = rp + mi;
+                const uint64_t m = sd.rmeta[pos];
+                const int64_t node = (int64_t)(m & kNodeMask);
+                const V* rec = wts + ((m >> kOffShift) & kOffMask);
+                unsigned mask = (unsigned)(m >> kMaskShift);
+                double acc;
+                if (!rcv_in) {
+                    acc = (double)win[node * B + rhs];
+                } else {
+                    acc = 0.0;
+                    if (m & kRcvFlag)
+                        for (int e = e0; e < e1; ++e)
+                            if (sd.rcv_pos[e] == pos) acc += (double)win[(int64_t)sd.rcv_idx[e] * B + rhs];
+                }
+                int t = 1;
+                while (mask) {
+                    int slot = __builtin_ctz(mask);
+                    mask &= mask - 1;
+                    acc += (double)rec[t++] * (double)Lam[(node + nbr_off(slot, a.st1, a.st2)) * B + rhs];
+                }
+                lds[mi * RG + r] = acc;
+            }
+            __syncthreads();
+            // lambda_j = sum_i M[i][j] b_i, summed in ascending i whatever the
+            // schedule, so every schedule produces the same bits
+            for (int j = slot0; j < k; j += SLOTS) {
+                double acc = 0.0;
+                const double* __restrict__ Mj = M + (size_t)j * k;
+                for (int i = 0; i < k; ++i) acc += Mj[i] * lds[i * RG + r];
+                const uint64_t m = sd.rmeta[rp + j];
+                const int64_t node = (int64_t)(m & kNodeMask);
+                const V* rec = wts + ((m >> kOffShift) & kOffMask);
+                Lam[node * B + rhs] = (V)acc;
+                if (outp) outp[node * B + rhs] = rec[0] * (V)acc;
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+}
+
+// out[alpha][r][b] = X[alpha][rcv_alpha(r)][b]  (P_alpha, Section 4.4)
+template <typename V>
+__global__ void k_gather_receivers(ApplyArgs a) {
+    const int64_t total = (int64_t)a.S * a.R * a.B;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t % a.B;
+        const int64_t rr = (t / a.B) % a.R;
+        const int64_t alpha = t / ((int64_t)a.B * a.R);
+        const int32_t node = a.src[alpha].rcv_node[rr];
+        ((V*)a.out)[t] = ((const V*)a.work)[(alpha * a.N + node) * a.B + b];
+    }
+}
+
+// g[n][b] = sum_alpha c_alpha[n] lambda_alpha[n][b], sources in order (Section 4.4)
+template <typename V>
+__global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
+    const int64_t NB = a.N * a.B;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NB;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t node = t / a.B;
+        V acc = (V)0;
+        for (int alpha = 0; alpha < a.S; ++alpha)
+            acc += ((const V*)cal[alpha])[node] * ((const V*)a.work)[alpha * NB + t];
+        ((V*)a.out)[t] = acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// batch and launches
+// ---------------------------------------------------------------------------
+
+template <typename V, int RG, int NT>
+static hipError_t launch_dir(bool fwd, const ApplyArgs& a, int grid, size_t lds, hipStream_t s) {
+    const void* fn = fwd ? (const void*)k_forward<V, RG, NT> : (const void*)k_reverse<V, RG, NT>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (fwd) hipLaunchKernelGGL((k_forward<V, RG, NT>), dim3(grid), dim3(NT), lds, s, a);
+    else hipLaunchKernelGGL((k_reverse<V, RG, NT>), dim3(grid), dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename V, int NT>
+static hipError_t launch_rg(bool fwd, int rg, const ApplyArgs& a, int grid, size_t lds, hipStream_t s) {
+    switch (rg) {
+        case 1: return launch_dir<V, 1, NT>(fwd, a, grid, lds, s);
+        case 2: return launch_dir<V, 2, NT>(fwd, a, grid, lds, s);
+        case 4: return launch_dir<V, 4, NT>(fwd, a, grid, lds, s);
+        case 8: return launch_dir<V, 8, NT>(fwd, a, grid, lds, s);
+        case 16: return launch_dir<V, 16, NT>(fwd, a, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename V>
+static hipError_t launch_sweep(bool fwd, const fm_tuning& t, const ApplyArgs& a, int grid, size_t lds,
+                               hipStream_t s) {
+    switch (t.threads) {
+        case 256: return launch_rg<V, 256>(fwd, t.rhs_per_group, a, grid, lds, s);
+        case 512: return launch_rg<V, 512>(fwd, t.rhs_per_group, a, grid, lds, s);
+        case 1024: return launch_rg<V, 1024>(fwd, t.rhs_per_group, a, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static constexpr size_t kLdsMax = 160 * 1024;
+
+int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precision, const fm_tuning* tuning,
+                 void* stream, fm_batch** out) {
+    if (!out) { set_error("null output pointer"); return FM_EINVAL; }
+    *out = nullptr;
+    if (!states || S < 1) { set_error("need at least one state"); return FM_EINVAL; }
+    if (B < 1) { set_error("B must be >= 1"); return FM_EINVAL; }
+    if (precision != FM_FP64 && precision != FM_FP32) { set_error("precision must be 64 or 32"); return FM_EINVAL; }
+    HostState* s0 = static_cast<HostState*>(states[0]);
+    if (!s0) { set_error("null state"); return FM_EINVAL; }
+    int32_t R = (int32_t)s0->pk.rcv_node.size();
+    int32_t maxk = 0;
+    for (int32_t i = 0; i < S; i++) {
+        HostState* si = static_cast<HostState*>(states[i]);
+        if (!si) { set_error("null state %d", i); return FM_EINVAL; }
+        if (!si->same_grid(*s0)) { set_error("state %d has another grid shape", i); return FM_EINVAL; }
+        if ((int32_t)si->pk.rcv_node.size() != R) { set_error("state %d has another receiver count", i); return FM_EINVAL; }
+        maxk = std::max(maxk, si->pk.max_blk_k);
+    }
+    fm_tuning t{};
+    if (tuning) t = *tuning;
+    if (t.threads == 0) t.threads = 1024;
+    if (t.rhs_per_group == 0) {
+        t.rhs_per_group = 1;
+        while (t.rhs_per_group < 16 && B % (t.rhs_per_group * 2) == 0 && t.rhs_per_group * 2 <= 4)
+            t.rhs_per_group *= 2;
+    }
+    t.xcd_aware = t.xcd_aware < 0 ? 0 : 1;
+    if (t.min_lds_bytes == 0) t.min_lds_bytes = 96 * 1024;
+    int rg = t.rhs_per_group;
+    if (rg != 1 && rg != 2 && rg != 4 && rg != 8 && rg != 16) { set_error("rhs_per_group must be 1,2,4,8 or 16"); return FM_EINVAL; }
+    if (B % rg != 0) { set_error("B=%d is not a multiple of rhs_per_group=%d", B, rg); return FM_EINVAL; }
+    if (t.threads != 256 && t.threads != 512 && t.threads != 1024) { set_error("threads must be 256, 512 or 1024"); return FM_EINVAL; }
+    size_t need = (size_t)maxk * rg * sizeof(double);
+    if (need > kLdsMax) {
+        set_error("largest SCC block (%d nodes) needs %zu B of LDS with %d rhs per group; use fewer", maxk, need, rg);
+        return FM_EINVAL;
+    }
+    size_t lds = std::max(need, (size_t)std::min<int64_t>(t.min_lds_bytes, (int64_t)kLdsMax));
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    for (int32_t i = 0; i < S; i++) {
+        int rc = upload_state(static_cast<HostState*>(states[i]));
+        if (rc) return rc;
+        if (precision == FM_FP32) {
+            rc = upload_fp32(static_cast<HostState*>(states[i]));
+            if (rc) return rc;
+        }
+    }
+    fm_batch* b = new fm_batch();
+    for (int32_t i = 0; i < S; i++) b->states.push_back(static_cast<HostState*>(states[i]));
+    b->S = S;
+    b->B = B;
+    b->prec = precision;
+    b->R = R;
+    b->tun = t;
+    b->stream = (hipStream_t)stream;
+    b->N = s0->N;
+    b->st1 = s0->stride[1];
+    b->st2 = s0->stride[2];
+    b->device = dev;
+    b->lds_bytes = lds;
+    b->items = S * (B / rg);
+    b->per_xcd = (b->items + 7) / 8;
+    b->grid = t.xcd_aware ? 8 * b->per_xcd : b->items;
+    std::vector<SrcDev> h(S);
+    for (int32_t i = 0; i < S; i++) {
+        HostState* si = static_cast<HostState*>(states[i]);
+        h[i] = si->dev->d;
+        if (precision == FM_FP32) {
+            h[i].fwts = si->dev->fwts32;
+            h[i].rwts = si->dev->rwts32;
+            h[i].cal_nat = si->dev->cal32;
+        }
+    }
+    size_t vbytes = precision == FM_FP64 ? 8 : 4;
+    size_t scratch = (size_t)S * (size_t)b->N * (size_t)B * vbytes;
+    hipError_t e = hipMalloc(&b->d_src, sizeof(SrcDev) * S + sizeof(void*) * S);
+    if (e == hipSuccess) e = hipMalloc(&b->scratch, scratch);
+    if (e != hipSuccess) {
+        if (b->d_src) (void)hipFree(b->d_src);
+        delete b;
+        set_error("batch allocation (%zu B scratch) failed: %s", scratch, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    std::vector<const void*> cal(S);
+    for (int32_t i = 0; i < S; i++) cal[i] = h[i].cal_nat;
+    e = hipMemcpy(b->d_src, h.data(), sizeof(SrcDev) * S, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy((char*)b->d_src + sizeof(SrcDev) * S, cal.data(), sizeof(void*) * S, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(b->d_src);
+        (void)hipFree(b->scratch);
+        delete b;
+        set_error("batch upload failed: %s", hipGetErrorString(e));
+        return FM_EHIP;
+    }
+    *out = b;
+    return FM_OK;
+}
+
+void batch_free(fm_batch* b) {
+    if (!b) return;
+    if (b->d_src) (void)hipFree(b->d_src);
+    if (b->scratch) (void)hipFree(b->scratch);
+    delete b;
+}
+
+static ApplyArgs base_args(const fm_batch* b) {
+    ApplyArgs a{};
+    a.src = b->d_src;
+    a.S = b->S;
+    a.B = b->B;
+    a.ngroups = b->B / b->tun.rhs_per_group;
+    a.items = b->items;
+    a.per_xcd = b->per_xcd;
+    a.xcd_aware = b->tun.xcd_aware;
+    a.N = b->N;
+    a.st1 = b->st1;
+    a.st2 = b->st2;
+    a.R = b->R;
+    return a;
+}
+
+static int check_device(const fm_batch* b) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != b->device) {
+        set_error("batch lives on device %d but device %d is current", b->device, dev);
+        return FM_ESTATE;
+    }
+    return FM_OK;
+}
+
+int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode) {
+    if (!b || !ds || !out) { set_error("null argument"); return FM_EINVAL; }
+    if (ds_mode != FM_DS_PER_PAIR && ds_mode != FM_DS_BROADCAST) { set_error("bad ds_mode %d", ds_mode); return FM_EINVAL; }
+    if (out_mode != FM_OUT_NODES && out_mode != FM_OUT_RECEIVERS) { set_error("bad out_mode %d", out_mode); return FM_EINVAL; }
+    if (out_mode == FM_OUT_RECEIVERS && b->R == 0) { set_error("the states have no receivers"); return FM_EINVAL; }
+    int rc = check_device(b);
+    if (rc) return rc;
+    ApplyArgs a = base_args(b);
+    a.in = ds;
+    a.in_mode = ds_mode;
+    a.out_mode = out_mode;
+    a.out = out;
+    a.work = out_mode == FM_OUT_NODES ? out : b->scratch;
+    hipError_t e = b->prec == FM_FP64 ? launch_sweep<double>(true, b->tun, a, b->grid, b->lds_bytes, b->stream)
+                                      : launch_sweep<float>(true, b->tun, a, b->grid, b->lds_bytes, b->stream);
+    if (e != hipSuccess) { set_error("forward launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    if (out_mode == FM_OUT_RECEIVERS) {
+        int64_t total = (int64_t)b->S * b->R * b->B;
+        int grid = (int)std::min<int64_t>((total + 255) / 256, 65535);
+        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_gather_receivers<double>, dim3(grid), dim3(256), 0, b->stream, a);
+        else hipLaunchKernelGGL(k_gather_receivers<float>, dim3(grid), dim3(256), 0, b->stream, a);
+        e = hipGetLastError();
+        if (e != hipSuccess) { set_error("gather launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    }
+    return FM_OK;
+}
+
+int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode) {
+    if (!b || !w || !out) { set_error("null argument"); return FM_EINVAL; }
+    if (w_mode != FM_W_NODES && w_mode != FM_W_RECEIVERS) { set_error("bad w_mode %d", w_mode); return FM_EINVAL; }
+    if (out_mode != FM_JT_PER_SOURCE && out_mode != FM_JT_SUMMED) { set_error("bad out_mode %d", out_mode); return FM_EINVAL; }
+    if (w_mode == FM_W_RECEIVERS && b->R == 0) { set_error("the states have no receivers"); return FM_EINVAL; }
+    int rc = check_device(b);
+    if (rc) return rc;
+    ApplyArgs a = base_args(b);
+    a.in = w;
+    a.in_mode = w_mode;
+    a.out_mode = out_mode;
+    a.out = out;
+    a.work = b->scratch;
+    hipError_t e = b->prec == FM_FP64 ? launch_sweep<double>(false, b->tun, a, b->grid, b->lds_bytes, b->stream)
+                                      : launch_sweep<float>(false, b->tun, a, b->grid, b->lds_bytes, b->stream);
+    if (e != hipSuccess) { set_error("reverse launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    if (out_mode == FM_JT_SUMMED) {
+        int64_t total = b->N * b->B;
+        int grid = (int)std::min<int64_t>((total + 255) / 256, 16384);
+        const void* const* cal = (const void* const*)((char*)b->d_src + sizeof(SrcDev) * b->S);
+        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_sum_sources<double>, dim3(grid), dim3(256), 0, b->stream, a, cal);
+        else hipLaunchKernelGGL(k_sum_sources<float>, dim3(grid), dim3(256), 0, b->stream, a, cal);
+        e = hipGetLastError();
+        if (e != hipSuccess) { set_error("source-sum launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    }
+    return FM_OK;
+}
+
+int batch_set_stream(fm_batch* b, void* stream) {
+    if (!b) { set_error("null batch"); return FM_EINVAL; }
+    b->stream = (hipStream_t)stream;
+    return FM_OK;
+}
+
+int batch_tuning(const fm_batch* b, fm_tuning* out) {
+    if (!b || !out) { set_error("null argument"); return FM_EINVAL; }
+    *out = b->tun;
+    return FM_OK;
+}
+
+}  // namespace fm

@@ -1,0 +1,110 @@
+// Internal declarations of the fmbtf library (not part of the C ABI).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fmbtf.h"
+
+namespace fm {
+
+// Thread-local error message behind fm_last_error().
+void set_error(const char* fmt, ...);
+void clear_error();
+
+// ---------------------------------------------------------------------------
+// Packed record format shared by the host packer and the kernels.
+//
+// Every node owns one record per traversal direction, stored in that
+// direction's level order:
+//   meta word (uint64): bits 0..30  node id
+//                       bit  31     node is a receiver (reverse records only)
+//                       bits 32..57 offset of the value record (in elements)
+//                       bits 58..63 neighbour mask
+//   value record:       [c_node, w_1, ..., w_m], one weight per set mask bit
+//                       in increasing bit order
+// Neighbour slot b: axis = b >> 1; side = b & 1; side 0 is node - stride[axis],
+// side 1 is node + stride[axis].  In forward records the mask lists the
+// predecessors j of the node with weight w_{node,j}; in reverse records it
+// lists the successors i with weight w_{i,node}.  For members of a nontrivial
+// SCC only the neighbours outside the component are listed; couplings inside
+// the component live in the block's dense factors.
+// ---------------------------------------------------------------------------
+constexpr int kNodeBits = 31;
+constexpr uint64_t kNodeMask = (1ull << kNodeBits) - 1;
+constexpr uint64_t kRcvFlag = 1ull << 31;
+constexpr int kOffShift = 32;
+constexpr int kOffBits = 26;
+constexpr uint64_t kOffMask = (1ull << kOffBits) - 1;
+constexpr int kMaskShift = 58;
+
+struct Packed {
+    int32_t L_f = 0, L_r = 0, nblk = 0;
+    // forward traversal
+    std::vector<uint64_t> fmeta;       // [N]
+    std::vector<double> fwts;          // records
+    std::vector<int32_t> flvl_ptr;     // [L_f + 1] position range per level
+    std::vector<int32_t> flvl_nsc;     // [L_f] scalar nodes at the start of each level
+    std::vector<int32_t> fblk_ptr;     // [L_f + 1] range into fblk_id
+    std::vector<int32_t> fblk_id;      // [nblk] blocks in forward level order
+    // reverse traversal
+    std::vector<uint64_t> rmeta;
+    std::vector<double> rwts;
+    std::vector<int32_t> rlvl_ptr, rlvl_nsc, rblk_ptr, rblk_id;
+    // nontrivial SCC blocks: member m sits at fpos+m / rpos+m
+    std::vector<int32_t> blk_k, blk_fpos, blk_rpos;
+    std::vector<int64_t> blk_inv;      // offset of the k x k inverse (column-major)
+    std::vector<double> inv;
+    std::vector<double> cal_nat;       // [N] calibration in natural order
+    // receivers
+    std::vector<int32_t> rcv_node;     // [R]
+    std::vector<int32_t> rcvlvl_ptr;   // [L_r + 1] range of receiver entries per reverse level
+    std::vector<int32_t> rcv_pos;      // reverse position of each entry (sorted)
+    std::vector<int32_t> rcv_idx;      // receiver index of each entry
+    int32_t max_blk_k = 0;
+    int64_t max_level_nodes = 0;
+};
+
+struct DeviceState;   // defined in the HIP translation unit
+
+struct HostState {
+    int dim = 3;
+    int64_t n[3] = {1, 1, 1};       // nodes per logical axis (axis 0 fastest)
+    int64_t stride[3] = {1, 1, 1};
+    int64_t N = 0;
+    int64_t src = 0;
+    // natural-order operator
+    std::vector<uint8_t> pmask, smask;
+    std::vector<double> w6;         // [N][6] weight per neighbour slot (0 if none)
+    std::vector<double> cal;        // [N]
+    // graph
+    std::vector<int32_t> comp;      // component id, numbered in topological order
+    int32_t ncomp = 0;
+    std::vector<int32_t> cptr, cnodes;      // members per component (ascending node id)
+    std::vector<int32_t> clev_f, clev_r;    // per component
+    Packed pk;
+    fm_stats stats{};
+    DeviceState* dev = nullptr;
+    // the grid shape, to check that the states of one batch agree
+    bool same_grid(const HostState& o) const {
+        return dim == o.dim && n[0] == o.n[0] && n[1] == o.n[1] && n[2] == o.n[2];
+    }
+};
+
+}  // namespace fm
+
+// The opaque handle of the C ABI is the host state itself.
+struct fm_state : fm::HostState {};
+
+namespace fm {
+
+// Host setup (setup.cpp).  Returns FM_OK or an FM_E* code with the message set.
+int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
+                const int64_t* rcv, int32_t n_rcv, fm_state** out);
+
+// Device side (device.hip).
+int upload_state(HostState* st);
+void free_device_state(HostState* st);
+
+}  // namespace fm

@@ -1,0 +1,588 @@
+// Host setup of one frozen source state (Algorithm 1, Phase I, lines 7-10).
+//
+//  1. face-upwind coefficients, row normalisation      Section 3.1, eq. (discrete-row)
+//  2. calibration c = (A T) / s                          Section 3.2
+//  3. dependency graph j -> i iff w_ij > 0                Section 3.3
+//  4. SCCs (iterative Tarjan, linear time) and the        Section 4.1, eq. (block-form)
+//     condensation DAG in topological order
+//  5. longest-path levels of the condensation DAG, in both directions
+//  6. dense LU with partial pivoting of every nontrivial  Section 4.3 (P_C A_C = L_C U_C),
+//     SCC block, checked for a vanishing pivot             Section 4.2 (factorisation success)
+//  7. packing into the per-direction level-ordered records read by the kernels
+//
+// Floating-point sums run in a fixed order (axis order for the face
+// coefficient, neighbour-slot order for d_p and (W T)_p) and this file is built
+// with -ffp-contract=off, so every upwind sign decision is a reproducible FP64
+// decision.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+
+#include "internal.h"
+
+namespace fm {
+
+namespace {
+
+struct Grid {
+    int dim;
+    int64_t n[3];
+    int64_t stride[3];
+    int64_t N;
+    const double* G;
+    int ncomp_g;   // metric components per node: 3 (2-D) or 6 (3-D)
+};
+
+// Full symmetric metric entry (a, b) of node p.
+inline double metric(const Grid& g, int64_t p, int a, int b) {
+    const double* m = g.G + (size_t)g.ncomp_g * (size_t)p;
+    if (g.dim == 2) {
+        if (a == b) return m[a];      // Gxx, Gzz
+        return m[2];                  // Gxz
+    }
+    if (a == b) return m[a];          // Gxx, Gyy, Gzz
+    int lo = a < b ? a : b, hi = a < b ? b : a;
+    if (lo == 0 && hi == 1) return m[3];
+    if (lo == 0 && hi == 2) return m[4];
+    return m[5];
+}
+
+inline int64_t coord(const Grid& g, int64_t p, int axis) {
+    return (p / g.stride[axis]) % g.n[axis];
+}
+
+// Nodal derivative of T along axis at node p: central inside, one-sided on the
+// first and last node of the axis, zero for a single-node axis.
+inline double nodal_derivative(const Grid& g, const double* T, int64_t p, int axis) {
+    int64_t c = coord(g, p, axis), n = g.n[axis], st = g.stride[axis];
+    if (n == 1) return 0.0;
+    if (c == 0) return T[p + st] - T[p];
+    if (c == n - 1) return T[p] - T[p - st];
+    return 0.5 * (T[p + st] - T[p - st]);
+}
+
+// a_f for the face between lo and lo + e_d (Section 3.1): G_f is the mean of
+// the two nodal metrics, the normal derivative the compact difference, each
+// tangential derivative the mean of the two nodal derivatives; the sum runs
+// over d' in axis order.
+inline double face_coefficient(const Grid& g, const double* T, int64_t lo, int d) {
+    int64_t hi = lo + g.stride[d];
+    double a = 0.0;
+    for (int dp = 0; dp < g.dim; dp++) {
+        double gd;
+        if (dp == d) gd = T[hi] - T[lo];
+        else gd = 0.5 * (nodal_derivative(g, T, lo, dp) + nodal_derivative(g, T, hi, dp));
+        double Gf = 0.5 * (metric(g, lo, d, dp) + metric(g, hi, d, dp));
+        double term = Gf * gd;
+        a = (dp == 0) ? term : a + term;
+    }
+    return a;
+}
+
+inline int64_t nbr(const Grid& g, int64_t p, int slot) {
+    int axis = slot >> 1;
+    return (slot & 1) ? p + g.stride[axis] : p - g.stride[axis];
+}
+
+inline bool has_nbr(const Grid& g, int64_t p, int slot) {
+    int axis = slot >> 1;
+    if (axis >= g.dim) return false;
+    int64_t c = coord(g, p, axis);
+    return (slot & 1) ? (c + 1 < g.n[axis]) : (c > 0);
+}
+
+// Dense LU with partial pivoting (largest magnitude, ties to the lowest row),
+// in place on a row-major k x k matrix.  Returns the index of the first pivot
+// below tol, or -1.
+int lu_factor(int k, double* a, int32_t* piv, double tol) {
+    for (int c = 0; c < k; c++) {
+        int p = c;
+        double best = std::fabs(a[(size_t)c * k + c]);
+        for (int r = c + 1; r < k; r++) {
+            double v = std::fabs(a[(size_t)r * k + c]);
+            if (v > best) { best = v; p = r; }
+        }
+        piv[c] = p;
+        if (!(best >= tol)) return c;
+        if (p != c) {
+            double* rc = a + (size_t)c * k;
+            double* rp = a + (size_t)p * k;
+            for (int j = 0; j < k; j++) std::swap(rc[j], rp[j]);
+        }
+        const double* rc = a + (size_t)c * k;
+        double inv = 1.0 / rc[c];
+        for (int r = c + 1; r < k; r++) {
+            double* rr = a + (size_t)r * k;
+            double l = rr[c] * inv;
+            rr[c] = l;
+            if (l != 0.0)
+                for (int j = c + 1; j < k; j++) rr[j] -= l * rc[j];
+        }
+    }
+    return -1;
+}
+
+// X = A^{-1} = U^{-1} L^{-1} P from the factors, row-major into x.
+void lu_inverse(int k, const double* lu, const int32_t* piv, double* x) {
+    std::vector<int32_t> perm(k);
+    for (int i = 0; i < k; i++) perm[i] = i;
+    for (int c = 0; c < k; c++) std::swap(perm[c], perm[piv[c]]);
+    // P I: row i of P is e_{perm[i]}
+    std::fill(x, x + (size_t)k * k, 0.0);
+    for (int i = 0; i < k; i++) x[(size_t)i * k + perm[i]] = 1.0;
+    // L^{-1} (unit lower), row operations
+    for (int i = 0; i < k; i++) {
+        double* xi = x + (size_t)i * k;
+        const double* li = lu + (size_t)i * k;
+        for (int p = 0; p < i; p++) {
+            double l = li[p];
+            if (l == 0.0) continue;
+            const double* xp = x + (size_t)p * k;
+            for (int j = 0; j < k; j++) xi[j] -= l * xp[j];
+        }
+    }
+    // U^{-1}
+    for (int i = k - 1; i >= 0; i--) {
+        double* xi = x + (size_t)i * k;
+        const double* ui = lu + (size_t)i * k;
+        for (int p = i + 1; p < k; p++) {
+            double u = ui[p];
+            if (u == 0.0) continue;
+            const double* xp = x + (size_t)p * k;
+            for (int j = 0; j < k; j++) xi[j] -= u * xp[j];
+        }
+        double d = 1.0 / ui[i];
+        for (int j = 0; j < k; j++) xi[j] *= d;
+    }
+}
+
+int validate(const fm_grid* g, const double* T, const double* s, int64_t src, const int64_t* rcv,
+             int32_t n_rcv, Grid& gr) {
+    if (!g || !g->G || !T || !s) { set_error("null argument"); return FM_EINVAL; }
+    if (g->dim != 2 && g->dim != 3) { set_error("dim must be 2 or 3, got %d", g->dim); return FM_EINVAL; }
+    if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) { set_error("grid sizes must be >= 1"); return FM_EINVAL; }
+    if (g->dim == 2 && g->n2 != 1) { set_error("2-D grids need n2 == 1"); return FM_EINVAL; }
+    gr.dim = g->dim;
+    gr.n[0] = g->n1;
+    if (g->dim == 3) { gr.n[1] = g->n2; gr.n[2] = g->n3; }
+    else { gr.n[1] = g->n3; gr.n[2] = 1; }
+    gr.stride[0] = 1;
+    gr.stride[1] = gr.n[0];
+    gr.stride[2] = gr.n[0] * gr.n[1];
+    gr.N = gr.n[0] * gr.n[1] * gr.n[2];
+    gr.G = g->G;
+    gr.ncomp_g = g->dim == 3 ? 6 : 3;
+    if (gr.N >= (int64_t)kNodeMask) { set_error("grid too large: %lld nodes", (long long)gr.N); return FM_EINVAL; }
+    if (src < 0 || src >= gr.N) { set_error("source node %lld out of range", (long long)src); return FM_EINVAL; }
+    if (n_rcv < 0 || (n_rcv > 0 && !rcv)) { set_error("bad receiver list"); return FM_EINVAL; }
+    for (int32_t r = 0; r < n_rcv; r++)
+        if (rcv[r] < 0 || rcv[r] >= gr.N) { set_error("receiver %d node %lld out of range", r, (long long)rcv[r]); return FM_EINVAL; }
+    for (int64_t p = 0; p < gr.N; p++) {
+        if (!std::isfinite(T[p])) { set_error("T[%lld] is not finite", (long long)p); return FM_EINVAL; }
+        if (!(s[p] > 0.0) || !std::isfinite(s[p])) { set_error("s[%lld] must be finite and > 0", (long long)p); return FM_EINVAL; }
+        const double* m = g->G + (size_t)gr.ncomp_g * p;
+        for (int c = 0; c < gr.ncomp_g; c++)
+            if (!std::isfinite(m[c])) { set_error("G[%lld] is not finite", (long long)p); return FM_EINVAL; }
+        for (int c = 0; c < gr.dim; c++)
+            if (!(m[c] > 0.0)) { set_error("G[%lld] has a nonpositive diagonal", (long long)p); return FM_EINVAL; }
+    }
+    if (T[src] != 0.0) { set_error("T at the source node must be 0, got %g", T[src]); return FM_EINVAL; }
+    return FM_OK;
+}
+
+}  // namespace
+
+int build_state(const fm_grid* g, const double* T, const double* s, int64_t src, const int64_t* rcv,
+                int32_t n_rcv, fm_state** out) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!out) { set_error("null output pointer"); return FM_EINVAL; }
+    *out = nullptr;
+    Grid gr;
+    int rc = validate(g, T, s, src, rcv, n_rcv, gr);
+    if (rc != FM_OK) return rc;
+    fm_state* st = new (std::nothrow) fm_state();
+    if (!st) { set_error("out of host memory"); return FM_ENOMEM; }
+    try {
+        const int64_t N = gr.N;
+        st->dim = gr.dim;
+        for (int a = 0; a < 3; a++) { st->n[a] = gr.n[a]; st->stride[a] = gr.stride[a]; }
+        st->N = N;
+        st->src = src;
+
+        // ---- 1-2: couplings, weights, calibration (Sections 3.1-3.2) ----
+        st->pmask.assign(N, 0);
+        st->w6.assign((size_t)N * 6, 0.0);
+        st->cal.assign(N, 0.0);
+        const int nslot = 2 * gr.dim;
+        int64_t E = 0;
+        for (int64_t p = 0; p < N; p++) {
+            double c6[6] = {0, 0, 0, 0, 0, 0};
+            for (int slot = 0; slot < nslot; slot++) {
+                if (!has_nbr(gr, p, slot)) continue;
+                int d = slot >> 1;
+                if (slot & 1) {
+                    double a = face_coefficient(gr, T, p, d);           // plus face of p
+                    c6[slot] = -a > 0.0 ? -a : 0.0;
+                } else {
+                    double a = face_coefficient(gr, T, p - gr.stride[d], d);   // minus face of p
+                    c6[slot] = a > 0.0 ? a : 0.0;
+                }
+            }
+            double dsum = 0.0;
+            for (int slot = 0; slot < nslot; slot++) dsum = dsum + c6[slot];
+            double acc = 0.0;
+            uint8_t mask = 0;
+            if (p != src && dsum > 0.0) {
+                for (int slot = 0; slot < nslot; slot++) {
+                    if (c6[slot] > 0.0) {
+                        double w = c6[slot] / dsum;
+                        if (w > 0.0) {
+                            st->w6[(size_t)p * 6 + slot] = w;
+                            mask |= (uint8_t)(1u << slot);
+                            acc = acc + w * T[nbr(gr, p, slot)];
+                            E++;
+                        }
+                    }
+                }
+            }
+            st->pmask[p] = mask;
+            double ell = T[p] - acc;
+            st->cal[p] = ell / s[p];
+        }
+        st->smask.assign(N, 0);
+        for (int64_t p = 0; p < N; p++) {
+            uint8_t m = st->pmask[p];
+            for (int slot = 0; slot < nslot; slot++)
+                if (m & (1u << slot)) st->smask[nbr(gr, p, slot)] |= (uint8_t)(1u << (slot ^ 1));
+        }
+
+        // ---- 3-4: SCCs by iterative Tarjan over predecessor edges ----
+        // Following predecessors, a component is completed after every
+        // component it depends on, so completion order is a topological order
+        // of the condensation DAG (Section 4.1).
+        std::vector<int32_t> idx(N, -1), low(N, 0);
+        std::vector<uint8_t> onstk(N, 0);
+        std::vector<int32_t> tstack;
+        tstack.reserve(1024);
+        std::vector<int32_t> cv;      // call stack: node
+        std::vector<int8_t> cs;       // call stack: next slot
+        cv.reserve(1024);
+        cs.reserve(1024);
+        st->comp.assign(N, -1);
+        int32_t counter = 0, ncomp = 0;
+        for (int64_t root = 0; root < N; root++) {
+            if (idx[root] >= 0) continue;
+            idx[root] = low[root] = counter++;
+            tstack.push_back((int32_t)root);
+            onstk[root] = 1;
+            cv.push_back((int32_t)root);
+            cs.push_back(0);
+            while (!cv.empty()) {
+                int32_t v = cv.back();
+                bool descended = false;
+                while (cs.back() < nslot) {
+                    int slot = cs.back()++;
+                    if (!(st->pmask[v] & (1u << slot))) continue;
+                    int32_t u = (int32_t)nbr(gr, v, slot);
+                    if (idx[u] < 0) {
+                        idx[u] = low[u] = counter++;
+                        tstack.push_back(u);
+                        onstk[u] = 1;
+                        cv.push_back(u);
+                        cs.push_back(0);
+                        descended = true;
+                        break;
+                    } else if (onstk[u]) {
+                        low[v] = std::min(low[v], idx[u]);
+                    }
+                }
+                if (descended) continue;
+                if (low[v] == idx[v]) {
+                    int32_t u;
+                    do {
+                        u = tstack.back();
+                        tstack.pop_back();
+                        onstk[u] = 0;
+                        st->comp[u] = ncomp;
+                    } while (u != v);
+                    ncomp++;
+                }
+                cv.pop_back();
+                cs.pop_back();
+                if (!cv.empty()) {
+                    int32_t p = cv.back();
+                    low[p] = std::min(low[p], low[v]);
+                }
+            }
+        }
+        st->ncomp = ncomp;
+        std::vector<int32_t>().swap(idx);
+        std::vector<int32_t>().swap(low);
+        std::vector<uint8_t>().swap(onstk);
+
+        // members per component, ascending node id
+        st->cptr.assign(ncomp + 1, 0);
+        for (int64_t p = 0; p < N; p++) st->cptr[st->comp[p] + 1]++;
+        for (int32_t c = 0; c < ncomp; c++) st->cptr[c + 1] += st->cptr[c];
+        st->cnodes.assign(N, 0);
+        {
+            std::vector<int32_t> fill(st->cptr.begin(), st->cptr.end() - 1);
+            for (int64_t p = 0; p < N; p++) st->cnodes[fill[st->comp[p]]++] = (int32_t)p;
+        }
+
+        // ---- 5: longest-path levels of the condensation DAG ----
+        st->clev_f.assign(ncomp, 0);
+        st->clev_r.assign(ncomp, 0);
+        std::vector<uint8_t> unres(ncomp, 0);   // on or downstream of a cycle (Proposition 2)
+        int64_t n_vio = 0;
+        for (int32_t c = 0; c < ncomp; c++) {
+            int32_t lev = 0;
+            bool nontrivial = st->cptr[c + 1] - st->cptr[c] > 1;
+            uint8_t un = nontrivial ? 1 : 0;
+            for (int32_t m = st->cptr[c]; m < st->cptr[c + 1]; m++) {
+                int32_t v = st->cnodes[m];
+                uint8_t pm = st->pmask[v];
+                for (int slot = 0; slot < nslot; slot++) {
+                    if (!(pm & (1u << slot))) continue;
+                    int32_t u = (int32_t)nbr(gr, v, slot);
+                    if (T[u] > T[v]) n_vio++;
+                    int32_t cu = st->comp[u];
+                    if (cu == c) continue;
+                    lev = std::max(lev, st->clev_f[cu] + 1);
+                    un |= unres[cu];
+                }
+            }
+            st->clev_f[c] = lev;
+            unres[c] = un;
+        }
+        for (int32_t c = ncomp - 1; c >= 0; c--) {
+            int32_t lev = 0;
+            for (int32_t m = st->cptr[c]; m < st->cptr[c + 1]; m++) {
+                int32_t v = st->cnodes[m];
+                uint8_t sm = st->smask[v];
+                for (int slot = 0; slot < nslot; slot++) {
+                    if (!(sm & (1u << slot))) continue;
+                    int32_t cu = st->comp[nbr(gr, v, slot)];
+                    if (cu == c) continue;
+                    lev = std::max(lev, st->clev_r[cu] + 1);
+                }
+            }
+            st->clev_r[c] = lev;
+        }
+        int32_t L_f = 0, L_r = 0;
+        for (int32_t c = 0; c < ncomp; c++) {
+            L_f = std::max(L_f, st->clev_f[c] + 1);
+            L_r = std::max(L_r, st->clev_r[c] + 1);
+        }
+
+        // ---- 6: factor every nontrivial block, keep A_C^{-1} ----
+        Packed& pk = st->pk;
+        std::vector<int32_t> blk_comp;
+        for (int32_t c = 0; c < ncomp; c++)
+            if (st->cptr[c + 1] - st->cptr[c] > 1) blk_comp.push_back(c);
+        const int32_t nblk = (int32_t)blk_comp.size();
+        std::vector<int32_t> comp_blk(ncomp, -1);
+        pk.nblk = nblk;
+        pk.blk_k.resize(nblk);
+        pk.blk_inv.resize(nblk);
+        int64_t inv_total = 0, n_cyc = 0;
+        int32_t largest = 0;
+        for (int32_t b = 0; b < nblk; b++) {
+            int32_t c = blk_comp[b];
+            comp_blk[c] = b;
+            int32_t k = st->cptr[c + 1] - st->cptr[c];
+            pk.blk_k[b] = k;
+            pk.blk_inv[b] = inv_total;
+            inv_total += (int64_t)k * k;
+            n_cyc += k;
+            largest = std::max(largest, k);
+        }
+        pk.max_blk_k = largest;
+        pk.inv.assign((size_t)inv_total, 0.0);
+        {
+            std::vector<double> a, x;
+            std::vector<int32_t> piv, local(0);
+            for (int32_t b = 0; b < nblk; b++) {
+                int32_t c = blk_comp[b];
+                int32_t k = pk.blk_k[b];
+                const int32_t* mem = st->cnodes.data() + st->cptr[c];
+                a.assign((size_t)k * k, 0.0);
+                // A_C = I - W_CC in local member order
+                for (int32_t i = 0; i < k; i++) {
+                    int32_t v = mem[i];
+                    a[(size_t)i * k + i] = 1.0;
+                    uint8_t pm = st->pmask[v];
+                    for (int slot = 0; slot < nslot; slot++) {
+                        if (!(pm & (1u << slot))) continue;
+                        int32_t u = (int32_t)nbr(gr, v, slot);
+                        if (st->comp[u] != c) continue;
+                        int32_t j = (int32_t)(std::lower_bound(mem, mem + k, u) - mem);
+                        a[(size_t)i * k + j] -= st->w6[(size_t)v * 6 + slot];
+                    }
+                }
+                double norm = 0.0;
+                for (int32_t i = 0; i < k; i++) {
+                    double rs = 0.0;
+                    for (int32_t j = 0; j < k; j++) rs += std::fabs(a[(size_t)i * k + j]);
+                    norm = std::max(norm, rs);
+                }
+                piv.assign(k, 0);
+                int bad = lu_factor(k, a.data(), piv.data(), 1e-14 * norm);
+                if (bad >= 0) {
+                    set_error("singular SCC block: %d nodes, pivot %d below 1e-14*||A_C||_inf", k, bad);
+                    delete st;
+                    return FM_ESINGULAR;
+                }
+                x.assign((size_t)k * k, 0.0);
+                lu_inverse(k, a.data(), piv.data(), x.data());
+                double* dst = pk.inv.data() + pk.blk_inv[b];
+                for (int32_t i = 0; i < k; i++)
+                    for (int32_t j = 0; j < k; j++) dst[(size_t)j * k + i] = x[(size_t)i * k + j];
+            }
+        }
+
+        // ---- 7: level-ordered packing ----
+        // order of components inside a level: singletons by node id, then blocks
+        auto pack_direction = [&](bool fwd, std::vector<uint64_t>& meta, std::vector<double>& wts,
+                                  std::vector<int32_t>& lvl_ptr, std::vector<int32_t>& lvl_nsc,
+                                  std::vector<int32_t>& blk_ptr, std::vector<int32_t>& blk_id,
+                                  std::vector<int32_t>& blk_pos, std::vector<int32_t>& pos_of, int32_t L) {
+            const std::vector<int32_t>& clev = fwd ? st->clev_f : st->clev_r;
+            std::vector<int64_t> cnt_sc(L + 1, 0), cnt_bl(L + 1, 0), nb(L + 1, 0);
+            for (int32_t c = 0; c < ncomp; c++) {
+                int32_t k = st->cptr[c + 1] - st->cptr[c];
+                if (k == 1) cnt_sc[clev[c]]++;
+                else { cnt_bl[clev[c]] += k; nb[clev[c]]++; }
+            }
+            lvl_ptr.assign(L + 1, 0);
+            lvl_nsc.assign(L, 0);
+            blk_ptr.assign(L + 1, 0);
+            for (int32_t l = 0; l < L; l++) {
+                lvl_ptr[l + 1] = (int32_t)(lvl_ptr[l] + cnt_sc[l] + cnt_bl[l]);
+                lvl_nsc[l] = (int32_t)cnt_sc[l];
+                blk_ptr[l + 1] = (int32_t)(blk_ptr[l] + nb[l]);
+                pk.max_level_nodes = std::max<int64_t>(pk.max_level_nodes, cnt_sc[l] + cnt_bl[l]);
+            }
+            std::vector<int32_t> next_sc(L), next_bl(L), next_b(L);
+            for (int32_t l = 0; l < L; l++) {
+                next_sc[l] = lvl_ptr[l];
+                next_bl[l] = lvl_ptr[l] + lvl_nsc[l];
+                next_b[l] = blk_ptr[l];
+            }
+            blk_id.assign(nblk, 0);
+            blk_pos.assign(nblk, 0);
+            pos_of.assign(N, 0);
+            // components in id order; singletons of one level then come in
+            // ascending component id; sort each level's singletons by node id
+            for (int32_t c = 0; c < ncomp; c++) {
+                int32_t k = st->cptr[c + 1] - st->cptr[c];
+                int32_t l = clev[c];
+                if (k == 1) {
+                    pos_of[st->cnodes[st->cptr[c]]] = next_sc[l]++;
+                } else {
+                    int32_t b = comp_blk[c];
+                    blk_id[next_b[l]++] = b;
+                    blk_pos[b] = next_bl[l];
+                    for (int32_t m = 0; m < k; m++) pos_of[st->cnodes[st->cptr[c] + m]] = next_bl[l]++;
+                }
+            }
+            // node ids of each level's singleton run in ascending order
+            std::vector<int32_t> order(N);
+            for (int64_t p = 0; p < N; p++) order[pos_of[p]] = (int32_t)p;
+            for (int32_t l = 0; l < L; l++) {
+                std::sort(order.begin() + lvl_ptr[l], order.begin() + lvl_ptr[l] + lvl_nsc[l]);
+                for (int32_t q = lvl_ptr[l]; q < lvl_ptr[l] + lvl_nsc[l]; q++) pos_of[order[q]] = q;
+            }
+            // records
+            meta.assign(N, 0);
+            wts.clear();
+            wts.reserve((size_t)(N + E));
+            for (int64_t q = 0; q < N; q++) {
+                int32_t v = order[q];
+                int32_t cv_ = st->comp[v];
+                uint8_t full = fwd ? st->pmask[v] : st->smask[v];
+                uint8_t mask = 0;
+                int64_t off = (int64_t)wts.size();
+                if (off > (int64_t)kOffMask) throw std::length_error("record offset overflow");
+                wts.push_back(st->cal[v]);
+                for (int slot = 0; slot < nslot; slot++) {
+                    if (!(full & (1u << slot))) continue;
+                    int32_t u = (int32_t)nbr(gr, v, slot);
+                    if (st->comp[u] == cv_) continue;   // internal to the block
+                    mask |= (uint8_t)(1u << slot);
+                    // forward: w_{v,u}; reverse: u is a successor, weight w_{u,v}
+                    double w = fwd ? st->w6[(size_t)v * 6 + slot] : st->w6[(size_t)u * 6 + (slot ^ 1)];
+                    wts.push_back(w);
+                }
+                meta[q] = (uint64_t)(uint32_t)v | ((uint64_t)off << kOffShift) | ((uint64_t)mask << kMaskShift);
+            }
+        };
+        std::vector<int32_t> fpos_of, rpos_of;
+        pk.L_f = L_f;
+        pk.L_r = L_r;
+        pack_direction(true, pk.fmeta, pk.fwts, pk.flvl_ptr, pk.flvl_nsc, pk.fblk_ptr, pk.fblk_id,
+                       pk.blk_fpos, fpos_of, L_f);
+        pack_direction(false, pk.rmeta, pk.rwts, pk.rlvl_ptr, pk.rlvl_nsc, pk.rblk_ptr, pk.rblk_id,
+                       pk.blk_rpos, rpos_of, L_r);
+        pk.cal_nat = st->cal;
+
+        // receivers: P^T entries sorted by reverse position, grouped per reverse level
+        pk.rcv_node.resize(n_rcv);
+        std::vector<std::pair<int32_t, int32_t>> ent(n_rcv);
+        for (int32_t r = 0; r < n_rcv; r++) {
+            pk.rcv_node[r] = (int32_t)rcv[r];
+            ent[r] = {rpos_of[rcv[r]], r};
+            pk.rmeta[rpos_of[rcv[r]]] |= kRcvFlag;
+        }
+        std::sort(ent.begin(), ent.end());
+        pk.rcv_pos.resize(n_rcv);
+        pk.rcv_idx.resize(n_rcv);
+        for (int32_t e = 0; e < n_rcv; e++) { pk.rcv_pos[e] = ent[e].first; pk.rcv_idx[e] = ent[e].second; }
+        pk.rcvlvl_ptr.assign(L_r + 1, 0);
+        {
+            int32_t e = 0;
+            for (int32_t l = 0; l < L_r; l++) {
+                while (e < n_rcv && pk.rcv_pos[e] < pk.rlvl_ptr[l + 1]) e++;
+                pk.rcvlvl_ptr[l + 1] = e;
+            }
+        }
+
+        // ---- statistics ----
+        int64_t n_unr = 0;
+        for (int64_t p = 0; p < N; p++) n_unr += unres[st->comp[p]];
+        fm_stats& S = st->stats;
+        S.N = N;
+        S.E = E;
+        S.levels_fwd = L_f;
+        S.levels_rev = L_r;
+        S.n_scc = nblk;
+        S.largest_scc = largest;
+        S.n_cyc = n_cyc;
+        S.sum_k2 = inv_total;
+        S.n_vio = n_vio;
+        S.n_unr = n_unr;
+        S.f_vio = E ? (double)n_vio / (double)E : 0.0;
+        S.f_cyc = (double)n_cyc / (double)N;
+        S.f_unr = (double)n_unr / (double)N;
+        S.state_bytes = (int64_t)(pk.fmeta.size() + pk.rmeta.size()) * 8 +
+                        (int64_t)(pk.fwts.size() + pk.rwts.size() + pk.inv.size() + pk.cal_nat.size()) * 8;
+        S.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    } catch (const std::bad_alloc&) {
+        delete st;
+        set_error("out of host memory during setup");
+        return FM_ENOMEM;
+    } catch (const std::length_error& e) {
+        delete st;
+        set_error("state too large for the packed format: %s", e.what());
+        return FM_EINVAL;
+    }
+    *out = st;
+    return FM_OK;
+}
+
+}  // namespace fm
