@@ -95,6 +95,7 @@ typedef struct fm_tuning {
     int32_t threads;        /* workgroup size: 256, 512 or 1024 */
     int32_t min_lds_bytes;  /* LDS reserved per workgroup (limits workgroups per CU) */
     int32_t xcd_aware;      /* 1 or 0 (default): keep the groups of one source on one XCD; -1: off */
+    int32_t unroll;         /* nodes per thread in flight inside a level: 1, 2 or 4 */
 } fm_tuning;
 
 /*

@@ -46,6 +46,7 @@ struct SrcDev {
     const int32_t* blk_rpos;
     const int64_t* blk_inv;
     const double* inv;
+    const double* invt;
     const void* cal_nat;
     const int32_t* rcv_node;
     const int32_t* rcvlvl_ptr;
@@ -147,6 +148,7 @@ int upload_state(HostState* st) {
     size_t o_brp = ar.add<int32_t>(pk.blk_rpos.size());
     size_t o_binv = ar.add<int64_t>(pk.blk_inv.size());
     size_t o_inv = ar.add<double>(pk.inv.size());
+    size_t o_invt = ar.add<double>(pk.invt.size());
     size_t o_cal = ar.add<double>(pk.cal_nat.size());
     size_t o_rn = ar.add<int32_t>(pk.rcv_node.size());
     size_t o_rlv = ar.add<int32_t>(pk.rcvlvl_ptr.size());
@@ -179,6 +181,7 @@ int upload_state(HostState* st) {
     rc = rc ? rc : put(b, o_brp, pk.blk_rpos);
     rc = rc ? rc : put(b, o_binv, pk.blk_inv);
     rc = rc ? rc : put(b, o_inv, pk.inv);
+    rc = rc ? rc : put(b, o_invt, pk.invt);
     rc = rc ? rc : put(b, o_cal, pk.cal_nat);
     rc = rc ? rc : put(b, o_rn, pk.rcv_node);
     rc = rc ? rc : put(b, o_rlv, pk.rcvlvl_ptr);
@@ -207,6 +210,7 @@ int upload_state(HostState* st) {
     d.blk_rpos = (const int32_t*)(b + o_brp);
     d.blk_inv = (const int64_t*)(b + o_binv);
     d.inv = (const double*)(b + o_inv);
+    d.invt = (const double*)(b + o_invt);
     d.cal_nat = b + o_cal;
     d.rcv_node = (const int32_t*)(b + o_rn);
     d.rcvlvl_ptr = (const int32_t*)(b + o_rlv);
@@ -271,181 +275,11 @@ struct ApplyArgs {
     void* work;             // J: X (out or scratch) ; J^T: lambda scratch
 };
 
-__device__ __forceinline__ int64_t nbr_off(int slot, int64_t st1, int64_t st2) {
-    int64_t st = (slot >> 1) == 0 ? 1 : ((slot >> 1) == 1 ? st1 : st2);
-    return (slot & 1) ? st : -st;
-}
+}  // namespace fm
 
-__device__ __forceinline__ bool item_of(const ApplyArgs& a, int& alpha, int& grp) {
-    int w = blockIdx.x;
-    int item = a.xcd_aware ? (w % 8) * a.per_xcd + (w / 8) : w;
-    if (item >= a.items) return false;
-    alpha = item / a.ngroups;
-    grp = item - alpha * a.ngroups;
-    return true;
-}
+#include "sweep.h"
 
-// Primal traversal: x_i = c_i ds_i + sum_{j in U(i)} w_ij x_j in topological
-// level order (eq. (discrete-row)), blocks x_C = A_C^{-1} b_C.
-template <typename V, int RG, int NT>
-__global__ __launch_bounds__(NT) void k_forward(ApplyArgs a) {
-    int alpha, grp;
-    if (!item_of(a, alpha, grp)) return;
-    extern __shared__ double lds[];
-    const SrcDev sd = a.src[alpha];
-    const V* __restrict__ wts = (const V*)sd.fwts;
-    const int r = threadIdx.x % RG;
-    const int slot0 = threadIdx.x / RG;
-    constexpr int SLOTS = NT / RG;
-    const int rhs = grp * RG + r;
-    const int64_t NB = a.N * a.B;
-    V* __restrict__ X = (V*)a.work + (size_t)alpha * NB;
-    const V* __restrict__ ds = (const V*)a.in + (a.in_mode == FM_DS_PER_PAIR ? (size_t)alpha * NB : 0);
-    const int B = a.B;
-    for (int l = 0; l < sd.L_f; ++l) {
-        const int p0 = sd.flvl_ptr[l];
-        const int nsc = sd.flvl_nsc[l];
-        for (int u = slot0; u < nsc; u += SLOTS) {
-            const uint64_t m = sd.fmeta[p0 + u];
-            const int64_t node = (int64_t)(m & kNodeMask);
-            const V* rec = wts + ((m >> kOffShift) & kOffMask);
-            unsigned mask = (unsigned)(m >> kMaskShift);
-            V acc = rec[0] * ds[node * B + rhs];
-            int t = 1;
-            while (mask) {
-                int slot = __builtin_ctz(mask);
-                mask &= mask - 1;
-                acc += rec[t++] * X[(node + nbr_off(slot, a.st1, a.st2)) * B + rhs];
-            }
-            X[node * B + rhs] = acc;
-        }
-        const int b0 = sd.fblk_ptr[l], b1 = sd.fblk_ptr[l + 1];
-        for (int bi = b0; bi < b1; ++bi) {
-            const int blk = sd.fblk_id[bi];
-            const int k = sd.blk_k[blk];
-            const int fp = sd.blk_fpos[blk];
-            const double* __restrict__ M = sd.inv + sd.blk_inv[blk];
-            for (int mi = slot0; mi < k; mi += SLOTS) {
-                const uint64_t m = sd.fmeta[fp + mi];
-                const int64_t node = (int64_t)(m & kNodeMask);
-                const V* rec = wts + ((m >> kOffShift) & kOffMask);
-                unsigned mask = (unsigned)(m >> kMaskShift);
-                double acc = (double)rec[0] * (double)ds[node * B + rhs];
-                int t = 1;
-                while (mask) {
-                    int slot = __builtin_ctz(mask);
-                    mask &= mask - 1;
-                    acc += (double)rec[t++] * (double)X[(node + nbr_off(slot, a.st1, a.st2)) * B + rhs];
-                }
-                lds[mi * RG + r] = acc;
-            }
-            __syncthreads();
-            for (int i = slot0; i < k; i += SLOTS) {
-                double acc = 0.0;
-                for (int j = 0; j < k; ++j) acc += M[(size_t)j * k + i] * lds[j * RG + r];
-                const int64_t node = (int64_t)(sd.fmeta[fp + i] & kNodeMask);
-                X[node * B + rhs] = (V)acc;
-            }
-            __syncthreads();
-        }
-        __syncthreads();
-    }
-}
-
-// Transpose traversal: lambda_j = r_j + sum_{i in succ(j)} w_ij lambda_i in
-// reverse level order; blocks lambda_C = A_C^{-T} b_C.
-template <typename V, int RG, int NT>
-__global__ __launch_bounds__(NT) void k_reverse(ApplyArgs a) {
-    int alpha, grp;
-    if (!item_of(a, alpha, grp)) return;
-    extern __shared__ double lds[];
-    const SrcDev sd = a.src[alpha];
-    const V* __restrict__ wts = (const V*)sd.rwts;
-    const int r = threadIdx.x % RG;
-    const int slot0 = threadIdx.x / RG;
-    constexpr int SLOTS = NT / RG;
-    const int rhs = grp * RG + r;
-    const int64_t NB = a.N * a.B;
-    const int B = a.B;
-    V* __restrict__ Lam = (V*)a.work + (size_t)alpha * NB;
-    const bool rcv_in = a.in_mode == FM_W_RECEIVERS;
-    const V* __restrict__ win = (const V*)a.in + (rcv_in ? (size_t)alpha * a.R * B : (size_t)alpha * NB);
-    V* __restrict__ outp = a.out_mode == FM_JT_PER_SOURCE ? (V*)a.out + (size_t)alpha * NB : nullptr;
-    for (int l = 0; l < sd.L_r; ++l) {
-        const int p0 = sd.rlvl_ptr[l];
-        const int nsc = sd.rlvl_nsc[l];
-        const int e0 = sd.rcvlvl_ptr[l], e1 = sd.rcvlvl_ptr[l + 1];
-        for (int u = slot0; u < nsc; u += SLOTS) {
-            const int pos = p0 + u;
-            const uint64_t m = sd.rmeta[pos];
-            const int64_t node = (int64_t)(m & kNodeMask);
-            const V* rec = wts + ((m >> kOffShift) & kOffMask);
-            unsigned mask = (unsigned)(m >> kMaskShift);
-            V acc;
-            if (!rcv_in) {
-                acc = win[node * B + rhs];
-            } else {
-                acc = (V)0;
-                if (m & kRcvFlag)
-                    for (int e = e0; e < e1; ++e)
-                        if (sd.rcv_pos[e] == pos) acc += win[(int64_t)sd.rcv_idx[e] * B + rhs];
-            }
-            int t = 1;
-            while (mask) {
-                int slot = __builtin_ctz(mask);
-                mask &= mask - 1;
-                acc += rec[t++] * Lam[(node + nbr_off(slot, a.st1, a.st2)) * B + rhs];
-            }
-            Lam[node * B + rhs] = acc;
-            if (outp) outp[node * B + rhs] = rec[0] * acc;
-        }
-        const int b0 = sd.rblk_ptr[l], b1 = sd.rblk_ptr[l + 1];
-        for (int bi = b0; bi < b1; ++bi) {
-            const int blk = sd.rblk_id[bi];
-            const int k = sd.blk_k[blk];
-            const int rp = sd.blk_rpos[blk];
-            const double* __restrict__ M = sd.inv + sd.blk_inv[blk];
-            for (int mi = slot0; mi < k; mi += SLOTS) {
-                const int pos = rp + mi;
-                const uint64_t m = sd.rmeta[pos];
-                const int64_t node = (int64_t)(m & kNodeMask);
-                const V* rec = wts + ((m >> kOffShift) & kOffMask);
-                unsigned mask = (unsigned)(m >> kMaskShift);
-                double acc;
-                if (!rcv_in) {
-                    acc = (double)win[node * B + rhs];
-                } else {
-                    acc = 0.0;
-                    if (m & kRcvFlag)
-                        for (int e = e0; e < e1; ++e)
-                            if (sd.rcv_pos[e] == pos) acc += (double)win[(int64_t)sd.rcv_idx[e] * B + rhs];
-                }
-                int t = 1;
-                while (mask) {
-                    int slot = __builtin_ctz(mask);
-                    mask &= mask - 1;
-                    acc += (double)rec[t++] * (double)Lam[(node + nbr_off(slot, a.st1, a.st2)) * B + rhs];
-                }
-                lds[mi * RG + r] = acc;
-            }
-            __syncthreads();
-            // lambda_j = sum_i M[i][j] b_i, summed in ascending i whatever the
-            // schedule, so every schedule produces the same bits
-            for (int j = slot0; j < k; j += SLOTS) {
-                double acc = 0.0;
-                const double* __restrict__ Mj = M + (size_t)j * k;
-                for (int i = 0; i < k; ++i) acc += Mj[i] * lds[i * RG + r];
-                const uint64_t m = sd.rmeta[rp + j];
-                const int64_t node = (int64_t)(m & kNodeMask);
-                const V* rec = wts + ((m >> kOffShift) & kOffMask);
-                Lam[node * B + rhs] = (V)acc;
-                if (outp) outp[node * B + rhs] = rec[0] * (V)acc;
-            }
-            __syncthreads();
-        }
-        __syncthreads();
-    }
-}
+namespace fm {
 
 // out[alpha][r][b] = X[alpha][rcv_alpha(r)][b]  (P_alpha, Section 4.4)
 template <typename V>
@@ -479,24 +313,41 @@ __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
 // batch and launches
 // ---------------------------------------------------------------------------
 
-template <typename V, int RG, int NT>
-static hipError_t launch_dir(bool fwd, const ApplyArgs& a, int grid, size_t lds, hipStream_t s) {
-    const void* fn = fwd ? (const void*)k_forward<V, RG, NT> : (const void*)k_reverse<V, RG, NT>;
+// VW values per lane access: 16 bytes (2 doubles, 4 floats) or the whole
+// group when it is smaller.
+template <typename V, int RG>
+constexpr int lane_width() {
+    return RG < (int)(16 / sizeof(V)) ? RG : (int)(16 / sizeof(V));
+}
+
+template <int DIR, typename V, int RG, int NT, int U>
+static hipError_t launch_one(const ApplyArgs& a, int grid, size_t lds, hipStream_t s) {
+    constexpr int VW = lane_width<V, RG>();
+    const void* fn = (const void*)k_sweep<DIR, V, RG, VW, NT, U>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    if (fwd) hipLaunchKernelGGL((k_forward<V, RG, NT>), dim3(grid), dim3(NT), lds, s, a);
-    else hipLaunchKernelGGL((k_reverse<V, RG, NT>), dim3(grid), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((k_sweep<DIR, V, RG, VW, NT, U>), dim3(grid), dim3(NT), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename V, int NT>
-static hipError_t launch_rg(bool fwd, int rg, const ApplyArgs& a, int grid, size_t lds, hipStream_t s) {
-    switch (rg) {
-        case 1: return launch_dir<V, 1, NT>(fwd, a, grid, lds, s);
-        case 2: return launch_dir<V, 2, NT>(fwd, a, grid, lds, s);
-        case 4: return launch_dir<V, 4, NT>(fwd, a, grid, lds, s);
-        case 8: return launch_dir<V, 8, NT>(fwd, a, grid, lds, s);
-        case 16: return launch_dir<V, 16, NT>(fwd, a, grid, lds, s);
+template <int DIR, typename V, int RG, int NT>
+static hipError_t launch_u(int u, const ApplyArgs& a, int grid, size_t lds, hipStream_t s) {
+    switch (u) {
+        case 1: return launch_one<DIR, V, RG, NT, 1>(a, grid, lds, s);
+        case 2: return launch_one<DIR, V, RG, NT, 2>(a, grid, lds, s);
+        case 4: return launch_one<DIR, V, RG, NT, 4>(a, grid, lds, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int DIR, typename V, int NT>
+static hipError_t launch_rg(const fm_tuning& t, const ApplyArgs& a, int grid, size_t lds, hipStream_t s) {
+    switch (t.rhs_per_group) {
+        case 1: return launch_u<DIR, V, 1, NT>(t.unroll, a, grid, lds, s);
+        case 2: return launch_u<DIR, V, 2, NT>(t.unroll, a, grid, lds, s);
+        case 4: return launch_u<DIR, V, 4, NT>(t.unroll, a, grid, lds, s);
+        case 8: return launch_u<DIR, V, 8, NT>(t.unroll, a, grid, lds, s);
+        case 16: return launch_u<DIR, V, 16, NT>(t.unroll, a, grid, lds, s);
     }
     return hipErrorInvalidValue;
 }
@@ -504,10 +355,18 @@ static hipError_t launch_rg(bool fwd, int rg, const ApplyArgs& a, int grid, size
 template <typename V>
 static hipError_t launch_sweep(bool fwd, const fm_tuning& t, const ApplyArgs& a, int grid, size_t lds,
                                hipStream_t s) {
-    switch (t.threads) {
-        case 256: return launch_rg<V, 256>(fwd, t.rhs_per_group, a, grid, lds, s);
-        case 512: return launch_rg<V, 512>(fwd, t.rhs_per_group, a, grid, lds, s);
-        case 1024: return launch_rg<V, 1024>(fwd, t.rhs_per_group, a, grid, lds, s);
+    if (fwd) {
+        switch (t.threads) {
+            case 256: return launch_rg<kFwd, V, 256>(t, a, grid, lds, s);
+            case 512: return launch_rg<kFwd, V, 512>(t, a, grid, lds, s);
+            case 1024: return launch_rg<kFwd, V, 1024>(t, a, grid, lds, s);
+        }
+    } else {
+        switch (t.threads) {
+            case 256: return launch_rg<kRev, V, 256>(t, a, grid, lds, s);
+            case 512: return launch_rg<kRev, V, 512>(t, a, grid, lds, s);
+            case 1024: return launch_rg<kRev, V, 1024>(t, a, grid, lds, s);
+        }
     }
     return hipErrorInvalidValue;
 }
@@ -535,6 +394,7 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     fm_tuning t{};
     if (tuning) t = *tuning;
     if (t.threads == 0) t.threads = 1024;
+    if (t.unroll == 0) t.unroll = 2;
     if (t.rhs_per_group == 0) {
         t.rhs_per_group = 1;
         while (t.rhs_per_group < 16 && B % (t.rhs_per_group * 2) == 0 && t.rhs_per_group * 2 <= 4)
@@ -546,6 +406,7 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     if (rg != 1 && rg != 2 && rg != 4 && rg != 8 && rg != 16) { set_error("rhs_per_group must be 1,2,4,8 or 16"); return FM_EINVAL; }
     if (B % rg != 0) { set_error("B=%d is not a multiple of rhs_per_group=%d", B, rg); return FM_EINVAL; }
     if (t.threads != 256 && t.threads != 512 && t.threads != 1024) { set_error("threads must be 256, 512 or 1024"); return FM_EINVAL; }
+    if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) { set_error("unroll must be 1, 2 or 4"); return FM_EINVAL; }
     size_t need = (size_t)maxk * rg * sizeof(double);
     if (need > kLdsMax) {
         set_error("largest SCC block (%d nodes) needs %zu B of LDS with %d rhs per group; use fewer", maxk, need, rg);
@@ -647,8 +508,11 @@ static int check_device(const fm_batch* b) {
     return FM_OK;
 }
 
+static bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
 int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode) {
     if (!b || !ds || !out) { set_error("null argument"); return FM_EINVAL; }
+    if (!aligned16(ds) || !aligned16(out)) { set_error("device buffers must be 16-byte aligned"); return FM_EINVAL; }
     if (ds_mode != FM_DS_PER_PAIR && ds_mode != FM_DS_BROADCAST) { set_error("bad ds_mode %d", ds_mode); return FM_EINVAL; }
     if (out_mode != FM_OUT_NODES && out_mode != FM_OUT_RECEIVERS) { set_error("bad out_mode %d", out_mode); return FM_EINVAL; }
     if (out_mode == FM_OUT_RECEIVERS && b->R == 0) { set_error("the states have no receivers"); return FM_EINVAL; }
@@ -676,6 +540,7 @@ int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out
 
 int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode) {
     if (!b || !w || !out) { set_error("null argument"); return FM_EINVAL; }
+    if (!aligned16(w) || !aligned16(out)) { set_error("device buffers must be 16-byte aligned"); return FM_EINVAL; }
     if (w_mode != FM_W_NODES && w_mode != FM_W_RECEIVERS) { set_error("bad w_mode %d", w_mode); return FM_EINVAL; }
     if (out_mode != FM_JT_PER_SOURCE && out_mode != FM_JT_SUMMED) { set_error("bad out_mode %d", out_mode); return FM_EINVAL; }
     if (w_mode == FM_W_RECEIVERS && b->R == 0) { set_error("the states have no receivers"); return FM_EINVAL; }

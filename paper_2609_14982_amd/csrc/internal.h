@@ -17,19 +17,23 @@ void clear_error();
 // Packed record format shared by the host packer and the kernels.
 //
 // Every node owns one record per traversal direction, stored in that
-// direction's level order:
+// direction's level order (position q):
 //   meta word (uint64): bits 0..30  node id
 //                       bit  31     node is a receiver (reverse records only)
-//                       bits 32..57 offset of the value record (in elements)
+//                       bits 32..57 offset of the node's extra weights in the
+//                                   overflow area (only with > 3 neighbours)
 //                       bits 58..63 neighbour mask
-//   value record:       [c_node, w_1, ..., w_m], one weight per set mask bit
-//                       in increasing bit order
-// Neighbour slot b: axis = b >> 1; side = b & 1; side 0 is node - stride[axis],
-// side 1 is node + stride[axis].  In forward records the mask lists the
-// predecessors j of the node with weight w_{node,j}; in reverse records it
-// lists the successors i with weight w_{i,node}.  For members of a nontrivial
-// SCC only the neighbours outside the component are listed; couplings inside
-// the component live in the block's dense factors.
+//   value record:       rec[q] = [c_node, w_1, w_2, w_3] (fixed 4 entries,
+//                       unused entries 0); weights w_4.. of a node with more
+//                       than three neighbours follow in the overflow area that
+//                       starts after the N fixed records.
+// Weights are listed in increasing mask-bit order.  Neighbour slot b: axis =
+// b >> 1; side = b & 1; side 0 is node - stride[axis], side 1 is node +
+// stride[axis].  In forward records the mask lists the predecessors j of the
+// node with weight w_{node,j}; in reverse records it lists the successors i
+// with weight w_{i,node}.  For members of a nontrivial SCC only the
+// neighbours outside the component are listed; couplings inside the
+// component live in the block's dense factors.
 // ---------------------------------------------------------------------------
 constexpr int kNodeBits = 31;
 constexpr uint64_t kNodeMask = (1ull << kNodeBits) - 1;
@@ -43,7 +47,7 @@ struct Packed {
     int32_t L_f = 0, L_r = 0, nblk = 0;
     // forward traversal
     std::vector<uint64_t> fmeta;       // [N]
-    std::vector<double> fwts;          // records
+    std::vector<double> fwts;          // [N][4] records, then the overflow area
     std::vector<int32_t> flvl_ptr;     // [L_f + 1] position range per level
     std::vector<int32_t> flvl_nsc;     // [L_f] scalar nodes at the start of each level
     std::vector<int32_t> fblk_ptr;     // [L_f + 1] range into fblk_id
@@ -54,8 +58,9 @@ struct Packed {
     std::vector<int32_t> rlvl_ptr, rlvl_nsc, rblk_ptr, rblk_id;
     // nontrivial SCC blocks: member m sits at fpos+m / rpos+m
     std::vector<int32_t> blk_k, blk_fpos, blk_rpos;
-    std::vector<int64_t> blk_inv;      // offset of the k x k inverse (column-major)
-    std::vector<double> inv;
+    std::vector<int64_t> blk_inv;      // offset of the k x k inverse in inv and invt
+    std::vector<double> inv;           // A_C^{-1}, column-major (entry (i,j) at j*k + i)
+    std::vector<double> invt;          // the same matrix row-major (entry (i,j) at i*k + j)
     std::vector<double> cal_nat;       // [N] calibration in natural order
     // receivers
     std::vector<int32_t> rcv_node;     // [R]

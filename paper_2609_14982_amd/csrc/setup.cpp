@@ -404,6 +404,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         }
         pk.max_blk_k = largest;
         pk.inv.assign((size_t)inv_total, 0.0);
+        pk.invt.assign((size_t)inv_total, 0.0);
         {
             std::vector<double> a, x;
             std::vector<int32_t> piv, local(0);
@@ -443,6 +444,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 double* dst = pk.inv.data() + pk.blk_inv[b];
                 for (int32_t i = 0; i < k; i++)
                     for (int32_t j = 0; j < k; j++) dst[(size_t)j * k + i] = x[(size_t)i * k + j];
+                std::copy(x.begin(), x.end(), pk.invt.begin() + pk.blk_inv[b]);
             }
         }
 
@@ -498,18 +500,21 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 std::sort(order.begin() + lvl_ptr[l], order.begin() + lvl_ptr[l] + lvl_nsc[l]);
                 for (int32_t q = lvl_ptr[l]; q < lvl_ptr[l] + lvl_nsc[l]; q++) pos_of[order[q]] = q;
             }
-            // records
+            // records: a fixed [c, w1, w2, w3] per position, further weights of
+            // the rare nodes with more than three neighbours in an overflow area
+            // after the N fixed records
             meta.assign(N, 0);
-            wts.clear();
-            wts.reserve((size_t)(N + E));
+            wts.assign((size_t)N * 4, 0.0);
+            std::vector<double> ovf;
             for (int64_t q = 0; q < N; q++) {
                 int32_t v = order[q];
                 int32_t cv_ = st->comp[v];
                 uint8_t full = fwd ? st->pmask[v] : st->smask[v];
                 uint8_t mask = 0;
-                int64_t off = (int64_t)wts.size();
-                if (off > (int64_t)kOffMask) throw std::length_error("record offset overflow");
-                wts.push_back(st->cal[v]);
+                double* rec = wts.data() + (size_t)q * 4;
+                rec[0] = st->cal[v];
+                int t = 0;
+                int64_t off = 0;
                 for (int slot = 0; slot < nslot; slot++) {
                     if (!(full & (1u << slot))) continue;
                     int32_t u = (int32_t)nbr(gr, v, slot);
@@ -517,10 +522,19 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                     mask |= (uint8_t)(1u << slot);
                     // forward: w_{v,u}; reverse: u is a successor, weight w_{u,v}
                     double w = fwd ? st->w6[(size_t)v * 6 + slot] : st->w6[(size_t)u * 6 + (slot ^ 1)];
-                    wts.push_back(w);
+                    if (t < 3) {
+                        rec[1 + t] = w;
+                    } else {
+                        if (t == 3) off = (int64_t)ovf.size();
+                        ovf.push_back(w);
+                    }
+                    t++;
                 }
+                if (off > (int64_t)kOffMask) throw std::length_error("record overflow area too large");
                 meta[q] = (uint64_t)(uint32_t)v | ((uint64_t)off << kOffShift) | ((uint64_t)mask << kMaskShift);
             }
+            wts.insert(wts.end(), ovf.begin(), ovf.end());
+            wts.resize(wts.size() + 4, 0.0);
         };
         std::vector<int32_t> fpos_of, rpos_of;
         pk.L_f = L_f;
@@ -570,7 +584,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         S.f_cyc = (double)n_cyc / (double)N;
         S.f_unr = (double)n_unr / (double)N;
         S.state_bytes = (int64_t)(pk.fmeta.size() + pk.rmeta.size()) * 8 +
-                        (int64_t)(pk.fwts.size() + pk.rwts.size() + pk.inv.size() + pk.cal_nat.size()) * 8;
+                        (int64_t)(pk.fwts.size() + pk.rwts.size() + 2 * pk.inv.size() + pk.cal_nat.size()) * 8;
         S.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     } catch (const std::bad_alloc&) {
         delete st;
