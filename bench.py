@@ -32,18 +32,41 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(stats_list, B, vbytes, wbytes, direction):
-    """Bytes one launch of the dominant sweep kernel must move, summed over
+def algorithmic_bytes(stats_list, B, vbytes, wbytes):
+    """Compulsory HBM bytes of one launch of a sweep kernel, summed over
     sources: the input and output vectors once per (source, rhs)
-    (2 * vbytes * N * B), plus the source's packed state read once: 8 B of
-    meta per node, the value records (1 + edges per node) * wbytes and the
-    FP64 SCC block matrices 8 * sum k^2.  Predecessor re-reads are counted as
-    cache hits."""
+    (2 * vbytes * N * B) plus the source's packed state read once - an 8-byte
+    meta word and a 4-entry value record per node (8 + 4 * wbytes) and the FP64
+    SCC block matrix of that direction (8 * sum k^2).  Predecessor re-reads
+    and the records' overflow entries (<0.5 % of nodes) are not counted."""
     total = 0
     for st in stats_list:
-        N, E, k2 = st["N"], st["E"], st["sum_k2"]
-        total += 2 * vbytes * N * B + 8 * N + wbytes * (N + E) + 8 * k2
+        N, k2 = st["N"], st["sum_k2"]
+        total += 2 * vbytes * N * B + (8 + 4 * wbytes) * N + 8 * k2
     return total
+
+
+KERNEL_SOURCES = ("paper_2609_14982_amd/csrc/sweep.h", "paper_2609_14982_amd/csrc/device.hip",
+                  "paper_2609_14982_amd/csrc/setup.cpp")
+
+
+def measured_traffic(config, precision):
+    """HBM bytes per launch of the primal sweep kernel from the committed
+    counter profile, or None when that profile is for another workload or for
+    different kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_k_sweep_{config}_{precision}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        doc = json.load(f)
+    h = hashlib.sha256()
+    for src in doc.get("kernel_sources", KERNEL_SOURCES):
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != doc.get("kernel_source_sha256"):
+        return None
+    return doc["per_launch"]["J"]["hbm_bytes"]
 
 
 def cpu_baseline(wl, n_src, B, seed):
@@ -85,8 +108,23 @@ def main():
     ap.add_argument("--rhs-per-group", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sources", type=int, default=1)
+    ap.add_argument("--cpu-sources", type=int, default=4)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the directional-sweeping comparison")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of a known size (HBM counter calibration)")
     args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        n = 1 << 29      # 2^29 doubles = 4 GiB read + 4 GiB written per copy
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": n * 8, "copy_calibration_bytes_written": n * 8,
+                          "copies": 3}))
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -167,23 +205,48 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     log(f"timed {args.steps} steps: {ms_per_step:.3f} ms/step; J {tJ.mean():.3f} ms, J^T {tT.mean():.3f} ms")
 
-    bytes_J = algorithmic_bytes(stats, B, vbytes, vbytes, "J")
-    bytes_T = algorithmic_bytes(stats, B, vbytes, vbytes, "JT")
+    # roofline of the dominant kernel: the primal sweep (one launch per apply_J;
+    # the receiver gather launched after it moves S*R*B values, <0.01 %)
+    bytes_J = algorithmic_bytes(stats, B, vbytes, vbytes)
     gbs_J = bytes_J / (tJ.mean() * 1e-3) / 1e9
-    gbs_T = bytes_T / (tT.mean() * 1e-3) / 1e9
-    dom = "J" if tJ.mean() >= tT.mean() else "JT"
-    ach = gbs_J if dom == "J" else gbs_T
-    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None,
-            "kernel": "k_forward (apply_J)" if dom == "J" else "k_reverse (apply_JT)",
-            "bytes_per_launch": bytes_J if dom == "J" else bytes_T,
-            "launch_ms": round(float(tJ.mean() if dom == "J" else tT.mean()), 4),
-            "other": {"J_GBs": round(gbs_J, 1), "JT_GBs": round(gbs_T, 1)}}
+    gbs_T = bytes_J / (tT.mean() * 1e-3) / 1e9
+    traffic = measured_traffic(args.config, args.precision) if not args.sources else None
+    roof = {"bound": "hbm", "achieved": round(gbs_J, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs_J / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "kernel": "k_sweep primal (apply_J)", "bytes_per_launch": bytes_J,
+            "launch_ms": round(float(tJ.mean()), 4),
+            "transpose_GBs_incl_source_sum": round(gbs_T, 1)}
+
+    sweep = None
+    if not args.no_sweep:
+        # the same paired application by directional Gauss-Seidel sweeping
+        # (Section 3.6) on the same GPU, converged to the same accuracy
+        log("directional-sweeping comparison (converged)")
+        rcv = torch.as_tensor(wl.rcv, device=dev)
+        r_nodes = torch.zeros((S, N, B), device=dev, dtype=dt)
+        batch.apply_J_sweep(p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS, max_cycles=1)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        cj = batch.apply_J_sweep(p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS, want_cycles=True)
+        e1.record(stream)
+        r_nodes.zero_()
+        r_nodes.index_add_(1, rcv, y)      # P^T y at the nodes
+        ct = batch.apply_JT_sweep(r_nodes, g, fm.FM_JT_SUMMED, want_cycles=True)
+        e2.record(stream)
+        torch.cuda.synchronize()
+        tsJ, tsT = e0.elapsed_time(e1), e1.elapsed_time(e2)
+        del r_nodes
+        sweep = {"value": round(S * B / ((tsJ + tsT) * 1e-3), 3), "unit": "paired applies/s",
+                 "J_ms": round(tsJ, 2), "JT_ms": round(tsT, 2),
+                 "cycles_J": [int(cj.min()), int(cj.max())], "cycles_JT": [int(ct.min()), int(ct.max())],
+                 "sweeps_per_cycle": 2 ** wl.dim}
+        log(f"sweeping: J {tsJ:.1f} ms ({cj.min()}-{cj.max()} cycles), J^T {tsT:.1f} ms "
+            f"({ct.min()}-{ct.max()} cycles)")
 
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_sources} source(s) x {B} rhs")
-        W.eikonal(wl) if wl.T is None else None
         cpu = cpu_baseline(wl, args.cpu_sources, B, 4001)
         log(f"cpu baseline: {cpu['value']:.3f} paired applies/s")
 
@@ -211,6 +274,8 @@ def main():
                    "J_ms": round(float(tJ.mean()), 4), "JT_ms": round(float(tT.mean()), 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "vs_sweeping": round(value / sweep["value"], 2) if sweep else None,
+        "sweeping_baseline": sweep,
     }
     print(json.dumps(res), flush=True)
 

@@ -184,6 +184,24 @@ int fm_apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t 
  */
 int fm_apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode);
 
+/*
+ * Comparison baseline, not the method: the same J and J^T computed by
+ * directional Gauss-Seidel sweeping (Section 3.6) on the GPU, without the
+ * graph analysis.  Every (source, rhs) system is swept over the 2^dim axis
+ * orderings (hyperplane by hyperplane, newest values) from zero until a whole
+ * cycle changes no entry by more than 1e-15 * max|x| or max_cycles cycles
+ * have run.  Layouts as fm_apply_J / fm_apply_JT, except that the transpose
+ * takes nodal input only (FM_W_NODES).  The first call on a batch uploads
+ * natural-order copies of W and W^T and so allocates device memory.
+ * cycles: NULL, or host [S * B / rhs_per_group] receiving the cycles each
+ * workgroup used (negative: not converged); non-NULL makes the call wait for
+ * the stream.  Errors: FM_EINVAL, FM_ENOMEM, FM_EHIP.
+ */
+int fm_apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode,
+                     int32_t max_cycles, int32_t* cycles);
+int fm_apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles,
+                      int32_t* cycles);
+
 /* Free a batch (its scratch); the states stay valid. */
 void fm_batch_free(fm_batch* b);
 

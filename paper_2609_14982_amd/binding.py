@@ -23,7 +23,7 @@ SYMBOLS = (
     "fm_build_frozen_state", "fm_build_frozen_states", "fm_state_stats",
     "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
     "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_apply_J",
-    "fm_apply_JT", "fm_batch_free", "fm_last_error",
+    "fm_apply_JT", "fm_apply_J_sweep", "fm_apply_JT_sweep", "fm_batch_free", "fm_last_error",
 )
 
 
@@ -79,6 +79,8 @@ def load():
         "fm_batch_tuning": (C.c_int, [vp, vp]),
         "fm_apply_J": (C.c_int, [vp, vp, i32, vp, i32]),
         "fm_apply_JT": (C.c_int, [vp, vp, i32, vp, i32]),
+        "fm_apply_J_sweep": (C.c_int, [vp, vp, i32, vp, i32, i32, vp]),
+        "fm_apply_JT_sweep": (C.c_int, [vp, vp, vp, i32, i32, vp]),
         "fm_batch_free": (None, [vp]),
         "fm_last_error": (C.c_char_p, []),
     }
@@ -268,6 +270,30 @@ class Batch:
         _check(load().fm_apply_JT(self._ptr, _dptr(w, self.dtype, w_shape, "w"), int(w_mode),
                                   _dptr(out, self.dtype, out_shape, "out"), int(out_mode)))
         return out
+
+    def _groups(self):
+        return self.S * (self.B // self.tuning()["rhs_per_group"])
+
+    def apply_J_sweep(self, ds, ds_mode, out, out_mode, max_cycles=10000, want_cycles=False):
+        """Comparison baseline: J by directional Gauss-Seidel sweeping."""
+        S, N, B = self.S, self.N, self.B
+        ds_shape = (S, N, B) if ds_mode == FM_DS_PER_PAIR else (N, B)
+        out_shape = (S, N, B) if out_mode == FM_OUT_NODES else (S, self.R, B)
+        cyc = np.zeros(self._groups(), dtype=np.int32) if want_cycles else None
+        _check(load().fm_apply_J_sweep(self._ptr, _dptr(ds, self.dtype, ds_shape, "ds"), int(ds_mode),
+                                       _dptr(out, self.dtype, out_shape, "out"), int(out_mode),
+                                       int(max_cycles), cyc.ctypes.data if cyc is not None else None))
+        return cyc
+
+    def apply_JT_sweep(self, w, out, out_mode, max_cycles=10000, want_cycles=False):
+        """Comparison baseline: J^T (nodal input) by directional Gauss-Seidel sweeping."""
+        S, N, B = self.S, self.N, self.B
+        out_shape = (S, N, B) if out_mode == FM_JT_PER_SOURCE else (N, B)
+        cyc = np.zeros(self._groups(), dtype=np.int32) if want_cycles else None
+        _check(load().fm_apply_JT_sweep(self._ptr, _dptr(w, self.dtype, (S, N, B), "w"),
+                                        _dptr(out, self.dtype, out_shape, "out"), int(out_mode),
+                                        int(max_cycles), cyc.ctypes.data if cyc is not None else None))
+        return cyc
 
     def free(self):
         if getattr(self, "_ptr", None) is not None and self._ptr.value:

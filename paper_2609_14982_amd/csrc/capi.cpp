@@ -30,6 +30,9 @@ int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out
 int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode);
 int batch_set_stream(fm_batch* b, void* stream);
 int batch_tuning(const fm_batch* b, fm_tuning* out);
+int apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode, int32_t max_cycles,
+                  int32_t* cycles_host);
+int apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles, int32_t* cycles_host);
 
 }  // namespace fm
 
@@ -159,6 +162,18 @@ int fm_apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t 
 int fm_apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode) {
     fm::clear_error();
     return fm::apply_JT(b, w, w_mode, out, out_mode);
+}
+
+int fm_apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode,
+                     int32_t max_cycles, int32_t* cycles) {
+    fm::clear_error();
+    return fm::apply_J_sweep(b, ds, ds_mode, out, out_mode, max_cycles, cycles);
+}
+
+int fm_apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles,
+                      int32_t* cycles) {
+    fm::clear_error();
+    return fm::apply_JT_sweep(b, w, out, out_mode, max_cycles, cycles);
 }
 
 void fm_batch_free(fm_batch* b) { fm::batch_free(b); }

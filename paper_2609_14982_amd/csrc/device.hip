@@ -56,6 +56,10 @@ struct SrcDev {
 };
 
 struct DeviceState {
+    void* blob_nat = nullptr;    // natural-order records for the sweeping baseline
+    void* blob_nat32 = nullptr;
+    const void* nat[4] = {nullptr, nullptr, nullptr, nullptr};     // fmeta, frec, rmeta, rrec
+    const void* nat32[2] = {nullptr, nullptr};                     // frec, rrec in FP32
     void* blob = nullptr;        // all FP64 arrays and integer tables
     void* blob32 = nullptr;      // FP32 copies of the records and calibration
     SrcDev d{};                  // pointers into blob (FP64 records)
@@ -79,6 +83,8 @@ struct fm_batch {
     int device = -1;
     size_t lds_bytes = 0;
     int32_t grid = 0, per_xcd = 0, items = 0;
+    void* nat_dev = nullptr;         // [S] NatDev, created by the first sweeping-baseline call
+    int32_t* cycles_dev = nullptr;   // [items]
 };
 
 namespace fm {
@@ -253,6 +259,8 @@ static int upload_fp32(HostState* st) {
 
 void free_device_state(HostState* st) {
     if (!st->dev) return;
+    if (st->dev->blob_nat) (void)hipFree(st->dev->blob_nat);
+    if (st->dev->blob_nat32) (void)hipFree(st->dev->blob_nat32);
     if (st->dev->blob) (void)hipFree(st->dev->blob);
     if (st->dev->blob32) (void)hipFree(st->dev->blob32);
     delete st->dev;
@@ -278,6 +286,7 @@ struct ApplyArgs {
 }  // namespace fm
 
 #include "sweep.h"
+#include "baseline.h"
 
 namespace fm {
 
@@ -477,6 +486,8 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
 
 void batch_free(fm_batch* b) {
     if (!b) return;
+    if (b->nat_dev) (void)hipFree(b->nat_dev);
+    if (b->cycles_dev) (void)hipFree(b->cycles_dev);
     if (b->d_src) (void)hipFree(b->d_src);
     if (b->scratch) (void)hipFree(b->scratch);
     delete b;
@@ -563,6 +574,205 @@ int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_
         else hipLaunchKernelGGL(k_sum_sources<float>, dim3(grid), dim3(256), 0, b->stream, a, cal);
         e = hipGetLastError();
         if (e != hipSuccess) { set_error("source-sum launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    }
+    return FM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// directional-sweeping comparison baseline
+// ---------------------------------------------------------------------------
+
+static int upload_natural(HostState* st, int prec) {
+    DeviceState* ds = st->dev;
+    if (!ds->blob_nat) {
+        std::vector<uint64_t> fm_, rm_;
+        std::vector<double> fr, rr;
+        pack_natural(st, true, fm_, fr);
+        pack_natural(st, false, rm_, rr);
+        Arena ar;
+        size_t o1 = ar.add<uint64_t>(fm_.size()), o2 = ar.add<double>(fr.size());
+        size_t o3 = ar.add<uint64_t>(rm_.size()), o4 = ar.add<double>(rr.size());
+        size_t total = ar.add<char>(0) + 256;
+        hipError_t e = hipMalloc(&ds->blob_nat, total);
+        if (e != hipSuccess) {
+            ds->blob_nat = nullptr;
+            set_error("hipMalloc(%zu) for baseline records failed: %s", total, hipGetErrorString(e));
+            return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+        }
+        char* b = (char*)ds->blob_nat;
+        int rc = put(b, o1, fm_);
+        rc = rc ? rc : put(b, o2, fr);
+        rc = rc ? rc : put(b, o3, rm_);
+        rc = rc ? rc : put(b, o4, rr);
+        if (rc) return rc;
+        ds->nat[0] = b + o1;
+        ds->nat[1] = b + o2;
+        ds->nat[2] = b + o3;
+        ds->nat[3] = b + o4;
+        if (prec == FM_FP32) {
+            std::vector<float> f32(fr.begin(), fr.end()), r32(rr.begin(), rr.end());
+            Arena a2;
+            size_t p1 = a2.add<float>(f32.size()), p2 = a2.add<float>(r32.size());
+            size_t t2 = a2.add<char>(0) + 256;
+            e = hipMalloc(&ds->blob_nat32, t2);
+            if (e != hipSuccess) {
+                ds->blob_nat32 = nullptr;
+                set_error("hipMalloc for FP32 baseline records failed: %s", hipGetErrorString(e));
+                return FM_ENOMEM;
+            }
+            char* c = (char*)ds->blob_nat32;
+            rc = put(c, p1, f32);
+            rc = rc ? rc : put(c, p2, r32);
+            if (rc) return rc;
+            ds->nat32[0] = c + p1;
+            ds->nat32[1] = c + p2;
+        }
+    }
+    return FM_OK;
+}
+
+static int prepare_baseline(fm_batch* b) {
+    if (b->nat_dev) return FM_OK;
+    std::vector<NatDev> h(b->S);
+    for (int32_t i = 0; i < b->S; i++) {
+        int rc = upload_natural(b->states[i], b->prec);
+        if (rc) return rc;
+        const DeviceState* ds = b->states[i]->dev;
+        h[i].fmeta = (const uint64_t*)ds->nat[0];
+        h[i].frec = b->prec == FM_FP64 ? ds->nat[1] : ds->nat32[0];
+        h[i].rmeta = (const uint64_t*)ds->nat[2];
+        h[i].rrec = b->prec == FM_FP64 ? ds->nat[3] : ds->nat32[1];
+    }
+    void* nd = nullptr;
+    int32_t* cyc = nullptr;
+    hipError_t e = hipMalloc(&nd, sizeof(NatDev) * b->S);
+    if (e == hipSuccess) e = hipMalloc(&cyc, sizeof(int32_t) * b->items);
+    if (e == hipSuccess) e = hipMemcpy(nd, h.data(), sizeof(NatDev) * b->S, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (nd) (void)hipFree(nd);
+        if (cyc) (void)hipFree(cyc);
+        set_error("baseline setup failed: %s", hipGetErrorString(e));
+        return FM_EHIP;
+    }
+    b->nat_dev = nd;
+    b->cycles_dev = cyc;
+    return FM_OK;
+}
+
+template <int DIR, typename V, int RG, int NT>
+static hipError_t launch_gs(const GsArgs& g, int grid, hipStream_t s) {
+    constexpr int VW = lane_width<V, RG>();
+    hipLaunchKernelGGL((k_gs_sweep<DIR, V, RG, VW, NT>), dim3(grid), dim3(NT), 0, s, g);
+    return hipGetLastError();
+}
+
+template <int DIR, typename V>
+static hipError_t launch_gs_rg(int rg, const GsArgs& g, int grid, hipStream_t s) {
+    switch (rg) {
+        case 1: return launch_gs<DIR, V, 1, 1024>(g, grid, s);
+        case 2: return launch_gs<DIR, V, 2, 1024>(g, grid, s);
+        case 4: return launch_gs<DIR, V, 4, 1024>(g, grid, s);
+        case 8: return launch_gs<DIR, V, 8, 1024>(g, grid, s);
+        case 16: return launch_gs<DIR, V, 16, 1024>(g, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static int run_gs(fm_batch* b, bool fwd, GsArgs& g, int32_t* cycles_host) {
+    const HostState* s0 = b->states[0];
+    g.nat = (const NatDev*)b->nat_dev;
+    g.cycles = b->cycles_dev;
+    g.tol = 1e-15;
+    g.dim = s0->dim;
+    g.m0 = (int32_t)s0->n[0];
+    g.m1 = (int32_t)s0->n[1];
+    g.m2 = (int32_t)s0->n[2];
+    int rg = b->tun.rhs_per_group;
+    hipError_t e;
+    if (b->prec == FM_FP64) e = fwd ? launch_gs_rg<kFwd, double>(rg, g, b->grid, b->stream) : launch_gs_rg<kRev, double>(rg, g, b->grid, b->stream);
+    else e = fwd ? launch_gs_rg<kFwd, float>(rg, g, b->grid, b->stream) : launch_gs_rg<kRev, float>(rg, g, b->grid, b->stream);
+    if (e != hipSuccess) { set_error("sweep launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    if (cycles_host) {
+        HIP_TRY(hipMemcpyAsync(cycles_host, b->cycles_dev, sizeof(int32_t) * b->items, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+    }
+    return FM_OK;
+}
+
+int apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode, int32_t max_cycles,
+                  int32_t* cycles_host) {
+    if (!b || !ds || !out) { set_error("null argument"); return FM_EINVAL; }
+    if (!aligned16(ds) || !aligned16(out)) { set_error("device buffers must be 16-byte aligned"); return FM_EINVAL; }
+    if (ds_mode != FM_DS_PER_PAIR && ds_mode != FM_DS_BROADCAST) { set_error("bad ds_mode %d", ds_mode); return FM_EINVAL; }
+    if (out_mode != FM_OUT_NODES && out_mode != FM_OUT_RECEIVERS) { set_error("bad out_mode %d", out_mode); return FM_EINVAL; }
+    if (out_mode == FM_OUT_RECEIVERS && b->R == 0) { set_error("the states have no receivers"); return FM_EINVAL; }
+    if (max_cycles < 1) { set_error("max_cycles must be >= 1"); return FM_EINVAL; }
+    int rc = check_device(b);
+    if (rc) return rc;
+    rc = prepare_baseline(b);
+    if (rc) return rc;
+    GsArgs g{};
+    g.a = base_args(b);
+    g.a.in = ds;
+    g.a.in_mode = ds_mode;
+    g.a.out = out;
+    g.a.out_mode = out_mode;
+    g.a.work = out_mode == FM_OUT_NODES ? out : b->scratch;
+    g.max_cycles = max_cycles;
+    rc = run_gs(b, true, g, nullptr);
+    if (rc) return rc;
+    if (out_mode == FM_OUT_RECEIVERS) {
+        int64_t total = (int64_t)b->S * b->R * b->B;
+        int grid = (int)std::min<int64_t>((total + 255) / 256, 65535);
+        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_gather_receivers<double>, dim3(grid), dim3(256), 0, b->stream, g.a);
+        else hipLaunchKernelGGL(k_gather_receivers<float>, dim3(grid), dim3(256), 0, b->stream, g.a);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) { set_error("gather launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    }
+    if (cycles_host) {
+        HIP_TRY(hipMemcpyAsync(cycles_host, b->cycles_dev, sizeof(int32_t) * b->items, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+    }
+    return FM_OK;
+}
+
+int apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles, int32_t* cycles_host) {
+    if (!b || !w || !out) { set_error("null argument"); return FM_EINVAL; }
+    if (!aligned16(w) || !aligned16(out)) { set_error("device buffers must be 16-byte aligned"); return FM_EINVAL; }
+    if (out_mode != FM_JT_PER_SOURCE && out_mode != FM_JT_SUMMED) { set_error("bad out_mode %d", out_mode); return FM_EINVAL; }
+    if (max_cycles < 1) { set_error("max_cycles must be >= 1"); return FM_EINVAL; }
+    int rc = check_device(b);
+    if (rc) return rc;
+    rc = prepare_baseline(b);
+    if (rc) return rc;
+    GsArgs g{};
+    g.a = base_args(b);
+    g.a.in = w;
+    g.a.in_mode = FM_W_NODES;
+    g.a.out = out;
+    g.a.out_mode = out_mode;
+    g.a.work = b->scratch;
+    g.max_cycles = max_cycles;
+    rc = run_gs(b, false, g, nullptr);
+    if (rc) return rc;
+    const void* const* cal = (const void* const*)((char*)b->d_src + sizeof(SrcDev) * b->S);
+    hipError_t e;
+    if (out_mode == FM_JT_SUMMED) {
+        int64_t total = b->N * b->B;
+        int grid = (int)std::min<int64_t>((total + 255) / 256, 16384);
+        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_sum_sources<double>, dim3(grid), dim3(256), 0, b->stream, g.a, cal);
+        else hipLaunchKernelGGL(k_sum_sources<float>, dim3(grid), dim3(256), 0, b->stream, g.a, cal);
+    } else {
+        int64_t total = (int64_t)b->S * b->N * b->B;
+        int grid = (int)std::min<int64_t>((total + 255) / 256, 16384);
+        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_scale_per_source<double>, dim3(grid), dim3(256), 0, b->stream, g.a, cal);
+        else hipLaunchKernelGGL(k_scale_per_source<float>, dim3(grid), dim3(256), 0, b->stream, g.a, cal);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) { set_error("output launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    if (cycles_host) {
+        HIP_TRY(hipMemcpyAsync(cycles_host, b->cycles_dev, sizeof(int32_t) * b->items, hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
     }
     return FM_OK;
 }

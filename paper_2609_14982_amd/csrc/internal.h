@@ -108,6 +108,10 @@ namespace fm {
 int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 const int64_t* rcv, int32_t n_rcv, fm_state** out);
 
+// Natural-order records of the full operator (W for fwd, W^T otherwise) in
+// the packed record format, for the directional-sweeping comparison baseline.
+void pack_natural(const HostState* st, bool fwd, std::vector<uint64_t>& meta, std::vector<double>& rec);
+
 // Device side (device.hip).
 int upload_state(HostState* st);
 void free_device_state(HostState* st);

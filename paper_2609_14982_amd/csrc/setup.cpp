@@ -599,4 +599,35 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
     return FM_OK;
 }
 
+void pack_natural(const HostState* st, bool fwd, std::vector<uint64_t>& meta, std::vector<double>& rec) {
+    const int64_t N = st->N;
+    const int nslot = 2 * st->dim;
+    meta.assign(N, 0);
+    rec.assign((size_t)N * 4, 0.0);
+    std::vector<double> ovf;
+    for (int64_t v = 0; v < N; v++) {
+        uint8_t mask = fwd ? st->pmask[v] : st->smask[v];
+        double* r = rec.data() + (size_t)v * 4;
+        r[0] = st->cal[v];
+        int t = 0;
+        int64_t off = 0;
+        for (int slot = 0; slot < nslot; slot++) {
+            if (!(mask & (1u << slot))) continue;
+            int axis = slot >> 1;
+            int64_t u = (slot & 1) ? v + st->stride[axis] : v - st->stride[axis];
+            double w = fwd ? st->w6[(size_t)v * 6 + slot] : st->w6[(size_t)u * 6 + (slot ^ 1)];
+            if (t < 3) {
+                r[1 + t] = w;
+            } else {
+                if (t == 3) off = (int64_t)ovf.size();
+                ovf.push_back(w);
+            }
+            t++;
+        }
+        meta[v] = (uint64_t)v | ((uint64_t)off << kOffShift) | ((uint64_t)mask << kMaskShift);
+    }
+    rec.insert(rec.end(), ovf.begin(), ovf.end());
+    rec.resize(rec.size() + 4, 0.0);
+}
+
 }  // namespace fm

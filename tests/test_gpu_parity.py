@@ -182,3 +182,42 @@ def test_apply_argument_errors(c1):
     with pytest.raises(fm.FmError):
         fm.Batch(states, 3, fm.FM_FP64, tuning={"rhs_per_group": 2})
     batch.free()
+
+
+def _sweep_run(states, B, direction, inp, in_mode, out_mode):
+    dev = torch.device("cuda:0")
+    batch = fm.Batch(states, B, fm.FM_FP64)
+    S, N, R = batch.S, batch.N, batch.R
+    x = torch.from_numpy(np.ascontiguousarray(inp)).to(dev)
+    if direction == "J":
+        out = torch.full((S, N, B) if out_mode == fm.FM_OUT_NODES else (S, R, B), float("nan"),
+                         device=dev, dtype=torch.float64)
+        cyc = batch.apply_J_sweep(x, in_mode, out, out_mode, want_cycles=True)
+    else:
+        out = torch.full((S, N, B) if out_mode == fm.FM_JT_PER_SOURCE else (N, B), float("nan"),
+                         device=dev, dtype=torch.float64)
+        cyc = batch.apply_JT_sweep(x, out, out_mode, want_cycles=True)
+    torch.cuda.synchronize()
+    res = out.cpu().numpy()
+    batch.free()
+    return res, cyc
+
+
+@pytest.mark.parametrize("case", ["c1", "curved"])
+def test_sweeping_baseline_matches_oracle(case, c1, curved):
+    """The comparison baseline (directional Gauss-Seidel, Section 3.6) must
+    reach the same frozen-operator answer as the oracle before any timing
+    comparison means anything."""
+    wl, states, ops = c1 if case == "c1" else curved
+    B = 2
+    print(f"case sweeping baseline {case} B={B}", flush=True)
+    ds = seeded_ds(wl, B, 71)
+    x, cyc = _sweep_run(states, B, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES)
+    assert np.all(cyc > 0), cyc
+    ref = oracle_J(ops, ds, True)
+    assert rel_l2_pairs(x, ref) <= TOL64
+    w = np.random.default_rng(72).standard_normal((wl.S, wl.N, B))
+    g, cyc2 = _sweep_run(states, B, "JT", w, fm.FM_W_NODES, fm.FM_JT_PER_SOURCE)
+    assert np.all(cyc2 > 0), cyc2
+    gref = oracle_JT(ops, w)
+    assert rel_l2_pairs(g, gref) <= TOL64
