@@ -202,6 +202,35 @@ int fm_apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, in
 int fm_apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles,
                       int32_t* cycles);
 
+/*
+ * LSQR over the paired actions: the Krylov least-squares inner loop of
+ * Algorithm 1 (line 20; Section 4.5), which applies J and J^T once per
+ * iteration at the same frozen state.  It solves min ||J x - d||_2 for each
+ * of the B columns independently: x is a model block [N][B] shared by all
+ * sources (FM_DS_BROADCAST), d is stacked receiver data [S][R][B], J^T sums
+ * over the sources.  All vectors and per-column scalars live on the device;
+ * create allocates them once, the other calls only enqueue kernels on the
+ * batch stream (no allocation, no synchronisation, no memset), so
+ * fm_lsqr_capture can record n iterations as one HIP graph that
+ * fm_lsqr_replay launches again and again.  Free the plan before its batch.
+ *   fm_lsqr_start    beta u = d, alpha v = J^T u, w = v, x = 0 (d: device [S][R][B])
+ *   fm_lsqr_iterate  enqueue n iterations
+ *   fm_lsqr_capture  record n iterations into a graph (needs a non-null stream)
+ *   fm_lsqr_replay   launch the recorded graph
+ *   fm_lsqr_buffers  device pointers of x [N][B], u [S][R][B], v [N][B] and the
+ *                    scalars [8][B] (alpha, beta, rhobar, phibar, rho, phi, theta, 1/norm);
+ *                    |phibar| is the current residual norm of each column
+ * Errors: FM_EINVAL, FM_ENOMEM, FM_EHIP, FM_ESTATE.
+ */
+typedef struct fm_lsqr fm_lsqr;
+int fm_lsqr_create(fm_batch* b, fm_lsqr** out);
+int fm_lsqr_start(fm_lsqr* L, const void* d);
+int fm_lsqr_iterate(fm_lsqr* L, int32_t n);
+int fm_lsqr_capture(fm_lsqr* L, int32_t n);
+int fm_lsqr_replay(fm_lsqr* L);
+int fm_lsqr_buffers(const fm_lsqr* L, void** x, void** u, void** v, double** scalars);
+void fm_lsqr_free(fm_lsqr* L);
+
 /* Free a batch (its scratch); the states stay valid. */
 void fm_batch_free(fm_batch* b);
 

@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     FM_W_RECEIVERS,
     Batch,
     FmError,
+    Lsqr,
     State,
     build_frozen_state,
     build_frozen_states,

@@ -24,6 +24,8 @@ SYMBOLS = (
     "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
     "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_apply_J",
     "fm_apply_JT", "fm_apply_J_sweep", "fm_apply_JT_sweep", "fm_batch_free", "fm_last_error",
+    "fm_lsqr_create", "fm_lsqr_start", "fm_lsqr_iterate", "fm_lsqr_capture", "fm_lsqr_replay",
+    "fm_lsqr_buffers", "fm_lsqr_free",
 )
 
 
@@ -82,6 +84,13 @@ def load():
         "fm_apply_J_sweep": (C.c_int, [vp, vp, i32, vp, i32, i32, vp]),
         "fm_apply_JT_sweep": (C.c_int, [vp, vp, vp, i32, i32, vp]),
         "fm_batch_free": (None, [vp]),
+        "fm_lsqr_create": (C.c_int, [vp, vp]),
+        "fm_lsqr_start": (C.c_int, [vp, vp]),
+        "fm_lsqr_iterate": (C.c_int, [vp, i32]),
+        "fm_lsqr_capture": (C.c_int, [vp, i32]),
+        "fm_lsqr_replay": (C.c_int, [vp]),
+        "fm_lsqr_buffers": (C.c_int, [vp, vp, vp, vp, vp]),
+        "fm_lsqr_free": (None, [vp]),
         "fm_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -305,3 +314,64 @@ class Batch:
             self.free()
         except Exception:
             pass
+
+
+class Lsqr:
+    """fm_lsqr*: LSQR over the paired actions of a batch (device-resident)."""
+
+    def __init__(self, batch: Batch):
+        self.batch = batch
+        out = C.c_void_p()
+        _check(load().fm_lsqr_create(batch._ptr, C.byref(out)))
+        self._ptr = out
+        ptrs = [C.c_void_p() for _ in range(4)]
+        _check(load().fm_lsqr_buffers(self._ptr, *[C.byref(p) for p in ptrs]))
+        self._x, self._u, self._v, self._scal = (p.value for p in ptrs)
+
+    def start(self, d):
+        b = self.batch
+        _check(load().fm_lsqr_start(self._ptr, _dptr(d, b.dtype, (b.S, b.R, b.B), "d")))
+
+    def iterate(self, n):
+        _check(load().fm_lsqr_iterate(self._ptr, int(n)))
+
+    def capture(self, n):
+        _check(load().fm_lsqr_capture(self._ptr, int(n)))
+
+    def replay(self):
+        _check(load().fm_lsqr_replay(self._ptr))
+
+    def x(self):
+        """A device copy of the current solution [N][B]."""
+        return _device_copy(self._x, (self.batch.N, self.batch.B), self.batch.dtype)
+
+    def scalars(self):
+        """Per-column scalars [8][B]: alpha, beta, rhobar, phibar, rho, phi, theta, 1/norm."""
+        import torch
+        return _device_copy(self._scal, (8, self.batch.B), torch.float64)
+
+    def free(self):
+        if getattr(self, "_ptr", None) is not None and self._ptr.value:
+            load().fm_lsqr_free(self._ptr)
+            self._ptr = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _device_copy(ptr, shape, dtype):
+    """Copy a library-owned device buffer into a new torch tensor."""
+    import torch
+    out = torch.empty(shape, dtype=dtype, device="cuda")
+    nbytes = out.numel() * out.element_size()
+    torch.cuda.synchronize()
+    hip = C.CDLL("libamdhip64.so")
+    hip.hipMemcpy.restype = C.c_int
+    hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    rc = hip.hipMemcpy(C.c_void_p(out.data_ptr()), C.c_void_p(ptr), nbytes, 3)   # device to device
+    if rc != 0:
+        raise FmError(FM_EHIP, f"hipMemcpy failed: {rc}")
+    return out

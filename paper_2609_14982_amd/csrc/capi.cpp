@@ -33,6 +33,13 @@ int batch_tuning(const fm_batch* b, fm_tuning* out);
 int apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode, int32_t max_cycles,
                   int32_t* cycles_host);
 int apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles, int32_t* cycles_host);
+int lsqr_create(fm_batch* b, fm_lsqr** out);
+int lsqr_start_any(fm_lsqr* L, const void* d);
+int lsqr_iterate_any(fm_lsqr* L, int32_t n);
+int lsqr_capture(fm_lsqr* L, int32_t n);
+int lsqr_replay(fm_lsqr* L);
+int lsqr_buffers(const fm_lsqr* L, void** x, void** u, void** v, double** scal);
+void lsqr_free(fm_lsqr* L);
 
 }  // namespace fm
 
@@ -175,6 +182,38 @@ int fm_apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, i
     fm::clear_error();
     return fm::apply_JT_sweep(b, w, out, out_mode, max_cycles, cycles);
 }
+
+int fm_lsqr_create(fm_batch* b, fm_lsqr** out) {
+    fm::clear_error();
+    return fm::lsqr_create(b, out);
+}
+
+int fm_lsqr_start(fm_lsqr* L, const void* d) {
+    fm::clear_error();
+    return fm::lsqr_start_any(L, d);
+}
+
+int fm_lsqr_iterate(fm_lsqr* L, int32_t n) {
+    fm::clear_error();
+    return fm::lsqr_iterate_any(L, n);
+}
+
+int fm_lsqr_capture(fm_lsqr* L, int32_t n) {
+    fm::clear_error();
+    return fm::lsqr_capture(L, n);
+}
+
+int fm_lsqr_replay(fm_lsqr* L) {
+    fm::clear_error();
+    return fm::lsqr_replay(L);
+}
+
+int fm_lsqr_buffers(const fm_lsqr* L, void** x, void** u, void** v, double** scalars) {
+    fm::clear_error();
+    return fm::lsqr_buffers(L, x, u, v, scalars);
+}
+
+void fm_lsqr_free(fm_lsqr* L) { fm::lsqr_free(L); }
 
 void fm_batch_free(fm_batch* b) { fm::batch_free(b); }
 

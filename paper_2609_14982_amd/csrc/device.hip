@@ -24,79 +24,9 @@
 #include <cstring>
 #include <vector>
 
-#include "internal.h"
+#include "batch.h"
 
 namespace fm {
-
-struct SrcDev {
-    const uint64_t* fmeta;
-    const void* fwts;
-    const int32_t* flvl_ptr;
-    const int32_t* flvl_nsc;
-    const int32_t* fblk_ptr;
-    const int32_t* fblk_id;
-    const uint64_t* rmeta;
-    const void* rwts;
-    const int32_t* rlvl_ptr;
-    const int32_t* rlvl_nsc;
-    const int32_t* rblk_ptr;
-    const int32_t* rblk_id;
-    const int32_t* blk_k;
-    const int32_t* blk_fpos;
-    const int32_t* blk_rpos;
-    const int64_t* blk_inv;
-    const double* inv;
-    const double* invt;
-    const void* cal_nat;
-    const int32_t* rcv_node;
-    const int32_t* rcvlvl_ptr;
-    const int32_t* rcv_pos;
-    const int32_t* rcv_idx;
-    int32_t L_f, L_r, n_rcv, pad;
-};
-
-struct DeviceState {
-    void* blob_nat = nullptr;    // natural-order records for the sweeping baseline
-    void* blob_nat32 = nullptr;
-    const void* nat[4] = {nullptr, nullptr, nullptr, nullptr};     // fmeta, frec, rmeta, rrec
-    const void* nat32[2] = {nullptr, nullptr};                     // frec, rrec in FP32
-    void* blob = nullptr;        // all FP64 arrays and integer tables
-    void* blob32 = nullptr;      // FP32 copies of the records and calibration
-    SrcDev d{};                  // pointers into blob (FP64 records)
-    const void* fwts32 = nullptr;
-    const void* rwts32 = nullptr;
-    const void* cal32 = nullptr;
-    int device = -1;
-};
-
-}  // namespace fm
-
-struct fm_batch {
-    std::vector<fm::HostState*> states;
-    int32_t S = 0, B = 0, prec = 64, R = 0;
-    fm_tuning tun{};
-    hipStream_t stream = nullptr;
-    fm::SrcDev* d_src = nullptr;     // [S]
-    void* scratch = nullptr;         // [S][N][B] of the batch precision
-    int64_t N = 0;
-    int64_t st1 = 1, st2 = 1;
-    int device = -1;
-    size_t lds_bytes = 0;
-    int32_t grid = 0, per_xcd = 0, items = 0;
-    void* nat_dev = nullptr;         // [S] NatDev, created by the first sweeping-baseline call
-    int32_t* cycles_dev = nullptr;   // [items]
-};
-
-namespace fm {
-
-#define HIP_TRY(expr)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess) {                                                          \
-            set_error("%s failed: %s", #expr, hipGetErrorString(e_));                    \
-            return FM_EHIP;                                                              \
-        }                                                                                \
-    } while (0)
 
 // ---------------------------------------------------------------------------
 // upload
@@ -271,18 +201,6 @@ void free_device_state(HostState* st) {
 // kernels
 // ---------------------------------------------------------------------------
 
-struct ApplyArgs {
-    const SrcDev* src;
-    int32_t S, B, ngroups, items, per_xcd, xcd_aware;
-    int64_t N;
-    int64_t st1, st2;       // node strides of logical axes 1 and 2
-    int32_t R;              // receivers per source (receiver layouts)
-    int32_t in_mode, out_mode;
-    const void* in;         // J: ds ; J^T: w
-    void* out;              // J: nodes output (or unused) ; J^T: per-source output
-    void* work;             // J: X (out or scratch) ; J^T: lambda scratch
-};
-
 }  // namespace fm
 
 #include "sweep.h"
@@ -332,9 +250,18 @@ constexpr int lane_width() {
 template <int DIR, typename V, int RG, int NT, int U>
 static hipError_t launch_one(const ApplyArgs& a, int grid, size_t lds, hipStream_t s) {
     constexpr int VW = lane_width<V, RG>();
-    const void* fn = (const void*)k_sweep<DIR, V, RG, VW, NT, U>;
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // raise the dynamic-LDS limit once per kernel and device, outside any
+    // stream capture that later launches may be part of
+    static int attr_device = -1;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
+    if (attr_device != dev) {
+        e = hipFuncSetAttribute((const void*)k_sweep<DIR, V, RG, VW, NT, U>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_device = dev;
+    }
     hipLaunchKernelGGL((k_sweep<DIR, V, RG, VW, NT, U>), dim3(grid), dim3(NT), lds, s, a);
     return hipGetLastError();
 }
@@ -493,7 +420,15 @@ void batch_free(fm_batch* b) {
     delete b;
 }
 
-static ApplyArgs base_args(const fm_batch* b) {
+ApplyArgs batch_args(const fm_batch* b);
+
+static ApplyArgs base_args(const fm_batch* b) { return batch_args(b); }
+
+const void* const* batch_calibration(const fm_batch* b) {
+    return (const void* const*)((const char*)b->d_src + sizeof(SrcDev) * b->S);
+}
+
+ApplyArgs batch_args(const fm_batch* b) {
     ApplyArgs a{};
     a.src = b->d_src;
     a.S = b->S;
