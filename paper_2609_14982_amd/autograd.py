@@ -1,0 +1,128 @@
+"""Differentiation wrapper and Gauss-Newton step over the frozen transport.
+
+ReceiverTraveltime is a torch.autograd.Function for the map
+    s (nodal slowness [N])  ->  receiver traveltimes [S][R]
+whose forward pass runs a caller-supplied nonlinear first-arrival solver
+(s -> T[S][N], the state of Section 2.1) and builds the frozen states
+(Algorithm 1, Phase I), and whose backward pass applies the source-summed
+transpose J^T = sum_alpha C_alpha A_alpha^{-T} P_alpha^T (Section 4.4) on the
+GPU.  The tangent is the frozen face-upwind transport with the calibrated
+right-hand side (Section 3.2); it is the derivative of the continuous state
+equation, not of the particular nonlinear solver, so finite differences of
+the solver agree with it to discretisation accuracy (exactly along the
+uniform scaling direction ds = s, where both give T).
+
+gauss_newton_step computes the Gauss-Newton increment of the data misfit
+0.5 ||P T(s) - d||^2 by CGLS on J (Algorithm 1, lines 15-20, with CGLS in
+place of LSMR and no regularisation).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .binding import (FM_DS_BROADCAST, FM_FP64, FM_JT_SUMMED, FM_OUT_RECEIVERS, FM_W_RECEIVERS, Batch,
+                      build_frozen_states)
+
+
+class TransportProblem:
+    """Grid, metric, sources, receivers and the nonlinear solver s -> T[S][N]."""
+
+    def __init__(self, dim, n1, n2, n3, G, src, rcv, solver, nthreads=None):
+        self.dim, self.n1, self.n2, self.n3 = dim, n1, n2, n3
+        self.G = np.ascontiguousarray(G, dtype=np.float64)
+        self.src = np.asarray(src, dtype=np.int64)
+        self.rcv = np.asarray(rcv, dtype=np.int64)
+        self.solver = solver
+        self.nthreads = nthreads
+        self.N = n1 * n2 * n3
+        self.S = int(self.src.shape[0])
+        self.R = int(self.rcv.shape[0])
+
+    def linearize(self, s: np.ndarray, B: int = 1, stream=None):
+        """Nonlinear solve at s and Phase I setup: returns (T [S][N], batch)."""
+        s = np.ascontiguousarray(s, dtype=np.float64)
+        T = np.ascontiguousarray(self.solver(s), dtype=np.float64)
+        states = build_frozen_states(self.dim, self.n1, self.n2, self.n3, self.G, T, s, self.src,
+                                     self.rcv, nthreads=self.nthreads)
+        return T, Batch(states, B, FM_FP64, stream=stream)
+
+
+class ReceiverTraveltime(torch.autograd.Function):
+    """s [N] -> P T(s) [S][R]; backward = J^T (source-summed) on the GPU."""
+
+    @staticmethod
+    def forward(ctx, s, problem: TransportProblem):
+        T, batch = problem.linearize(s.detach().double().cpu().numpy())
+        ctx.batch = batch
+        ctx.problem = problem
+        ctx.s_device = s.device
+        ctx.s_dtype = s.dtype
+        return torch.from_numpy(np.ascontiguousarray(T[:, problem.rcv])).to(device=s.device, dtype=s.dtype)
+
+    @staticmethod
+    def backward(ctx, grad):
+        problem, batch = ctx.problem, ctx.batch
+        dev = torch.device("cuda")
+        g = grad.detach().to(device=dev, dtype=torch.float64).reshape(problem.S, problem.R, 1).contiguous()
+        out = torch.empty((problem.N, 1), device=dev, dtype=torch.float64)
+        batch.apply_JT(g, FM_W_RECEIVERS, out, FM_JT_SUMMED)
+        return out.reshape(problem.N).to(device=ctx.s_device, dtype=ctx.s_dtype), None
+
+
+def receiver_traveltime(s: torch.Tensor, problem: TransportProblem) -> torch.Tensor:
+    return ReceiverTraveltime.apply(s, problem)
+
+
+def apply_J_receivers(batch: Batch, p: torch.Tensor) -> torch.Tensor:
+    """J p for a model block p [N][B] -> [S][R][B]."""
+    out = torch.empty((batch.S, batch.R, batch.B), device=p.device, dtype=p.dtype)
+    batch.apply_J(p.contiguous(), FM_DS_BROADCAST, out, FM_OUT_RECEIVERS)
+    return out
+
+
+def apply_JT_summed(batch: Batch, y: torch.Tensor) -> torch.Tensor:
+    """J^T y for receiver data y [S][R][B] -> [N][B]."""
+    out = torch.empty((batch.N, batch.B), device=y.device, dtype=y.dtype)
+    batch.apply_JT(y.contiguous(), FM_W_RECEIVERS, out, FM_JT_SUMMED)
+    return out
+
+
+def cgls(batch: Batch, r: torch.Tensor, n_iter: int):
+    """CGLS for min ||J x - r|| per column: r [S][R][B] -> (x [N][B], residual norms per iteration)."""
+    B = batch.B
+    x = torch.zeros((batch.N, B), device=r.device, dtype=r.dtype)
+    res = r.clone()
+    s = apply_JT_summed(batch, res)
+    p = s.clone()
+    gamma = (s * s).sum(dim=0)
+    norms = [torch.linalg.vector_norm(res.reshape(-1, B), dim=0)]
+    for _ in range(n_iter):
+        q = apply_J_receivers(batch, p)
+        qq = (q * q).reshape(-1, B).sum(dim=0)
+        alpha = torch.where(qq > 0, gamma / torch.where(qq > 0, qq, torch.ones_like(qq)), torch.zeros_like(qq))
+        x += alpha * p
+        res -= alpha * q
+        s = apply_JT_summed(batch, res)
+        gnew = (s * s).sum(dim=0)
+        beta = torch.where(gamma > 0, gnew / torch.where(gamma > 0, gamma, torch.ones_like(gamma)),
+                           torch.zeros_like(gamma))
+        p = s + beta * p
+        gamma = gnew
+        norms.append(torch.linalg.vector_norm(res.reshape(-1, B), dim=0))
+    return x, torch.stack(norms)
+
+
+def gauss_newton_step(problem: TransportProblem, s: np.ndarray, d_obs: np.ndarray, n_iter: int = 30):
+    """One matrix-free Gauss-Newton increment ds for 0.5 ||P T(s) - d_obs||^2:
+    linearise at s, then CGLS on J ds = d_obs - P T(s).  Returns (ds, misfit
+    before, CGLS residual norms)."""
+    dev = torch.device("cuda")
+    T, batch = problem.linearize(s)
+    r = d_obs - T[:, problem.rcv]
+    rt = torch.from_numpy(np.ascontiguousarray(r)[:, :, None]).to(dev)
+    ds, norms = cgls(batch, rt, n_iter)
+    torch.cuda.synchronize()
+    out = ds[:, 0].cpu().numpy()
+    batch.free()
+    return out, 0.5 * float(np.sum(r * r)), norms[:, 0].cpu().numpy()

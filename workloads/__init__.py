@@ -19,6 +19,8 @@ from .grids import (  # noqa: F401
     metric_from_coords,
     mu_g,
     smooth_noise,
+    small_3d,
+    traveltime_solver,
     data_noise,
     CONFIG_NAMES,
 )

@@ -160,6 +160,18 @@ def eikonal(wl: Workload, init_radius: int = 2, nthreads: int | None = None) -> 
     return T
 
 
+def traveltime_solver(wl: Workload, init_radius: int = 2, nthreads: int | None = None):
+    """A callable s -> T[S][N]: the first-arrival generator for this grid,
+    sources and a given slowness field."""
+    import copy
+
+    def solve(s):
+        w2 = copy.copy(wl)
+        w2.s = np.ascontiguousarray(s, dtype=np.float64)
+        return eikonal(w2, init_radius=init_radius, nthreads=nthreads)
+    return solve
+
+
 # --------------------------------------------------------------------------
 # seeded vectors
 # --------------------------------------------------------------------------
