@@ -95,7 +95,11 @@ typedef struct fm_tuning {
     int32_t threads;        /* workgroup size: 256, 512 or 1024 */
     int32_t min_lds_bytes;  /* LDS reserved per workgroup (limits workgroups per CU) */
     int32_t xcd_aware;      /* 1 or 0 (default): keep the groups of one source on one XCD; -1: off */
-    int32_t unroll;         /* nodes per thread in flight inside a level: 1, 2 or 4 */
+    int32_t unroll;         /* nodes per thread in flight inside a level: 1, 2 or 4 (rhs groups);
+                               2, 3, 4 (split, 4 lanes per node) or 2, 4, 6 (split, 8 lanes) */
+    int32_t split;          /* workgroups sharing one source and all B rhs (node split):
+                               0 = choose (the rhs-group kernel when no split fits),
+                               1 = off (rhs groups), 2, 4, 8, 16 = that many */
 } fm_tuning;
 
 /*
@@ -162,6 +166,28 @@ int fm_batch_set_stream(fm_batch* b, void* hip_stream);
 
 /* The schedule the batch resolved (defaults filled in). */
 int fm_batch_tuning(const fm_batch* b, fm_tuning* out);
+
+/*
+ * Wait for the batch stream and report whether the applies enqueued since
+ * the last call completed normally.  With the node split (fm_tuning.split >
+ * 1) the workgroups of one source wait on each other at every level; each
+ * wait gives up after about 10 s without progress (possible only when the
+ * launch cannot keep all its workgroups resident, e.g. beside other work
+ * that holds the device), and the launch then runs to its end with invalid
+ * outputs.  That case returns FM_EHIP (and clears the flag).
+ * Errors: FM_EINVAL, FM_ESTATE, FM_EHIP.
+ */
+int fm_batch_status(fm_batch* b);
+
+/*
+ * Diagnostic of the node split: waits for the batch stream, then writes for
+ * every source (host xcd_masks [S]) the set of XCDs (bit i = XCD i) its
+ * workgroups ran on in the last apply.  One bit per source means the
+ * workgroups exchanged values through one L2 (the fast path); more bits mean
+ * that launch used device-scope fences at every level.
+ * Errors: FM_EINVAL (no node split), FM_ESTATE, FM_EHIP.
+ */
+int fm_batch_split_info(fm_batch* b, int32_t* xcd_masks);
 
 /*
  * Primal action dT = J ds for every (source, rhs) pair (Algorithm 1, lines

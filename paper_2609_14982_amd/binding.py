@@ -22,7 +22,8 @@ _ERRNAMES = {FM_EINVAL: "FM_EINVAL", FM_ESINGULAR: "FM_ESINGULAR", FM_ENOMEM: "F
 SYMBOLS = (
     "fm_build_frozen_state", "fm_build_frozen_states", "fm_state_stats",
     "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
-    "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_apply_J",
+    "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_batch_status", "fm_batch_split_info",
+    "fm_apply_J",
     "fm_apply_JT", "fm_apply_J_sweep", "fm_apply_JT_sweep", "fm_batch_free", "fm_last_error",
     "fm_lsqr_create", "fm_lsqr_start", "fm_lsqr_iterate", "fm_lsqr_capture", "fm_lsqr_replay",
     "fm_lsqr_buffers", "fm_lsqr_free",
@@ -50,7 +51,8 @@ class fm_stats(C.Structure):
 
 class fm_tuning(C.Structure):
     _fields_ = [("rhs_per_group", C.c_int32), ("threads", C.c_int32),
-                ("min_lds_bytes", C.c_int32), ("xcd_aware", C.c_int32), ("unroll", C.c_int32)]
+                ("min_lds_bytes", C.c_int32), ("xcd_aware", C.c_int32), ("unroll", C.c_int32),
+                ("split", C.c_int32)]
 
 
 _lib = None
@@ -79,6 +81,8 @@ def load():
         "fm_batch_create": (C.c_int, [vp, i32, i32, i32, vp, vp, vp]),
         "fm_batch_set_stream": (C.c_int, [vp, vp]),
         "fm_batch_tuning": (C.c_int, [vp, vp]),
+        "fm_batch_status": (C.c_int, [vp]),
+        "fm_batch_split_info": (C.c_int, [vp, vp]),
         "fm_apply_J": (C.c_int, [vp, vp, i32, vp, i32]),
         "fm_apply_JT": (C.c_int, [vp, vp, i32, vp, i32]),
         "fm_apply_J_sweep": (C.c_int, [vp, vp, i32, vp, i32, i32, vp]),
@@ -259,6 +263,16 @@ class Batch:
         t = fm_tuning()
         _check(load().fm_batch_tuning(self._ptr, C.byref(t)))
         return {k: getattr(t, k) for k, _ in fm_tuning._fields_}
+
+    def status(self):
+        """Synchronise the batch stream; raises FmError if a node-split wait timed out."""
+        _check(load().fm_batch_status(self._ptr))
+
+    def split_info(self):
+        """XCD bit mask per source of the last node-split apply."""
+        m = np.zeros(self.S, dtype=np.int32)
+        _check(load().fm_batch_split_info(self._ptr, m.ctypes.data))
+        return m
 
     def set_stream(self, stream):
         _check(load().fm_batch_set_stream(self._ptr, C.c_void_p(stream.cuda_stream)))

@@ -26,6 +26,7 @@ struct SrcDev {
     const int32_t* blk_fpos;
     const int32_t* blk_rpos;
     const int64_t* blk_inv;
+    const int64_t* blk_moff;    // first staging row of each block (prefix sum of k)
     const double* inv;
     const double* invt;
     const void* cal_nat;
@@ -66,6 +67,12 @@ struct fm_batch {
     int32_t grid = 0, per_xcd = 0, items = 0;
     void* nat_dev = nullptr;         // [S] NatDev, created by the first sweeping-baseline call
     int32_t* cycles_dev = nullptr;   // [items]
+    // node split (tun.split > 1)
+    int32_t split_grid = 0, split_per_xcd = 0, split_items = 0, split_lds_rows = 0;
+    size_t split_lds = 0;
+    int64_t stage_rows = 0;
+    void* stage = nullptr;           // [S][stage_rows][B] FP64 block right-hand sides
+    unsigned* sync = nullptr;        // counters [S*32], XCD masks [S*32], abort word
 };
 
 namespace fm {

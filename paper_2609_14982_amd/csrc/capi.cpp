@@ -30,6 +30,8 @@ int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out
 int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode);
 int batch_set_stream(fm_batch* b, void* stream);
 int batch_tuning(const fm_batch* b, fm_tuning* out);
+int batch_status(fm_batch* b);
+int batch_split_info(fm_batch* b, int32_t* xcd_masks);
 int apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode, int32_t max_cycles,
                   int32_t* cycles_host);
 int apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles, int32_t* cycles_host);
@@ -159,6 +161,16 @@ int fm_batch_set_stream(fm_batch* b, void* hip_stream) {
 int fm_batch_tuning(const fm_batch* b, fm_tuning* out) {
     fm::clear_error();
     return fm::batch_tuning(b, out);
+}
+
+int fm_batch_status(fm_batch* b) {
+    fm::clear_error();
+    return fm::batch_status(b);
+}
+
+int fm_batch_split_info(fm_batch* b, int32_t* xcd_masks) {
+    fm::clear_error();
+    return fm::batch_split_info(b, xcd_masks);
 }
 
 int fm_apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode) {

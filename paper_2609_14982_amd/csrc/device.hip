@@ -83,6 +83,12 @@ int upload_state(HostState* st) {
     size_t o_bfp = ar.add<int32_t>(pk.blk_fpos.size());
     size_t o_brp = ar.add<int32_t>(pk.blk_rpos.size());
     size_t o_binv = ar.add<int64_t>(pk.blk_inv.size());
+    std::vector<int64_t> moff(pk.blk_k.size());
+    {
+        int64_t acc = 0;
+        for (size_t i = 0; i < pk.blk_k.size(); i++) { moff[i] = acc; acc += pk.blk_k[i]; }
+    }
+    size_t o_moff = ar.add<int64_t>(moff.size());
     size_t o_inv = ar.add<double>(pk.inv.size());
     size_t o_invt = ar.add<double>(pk.invt.size());
     size_t o_cal = ar.add<double>(pk.cal_nat.size());
@@ -116,6 +122,7 @@ int upload_state(HostState* st) {
     rc = rc ? rc : put(b, o_bfp, pk.blk_fpos);
     rc = rc ? rc : put(b, o_brp, pk.blk_rpos);
     rc = rc ? rc : put(b, o_binv, pk.blk_inv);
+    rc = rc ? rc : put(b, o_moff, moff);
     rc = rc ? rc : put(b, o_inv, pk.inv);
     rc = rc ? rc : put(b, o_invt, pk.invt);
     rc = rc ? rc : put(b, o_cal, pk.cal_nat);
@@ -145,6 +152,7 @@ int upload_state(HostState* st) {
     d.blk_fpos = (const int32_t*)(b + o_bfp);
     d.blk_rpos = (const int32_t*)(b + o_brp);
     d.blk_inv = (const int64_t*)(b + o_binv);
+    d.blk_moff = (const int64_t*)(b + o_moff);
     d.inv = (const double*)(b + o_inv);
     d.invt = (const double*)(b + o_invt);
     d.cal_nat = b + o_cal;
@@ -204,6 +212,7 @@ void free_device_state(HostState* st) {
 }  // namespace fm
 
 #include "sweep.h"
+#include "split.h"
 #include "baseline.h"
 
 namespace fm {
@@ -222,17 +231,54 @@ __global__ void k_gather_receivers(ApplyArgs a) {
     }
 }
 
-// g[n][b] = sum_alpha c_alpha[n] lambda_alpha[n][b], sources in order (Section 4.4)
+// g[n][b] = sum_alpha c_alpha[n] lambda_alpha[n][b], sources in ascending
+// order (Section 4.4).  A streaming reduction: each thread takes VW
+// consecutive values of one node (one 16-byte access per source) and keeps
+// the accesses of SU sources in flight.
 template <typename V>
 __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
+    constexpr int VW = 16 / (int)sizeof(V);
+    constexpr int SU = 8;
     const int64_t NB = a.N * a.B;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NB;
-         t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t node = t / a.B;
-        V acc = (V)0;
-        for (int alpha = 0; alpha < a.S; ++alpha)
-            acc += ((const V*)cal[alpha])[node] * ((const V*)a.work)[alpha * NB + t];
-        ((V*)a.out)[t] = acc;
+    const V* __restrict__ work = (const V*)a.work;
+    V* __restrict__ out = (V*)a.out;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (a.B % VW == 0) {
+        for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NB / VW; t += stride) {
+            const int64_t e0 = t * VW;
+            const int64_t node = e0 / a.B;
+            V acc[VW];
+#pragma unroll
+            for (int v = 0; v < VW; ++v) acc[v] = (V)0;
+            for (int a0 = 0; a0 < a.S; a0 += SU) {
+                Pack<V, VW> x[SU];
+                V c[SU];
+#pragma unroll
+                for (int u = 0; u < SU; ++u) {
+                    if (a0 + u < a.S) {
+                        x[u] = ld<V, VW>(work + (int64_t)(a0 + u) * NB + e0);
+                        c[u] = ((const V*)cal[a0 + u])[node];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < SU; ++u)
+                    if (a0 + u < a.S) {
+#pragma unroll
+                        for (int v = 0; v < VW; ++v) acc[v] += c[u] * x[u].v[v];
+                    }
+            }
+            Pack<V, VW> o;
+#pragma unroll
+            for (int v = 0; v < VW; ++v) o.v[v] = acc[v];
+            st<V, VW>(out + e0, o);
+        }
+    } else {
+        for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NB; t += stride) {
+            const int64_t node = t / a.B;
+            V acc = (V)0;
+            for (int alpha = 0; alpha < a.S; ++alpha) acc += ((const V*)cal[alpha])[node] * work[alpha * NB + t];
+            out[t] = acc;
+        }
     }
 }
 
@@ -308,6 +354,162 @@ static hipError_t launch_sweep(bool fwd, const fm_tuning& t, const ApplyArgs& a,
 }
 
 static constexpr size_t kLdsMax = 160 * 1024;
+template <int DIR, typename V, int LPN, int NT, int U>
+static const void* split_fn() {
+    return (const void*)k_split<DIR, V, LPN, NT, U>;
+}
+
+// The node-split kernels that are built (lanes per node, threads, unroll).
+#define FM_SPLIT_SHAPES(X)                                             \
+    X(4, 512, 2) X(4, 512, 3) X(4, 512, 4) X(4, 1024, 2)               \
+    X(8, 512, 2) X(8, 512, 4) X(8, 512, 6) X(8, 1024, 2) X(8, 1024, 3)
+
+static const void* split_kernel(bool fwd, bool fp64, int lpn, int nt, int u) {
+#define FM_SPLIT_PTR(L_, N_, U_)                                                               \
+    if (lpn == L_ && nt == N_ && u == U_) {                                                    \
+        if (fwd) return fp64 ? split_fn<kFwd, double, L_, N_, U_>() : split_fn<kFwd, float, L_, N_, U_>(); \
+        return fp64 ? split_fn<kRev, double, L_, N_, U_>() : split_fn<kRev, float, L_, N_, U_>();          \
+    }
+    FM_SPLIT_SHAPES(FM_SPLIT_PTR)
+#undef FM_SPLIT_PTR
+    return nullptr;
+}
+
+template <int DIR, typename V, int LPN, int NT, int U>
+static hipError_t launch_split_one(const ApplyArgs& a, const SplitArgs& s, int grid, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL((k_split<DIR, V, LPN, NT, U>), dim3(grid), dim3(NT), lds, st, a, s);
+    return hipGetLastError();
+}
+
+template <int DIR, typename V>
+static hipError_t launch_split_dir(int lpn, int nt, int u, const ApplyArgs& a, const SplitArgs& s, int grid,
+                                   size_t lds, hipStream_t st) {
+#define FM_SPLIT_LAUNCH(L_, N_, U_) \
+    if (lpn == L_ && nt == N_ && u == U_) return launch_split_one<DIR, V, L_, N_, U_>(a, s, grid, lds, st);
+    FM_SPLIT_SHAPES(FM_SPLIT_LAUNCH)
+#undef FM_SPLIT_LAUNCH
+    return hipErrorInvalidValue;
+}
+
+static int split_lpn(const fm_batch* b) {
+    const int vw = b->prec == FM_FP64 ? 2 : 4;
+    return b->B / vw;
+}
+
+// Reset the counters, then one node-split sweep; a.work is the X/lambda array.
+static hipError_t launch_split(const fm_batch* b, bool fwd, const ApplyArgs& a0) {
+    ApplyArgs a = a0;
+    a.items = b->split_items;
+    a.per_xcd = b->split_per_xcd;
+    SplitArgs s{};
+    s.ctr = b->sync;
+    s.xmask = b->sync + (size_t)b->S * kCtrStride;
+    s.abort_w = b->sync + (size_t)2 * b->S * kCtrStride;
+    s.stage = b->stage;
+    s.stage_rows = b->stage_rows;
+    s.P = b->tun.split;
+    s.lds_rows = b->split_lds_rows;
+    const size_t vbytes = b->prec == FM_FP64 ? 8 : 4;
+    s.inv_l1 = ((size_t)b->B * vbytes) % 128 != 0 || ((uintptr_t)a.work & 127u) != 0;
+    hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(256), 0, b->stream, s, b->S);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int lpn = split_lpn(b), nt = b->tun.threads, u = b->tun.unroll;
+    if (b->prec == FM_FP64)
+        return fwd ? launch_split_dir<kFwd, double>(lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream)
+                   : launch_split_dir<kRev, double>(lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream);
+    return fwd ? launch_split_dir<kFwd, float>(lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream)
+               : launch_split_dir<kRev, float>(lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream);
+}
+
+// Choose and prepare the node split of a new batch (tun.split resolved in
+// place: 1 when the rhs-group kernel runs).  Every workgroup of the launch
+// must be resident at once, since the workgroups of a source wait on each
+// other: the grid is checked against the occupancy of the kernel.
+static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
+    const bool fp64 = b->prec == FM_FP64;
+    const int vw = fp64 ? 2 : 4;
+    const int lpn = b->B % vw == 0 ? b->B / vw : 0;
+    if (t.split == 1) return FM_OK;
+    // the node split defaults to 512 threads and batches of 256-384 nodes (a
+    // workgroup's share of a typical level in one round trip)
+    const int nt = asked.threads ? asked.threads : 512;
+    const int u = asked.unroll ? asked.unroll : (lpn == 8 ? 4 : 3);
+    const void* kf = split_kernel(true, fp64, lpn, nt, u);
+    const void* kr = split_kernel(false, fp64, lpn, nt, u);
+    const bool built = kf && kr;
+    if (t.split != 0 && t.split != 2 && t.split != 4 && t.split != 8 && t.split != 16) {
+        set_error("split must be 0, 1, 2, 4, 8 or 16");
+        return FM_EINVAL;
+    }
+    // the kernel addresses one source's [N][B] arrays with 32-bit byte offsets
+    const bool fits32 = (uint64_t)b->N * (uint64_t)b->B * (fp64 ? 8u : 4u) < (1ull << 32) &&
+                        (uint64_t)b->N * 4u * (fp64 ? 8u : 4u) < (1ull << 32);
+    if (!built || !fits32) {
+        if (t.split == 0) { t.split = 1; return FM_OK; }
+        if (!fits32) {
+            set_error("node split: one source's vectors (N=%lld x B=%d) exceed 4 GiB", (long long)b->N, b->B);
+            return FM_EINVAL;
+        }
+        set_error("no node-split kernel for B=%d in this precision with %d threads and unroll %d (B must be %s; "
+                  "see the built shapes)", b->B, nt, u, fp64 ? "8 or 16" : "16 or 32");
+        return FM_EINVAL;
+    }
+    // the kernel's few bytes of static LDS come out of the same 160 KB
+    const int64_t lds_cap = (int64_t)kLdsMax - 1024;
+    const size_t lds = (size_t)std::min<int64_t>(std::max<int64_t>(t.min_lds_bytes, 16 * 1024), lds_cap);
+    int dev = b->device, cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int occ = 1 << 30;
+    for (const void* k : {kf, kr}) {
+        HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap));
+        int nb = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, nt, lds));
+        occ = std::min(occ, nb);
+    }
+    const int64_t cap = (int64_t)occ * cus;
+    const int64_t per8 = (b->S + 7) / 8;
+    auto fits = [&](int P) { return 8 * per8 * P <= cap; };
+    int P = t.split;
+    if (P == 0) {
+        P = 1;
+        for (int c : {8, 4, 2})
+            if (fits(c)) { P = c; break; }
+        if (P == 1) { t.split = 1; return FM_OK; }
+    } else if (!fits(P)) {
+        set_error("split %d needs %lld resident workgroups; the device holds %lld", P, (long long)(8 * per8 * P),
+                  (long long)cap);
+        return FM_EINVAL;
+    }
+    int64_t rows = 1;
+    for (HostState* st : b->states) {
+        int64_t sum = 0;
+        for (int32_t k : st->pk.blk_k) sum += k;
+        rows = std::max(rows, sum);
+    }
+    t.split = P;
+    t.threads = nt;
+    t.unroll = u;
+    b->split_per_xcd = (int32_t)(per8 * P);
+    b->split_grid = 8 * b->split_per_xcd;
+    b->split_items = b->S * P;
+    b->split_lds = lds;
+    b->split_lds_rows = (int32_t)(lds / ((size_t)b->B * sizeof(double)));
+    b->stage_rows = rows;
+    if (b->split_lds_rows < 1) { set_error("LDS too small for one staged row"); return FM_EINVAL; }
+    const size_t stage = (size_t)b->S * rows * b->B * sizeof(double);
+    const size_t sync = ((size_t)2 * b->S * kCtrStride + 64) * sizeof(unsigned);
+    hipError_t e = hipMalloc(&b->stage, stage);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->sync, sync);
+    if (e == hipSuccess) e = hipMemset(b->sync, 0, sync);
+    if (e != hipSuccess) {
+        set_error("node-split buffers (%zu B) failed: %s", stage + sync, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    return FM_OK;
+}
+
+void batch_free(fm_batch* b);
 
 int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precision, const fm_tuning* tuning,
                  void* stream, fm_batch** out) {
@@ -342,7 +544,7 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     if (rg != 1 && rg != 2 && rg != 4 && rg != 8 && rg != 16) { set_error("rhs_per_group must be 1,2,4,8 or 16"); return FM_EINVAL; }
     if (B % rg != 0) { set_error("B=%d is not a multiple of rhs_per_group=%d", B, rg); return FM_EINVAL; }
     if (t.threads != 256 && t.threads != 512 && t.threads != 1024) { set_error("threads must be 256, 512 or 1024"); return FM_EINVAL; }
-    if (t.unroll != 1 && t.unroll != 2 && t.unroll != 4) { set_error("unroll must be 1, 2 or 4"); return FM_EINVAL; }
+    if (t.unroll < 1 || t.unroll > 6) { set_error("unroll must be 1 to 6"); return FM_EINVAL; }
     size_t need = (size_t)maxk * rg * sizeof(double);
     if (need > kLdsMax) {
         set_error("largest SCC block (%d nodes) needs %zu B of LDS with %d rhs per group; use fewer", maxk, need, rg);
@@ -407,12 +609,23 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
         set_error("batch upload failed: %s", hipGetErrorString(e));
         return FM_EHIP;
     }
+    int rc = prepare_split(b, b->tun, tuning ? *tuning : fm_tuning{});
+    if (rc == FM_OK && b->tun.split == 1 && b->tun.unroll != 1 && b->tun.unroll != 2 && b->tun.unroll != 4) {
+        set_error("the rhs-group kernel takes unroll 1, 2 or 4");
+        rc = FM_EINVAL;
+    }
+    if (rc) {
+        batch_free(b);
+        return rc;
+    }
     *out = b;
     return FM_OK;
 }
 
 void batch_free(fm_batch* b) {
     if (!b) return;
+    if (b->stage) (void)hipFree(b->stage);
+    if (b->sync) (void)hipFree(b->sync);
     if (b->nat_dev) (void)hipFree(b->nat_dev);
     if (b->cycles_dev) (void)hipFree(b->cycles_dev);
     if (b->d_src) (void)hipFree(b->d_src);
@@ -470,8 +683,9 @@ int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out
     a.out_mode = out_mode;
     a.out = out;
     a.work = out_mode == FM_OUT_NODES ? out : b->scratch;
-    hipError_t e = b->prec == FM_FP64 ? launch_sweep<double>(true, b->tun, a, b->grid, b->lds_bytes, b->stream)
-                                      : launch_sweep<float>(true, b->tun, a, b->grid, b->lds_bytes, b->stream);
+    hipError_t e = b->tun.split > 1       ? launch_split(b, true, a)
+                   : b->prec == FM_FP64 ? launch_sweep<double>(true, b->tun, a, b->grid, b->lds_bytes, b->stream)
+                                        : launch_sweep<float>(true, b->tun, a, b->grid, b->lds_bytes, b->stream);
     if (e != hipSuccess) { set_error("forward launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
     if (out_mode == FM_OUT_RECEIVERS) {
         int64_t total = (int64_t)b->S * b->R * b->B;
@@ -498,8 +712,9 @@ int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_
     a.out_mode = out_mode;
     a.out = out;
     a.work = b->scratch;
-    hipError_t e = b->prec == FM_FP64 ? launch_sweep<double>(false, b->tun, a, b->grid, b->lds_bytes, b->stream)
-                                      : launch_sweep<float>(false, b->tun, a, b->grid, b->lds_bytes, b->stream);
+    hipError_t e = b->tun.split > 1       ? launch_split(b, false, a)
+                   : b->prec == FM_FP64 ? launch_sweep<double>(false, b->tun, a, b->grid, b->lds_bytes, b->stream)
+                                        : launch_sweep<float>(false, b->tun, a, b->grid, b->lds_bytes, b->stream);
     if (e != hipSuccess) { set_error("reverse launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
     if (out_mode == FM_JT_SUMMED) {
         int64_t total = b->N * b->B;
@@ -709,6 +924,37 @@ int apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int3
         HIP_TRY(hipMemcpyAsync(cycles_host, b->cycles_dev, sizeof(int32_t) * b->items, hipMemcpyDeviceToHost, b->stream));
         HIP_TRY(hipStreamSynchronize(b->stream));
     }
+    return FM_OK;
+}
+
+int batch_status(fm_batch* b) {
+    if (!b) { set_error("null batch"); return FM_EINVAL; }
+    int rc = check_device(b);
+    if (rc) return rc;
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if (b->sync) {
+        unsigned* w = b->sync + (size_t)2 * b->S * kCtrStride;
+        unsigned v = 0;
+        HIP_TRY(hipMemcpy(&v, w, sizeof(v), hipMemcpyDeviceToHost));
+        if (v) {
+            HIP_TRY(hipMemset(w, 0, sizeof(unsigned)));
+            set_error("a level barrier of a node-split apply timed out; the outputs since the last check are invalid");
+            return FM_EHIP;
+        }
+    }
+    return FM_OK;
+}
+
+int batch_split_info(fm_batch* b, int32_t* xcd_masks) {
+    if (!b || !xcd_masks) { set_error("null argument"); return FM_EINVAL; }
+    int rc = check_device(b);
+    if (rc) return rc;
+    if (!b->sync) { set_error("the batch does not use the node split"); return FM_EINVAL; }
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    std::vector<unsigned> m((size_t)b->S * kCtrStride);
+    HIP_TRY(hipMemcpy(m.data(), b->sync + (size_t)b->S * kCtrStride, m.size() * sizeof(unsigned),
+                      hipMemcpyDeviceToHost));
+    for (int32_t i = 0; i < b->S; i++) xcd_masks[i] = (int32_t)m[(size_t)i * kCtrStride];
     return FM_OK;
 }
 

@@ -1,0 +1,568 @@
+// Node-split level walk: P workgroups share one source and all B right-hand
+// sides.  Included by device.hip only, after sweep.h.
+//
+// Why.  A level step is bound by the number of cache-line requests each CU
+// keeps in flight, not by bytes.  With the rhs-group split every node's
+// 128-byte line of B = 16 FP64 values is requested by B / RG workgroups that
+// each use RG of them; here one workgroup takes a node and all B values, so
+// every line request carries a full line, and the P workgroups of a source
+// take disjoint slices of each level instead.
+//
+// Synchronisation.  Nodes of one level are independent (Section 4.1,
+// Proposition 3), so the P workgroups only meet at the end of a level: each
+// waits for its own stores to complete, one thread adds 1 to the source's
+// arrival counter and polls it until all P have arrived.  The counter is only
+// touched by device-scope atomics, which every XCD sees.  The node values are
+// exchanged through the L2 of the XCD the P workgroups run on (workgroups are
+// dispatched to XCDs round-robin and the P of one source sit P-aligned in one
+// XCD's share of the grid); whether they really share an XCD is checked at
+// the first barrier from the XCC_ID hardware register, and if not, every
+// barrier adds the device-scope release (L2 write-back) and acquire (cache
+// invalidate) so that the result is right either way.  A node's values are
+// written once per launch and read only after the barrier that follows, and
+// with rows of a multiple of 128 bytes no cache line holds two nodes, so no
+// stale line can sit in a CU's L1; shorter rows take the acquire at every
+// barrier.  Every wait is bounded: after ~10 s without progress the wave sets
+// the batch's abort word and all later barriers of the launch return at once,
+// so a launch always ends (fm_batch_status reports the failure).
+//
+// Nontrivial SCC blocks (Section 4.3) take two phases.  Phase 1 computes the
+// block right-hand sides b_C = q_C + sum_ext w x for the members (members
+// split over the P workgroups, like singletons) into a per-source staging
+// area; a barrier; phase 2 splits the block's rows over the P workgroups, each
+// row owned by one thread that accumulates all B right-hand sides while b_C
+// streams through LDS in chunks; a second barrier.
+#pragma once
+
+namespace fm {
+
+struct SplitArgs {
+    unsigned* ctr;      // [S] arrival counters, one per 128-byte line (32 words apart)
+    unsigned* xmask;    // [S] XCDs seen per source, one per 128-byte line
+    unsigned* abort_w;  // one word: set when a barrier wait timed out
+    void* stage;        // [S][stage_rows][B] block right-hand sides
+    int64_t stage_rows;
+    int32_t P;          // workgroups per source
+    int32_t lds_rows;   // rows of b_C per LDS chunk
+    int32_t inv_l1;     // rows are not a multiple of 128 bytes
+};
+
+constexpr int kCtrStride = 32;                 // words between counters
+constexpr uint64_t kBarrierTicks = 1000000000; // 10 s of the 100 MHz realtime clock
+
+struct GroupSync {
+    unsigned* ctr;
+    unsigned* abort_w;
+    unsigned target;
+    bool agent;       // device-scope release/acquire around every barrier
+    bool inv_l1;      // acquire at every barrier
+    bool dead;        // a wait of this launch timed out somewhere
+};
+
+__device__ __forceinline__ unsigned xcc_id() {
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 0xfu;
+}
+
+// All threads of the workgroup call this at the same point.
+__device__ __forceinline__ void group_barrier(GroupSync& g, int P) {
+    __shared__ unsigned s_dead;
+    g.target += (unsigned)P;
+    // this wave's stores have reached the L2 before the arrival is counted
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    if (g.agent) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned dead = g.dead ? 1u : 0u;
+        __hip_atomic_fetch_add(g.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!dead) {
+            const uint64_t t0 = wall_clock64();
+            for (;;) {
+                const unsigned c = __hip_atomic_load(g.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if ((int)(c - g.target) >= 0) break;
+                if (__hip_atomic_load(g.abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { dead = 1u; break; }
+                if (wall_clock64() - t0 > kBarrierTicks) {
+                    __hip_atomic_fetch_or(g.abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    dead = 1u;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        s_dead = dead;
+    }
+    __syncthreads();
+    g.dead = s_dead != 0u;
+    if (g.agent || g.inv_l1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+// [lo, hi) of n items for part p of P (contiguous, sizes differ by <= 1)
+__device__ __forceinline__ void share(int n, int P, int p, int& lo, int& hi) {
+    const int q = n / P, r = n % P;
+    lo = p * q + (p < r ? p : r);
+    hi = lo + q + (p < r ? 1 : 0);
+}
+
+// Phase 1 of the level's blocks: b_C of this workgroup's share of every
+// block's members into the staging rows (LPN lanes per member).
+template <int DIR, typename V, int LPN, int NT>
+__device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
+                                                const V* __restrict__ wts, const V* __restrict__ in,
+                                                const V* __restrict__ X, double* __restrict__ stage, const Ctx& cx,
+                                                int P, int part, int slot0) {
+    constexpr int VW = 16 / (int)sizeof(V);
+    constexpr int SLOTS = NT / LPN;
+    const V* ovf_base = wts + cx.N * 4;
+    for (int bi = d.b0; bi < d.b1; ++bi) {
+        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
+        const int k = sd.blk_k[blk];
+        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
+        const int64_t moff = sd.blk_moff[blk];
+        int lo, hi;
+        share(k, P, part, lo, hi);
+        for (int mi = lo + slot0; mi < hi; mi += SLOTS) {
+            NodeOps<V, VW> p;
+            fetch_static<DIR, V, VW>(p, meta[bp + mi], bp + mi, wts, in, cx, sd, d);
+            Pack<double, VW> o;
+            combine<DIR, V, VW, double>(p, ovf_base, X, cx, o.v);
+            st<double, VW>(stage + (moff + mi) * cx.B + cx.rhs0, o);
+        }
+    }
+}
+
+// Phase 2: rows of this workgroup's share of each block,
+// x_i = sum_j Minv(i, j) b_j (primal, column-major inverse) or
+// y_j = sum_i Minv(i, j) b_i (transpose, row-major copy), in ascending
+// order of the summation index.  A row's B right-hand sides are split over
+// NH threads of RP each (consecutive threads take consecutive rows, so a
+// wave reads a contiguous piece of each matrix column); every thread keeps G
+// matrix entries in flight.
+template <int DIR, typename V, int B, int NT>
+__device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
+                                                  const V* __restrict__ wts, const double* __restrict__ stage,
+                                                  V* __restrict__ X, V* __restrict__ outp, int P, int part,
+                                                  int lds_rows, double* lds) {
+    constexpr int RP = B < 8 ? B : 8;
+    constexpr int NH = B / RP;
+    constexpr int ROWS = NT / NH;
+    constexpr int G = 16;
+    const int h = (int)threadIdx.x / ROWS;
+    const int tr = (int)threadIdx.x % ROWS;
+    for (int bi = d.b0; bi < d.b1; ++bi) {
+        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
+        const int k = sd.blk_k[blk];
+        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
+        const int64_t moff = sd.blk_moff[blk];
+        const double* __restrict__ Mx = DIR == kFwd ? sd.inv + sd.blk_inv[blk] : sd.invt + sd.blk_inv[blk];
+        const double* __restrict__ bsrc = stage + moff * B;
+        int lo, hi;
+        share(k, P, part, lo, hi);
+        // every thread of the workgroup passes the same barriers: the row
+        // loop runs the same number of times in all of them
+        for (int r0 = lo; r0 < hi; r0 += ROWS) {
+            const int i = r0 + tr;
+            const bool own = i < hi;
+            double acc[RP];
+#pragma unroll
+            for (int rr = 0; rr < RP; ++rr) acc[rr] = 0.0;
+            for (int j0 = 0; j0 < k; j0 += lds_rows) {
+                const int jn = min(lds_rows, k - j0);
+                __syncthreads();
+                for (int t = threadIdx.x; t < jn * B; t += NT) lds[t] = bsrc[(int64_t)j0 * B + t];
+                __syncthreads();
+                if (own) {
+                    const double* __restrict__ col = Mx + (size_t)j0 * k + i;
+                    const double* __restrict__ bl = lds + h * RP;
+                    int j = 0;
+                    for (; j + G <= jn; j += G) {
+                        double m[G];
+#pragma unroll
+                        for (int t = 0; t < G; ++t) m[t] = col[(size_t)(j + t) * k];
+#pragma unroll
+                        for (int t = 0; t < G; ++t) {
+                            const double* bj = bl + (j + t) * B;
+#pragma unroll
+                            for (int rr = 0; rr < RP; ++rr) acc[rr] += m[t] * bj[rr];
+                        }
+                    }
+                    for (; j < jn; ++j) {
+                        const double m = col[(size_t)j * k];
+                        const double* bj = bl + j * B;
+#pragma unroll
+                        for (int rr = 0; rr < RP; ++rr) acc[rr] += m * bj[rr];
+                    }
+                }
+            }
+            if (own) {
+                const uint64_t mw = meta[bp + i];
+                const int64_t node = (int64_t)(mw & kNodeMask);
+                const V c = wts[(size_t)(bp + i) * 4];
+                V* dst = X + node * B + h * RP;
+#pragma unroll
+                for (int rr = 0; rr < RP; ++rr) dst[rr] = (V)acc[rr];
+                if (DIR == kRev && outp) {
+                    V* o = outp + node * B + h * RP;
+#pragma unroll
+                    for (int rr = 0; rr < RP; ++rr) o[rr] = c * (V)acc[rr];
+                }
+            }
+        }
+    }
+}
+
+// Streaming loads: records, meta words and inputs are read once per launch,
+// so they are loaded non-temporally and leave the L2 to the node values that
+// later levels read again.
+template <typename V, int VW>
+__device__ __forceinline__ Pack<V, VW> ld_stream(const V* p) {
+    typedef V vec __attribute__((ext_vector_type(VW)));
+    const vec x = __builtin_nontemporal_load(reinterpret_cast<const vec*>(p));
+    Pack<V, VW> r;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) r.v[v] = x[v];
+    return r;
+}
+
+// Record and input of one node (as fetch_static, streaming loads).
+template <int DIR, typename V, int VW>
+__device__ __forceinline__ void fetch_stream(NodeOps<V, VW>& p, uint64_t m, int pos, const V* __restrict__ wts,
+                                             const V* __restrict__ in, const Ctx& cx, const SrcDev& sd,
+                                             const LevelDesc& d) {
+    p.node = (int64_t)(m & kNodeMask);
+    p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
+    p.mask = (uint32_t)(m >> kMaskShift);
+    p.rec = ld_stream<V, 4>(wts + (size_t)pos * 4);
+    if (DIR == kFwd || !cx.rcv_in) {
+        p.inp = ld_stream<V, VW>(in + p.node * cx.B + cx.rhs0);
+    } else {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) p.inp.v[v] = (V)0;
+        if (m & kRcvFlag)
+            for (int e = d.e0; e < d.e1; ++e)
+                if (sd.rcv_pos[e] == pos) {
+                    const Pack<V, VW> y = ld<V, VW>(in + (int64_t)sd.rcv_idx[e] * cx.B + cx.rhs0);
+#pragma unroll
+                    for (int v = 0; v < VW; ++v) p.inp.v[v] += y.v[v];
+                }
+    }
+}
+
+// The first three neighbour values of a node, by set-bit rank (the k-th set
+// mask bit, ascending slot, is the k-th weight of the record).
+template <typename V, int VW>
+__device__ __forceinline__ void load_nbrs(const NodeOps<V, VW>& p, const V* __restrict__ X, const Ctx& cx,
+                                          Pack<V, VW> xv[3]) {
+    uint32_t m = p.mask;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (m != 0u) {
+            const int sl = __builtin_ctz(m);
+            xv[t] = ld<V, VW>(X + (p.node + slot_off(sl, cx.st1, cx.st2)) * cx.B + cx.rhs0);
+        }
+        m &= m - 1u;
+    }
+}
+
+// x_node = c*ds + sum_j w_j x_j (primal) or r + sum_i w_i lambda_i
+// (transpose) in ascending slot order (the order of the rhs-group kernel:
+// same bits); neighbours past the third (rare) are loaded here.
+template <int DIR, typename V, int VW, typename T>
+__device__ __forceinline__ void accumulate(const NodeOps<V, VW>& p, const Pack<V, VW> xv[3],
+                                           const V* __restrict__ ovf_base, const V* __restrict__ X, const Ctx& cx,
+                                           T acc[VW]) {
+    uint32_t m = p.mask;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc[v] = (DIR == kFwd) ? (T)p.rec.v[0] * (T)p.inp.v[v] : (T)p.inp.v[v];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (m != 0u) {
+#pragma unroll
+            for (int v = 0; v < VW; ++v) acc[v] += (T)p.rec.v[1 + t] * (T)xv[t].v[v];
+        }
+        m &= m - 1u;
+    }
+    for (int t = 3; m != 0u; ++t) {
+        const int sl = __builtin_ctz(m);
+        m &= m - 1u;
+        const Pack<V, VW> x = ld<V, VW>(X + (p.node + slot_off(sl, cx.st1, cx.st2)) * cx.B + cx.rhs0);
+        const T w = (T)ovf_base[p.ovf + (t - 3)];
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] += w * (T)x.v[v];
+    }
+}
+
+// Singleton operands with 32-bit byte offsets: every array of one source
+// (a [N][B] vector, the [N][4] records) spans less than 4 GiB, so an access
+// is a uniform base pointer plus one 32-bit lane offset (the "saddr" form of
+// the global loads) and a neighbour's offset is the node's plus a signed
+// axis stride.  This keeps the per-node address arithmetic to a few 32-bit
+// instructions.
+template <typename V, int VW>
+struct Node32 {
+    uint32_t row;    // byte offset of this lane's values in a [N][B] array
+    uint32_t mask;   // neighbour mask (0 for an empty slot)
+    uint32_t ovf;
+    bool ok;
+    Pack<V, 4> rec;
+    Pack<V, VW> inp;
+};
+
+// byte stride of one step along each logical axis in a [N][B] array, kept
+// as three scalars (a struct or array indexed by the slot ends up in scratch
+// memory)
+struct Strides32 {
+    int32_t a0, a1, a2;
+};
+
+__device__ __forceinline__ uint32_t nbr_row(uint32_t row, int slot, int32_t a0, int32_t a1, int32_t a2) {
+    const int32_t m = slot < 2 ? a0 : (slot < 4 ? a1 : a2);
+    return row + (uint32_t)((slot & 1) ? m : -m);
+}
+
+template <typename V, int VW>
+__device__ __forceinline__ Pack<V, VW> ldb(const char* base, uint32_t off) {
+    return ld<V, VW>(reinterpret_cast<const V*>(base + off));
+}
+
+template <typename V, int VW>
+__device__ __forceinline__ Pack<V, VW> ldb_stream(const char* base, uint32_t off) {
+    return ld_stream<V, VW>(reinterpret_cast<const V*>(base + off));
+}
+
+template <int DIR, typename V, int VW>
+__device__ __forceinline__ void fetch32(Node32<V, VW>& p, uint64_t m, int pos, const char* __restrict__ wtc,
+                                        const char* __restrict__ inc, uint32_t rowb, uint32_t lane_off,
+                                        const Ctx& cx, const SrcDev& sd, const LevelDesc& d, const V* in) {
+    const uint32_t node = (uint32_t)(m & kNodeMask);
+    p.row = node * rowb + lane_off;
+    p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
+    p.mask = (uint32_t)(m >> kMaskShift);
+    p.rec = ldb_stream<V, 4>(wtc, (uint32_t)pos * (uint32_t)(4 * sizeof(V)));
+    if (DIR == kFwd || !cx.rcv_in) {
+        p.inp = ldb_stream<V, VW>(inc, p.row);
+    } else {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) p.inp.v[v] = (V)0;
+        if (m & kRcvFlag)
+            for (int e = d.e0; e < d.e1; ++e)
+                if (sd.rcv_pos[e] == pos) {
+                    const Pack<V, VW> y = ld<V, VW>(in + (int64_t)sd.rcv_idx[e] * cx.B + cx.rhs0);
+#pragma unroll
+                    for (int v = 0; v < VW; ++v) p.inp.v[v] += y.v[v];
+                }
+    }
+}
+
+template <typename V, int VW>
+__device__ __forceinline__ void nbrs32(const Node32<V, VW>& p, const char* __restrict__ Xc, const Strides32 sx,
+                                       Pack<V, VW> xv[3]) {
+    uint32_t m = p.mask;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (m != 0u) xv[t] = ldb<V, VW>(Xc, nbr_row(p.row, __builtin_ctz(m), sx.a0, sx.a1, sx.a2));
+        m &= m - 1u;
+    }
+}
+
+// x_node = c*ds + sum_j w_j x_j (primal) or r + sum_i w_i lambda_i
+// (transpose) in ascending slot order (the order of the rhs-group kernel,
+// hence the same bits); neighbours past the third (rare) are loaded here.
+template <int DIR, typename V, int VW>
+__device__ __forceinline__ void acc32(const Node32<V, VW>& p, const Pack<V, VW> xv[3], const V* __restrict__ ovf_base,
+                                      const char* __restrict__ Xc, const Strides32 sx, V acc[VW]) {
+    uint32_t m = p.mask;
+#pragma unroll
+    for (int v = 0; v < VW; ++v) acc[v] = (DIR == kFwd) ? p.rec.v[0] * p.inp.v[v] : p.inp.v[v];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+        if (m != 0u) {
+#pragma unroll
+            for (int v = 0; v < VW; ++v) acc[v] += p.rec.v[1 + t] * xv[t].v[v];
+        }
+        m &= m - 1u;
+    }
+    for (int t = 3; m != 0u; ++t) {
+        const Pack<V, VW> x = ldb<V, VW>(Xc, nbr_row(p.row, __builtin_ctz(m), sx.a0, sx.a1, sx.a2));
+        m &= m - 1u;
+        const V w = ovf_base[p.ovf + (t - 3)];
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] += w * x.v[v];
+    }
+}
+
+// Position of this workgroup in its source's sequence of batches: every
+// level has at least one batch (possibly empty), so that every level ends
+// with its barrier.
+struct Cursor {
+    int l, base, lo, hi;
+    LevelDesc d;
+};
+
+template <int DIR, int BATCH>
+__device__ __forceinline__ void cursor_next(Cursor& c, const SrcDev& sd, int L, int P, int part) {
+    if (c.base + BATCH < c.hi) {
+        c.base += BATCH;
+        return;
+    }
+    if (++c.l < L) {
+        c.d = load_desc<DIR>(sd, c.l);
+        share(c.d.nsc, P, part, c.lo, c.hi);
+        c.base = c.lo;
+    }
+}
+
+template <int DIR, typename V, int LPN, int NT, int U>
+__global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
+    constexpr int VW = 16 / (int)sizeof(V);
+    constexpr int B = LPN * VW;
+    constexpr int SLOTS = NT / LPN;
+    constexpr int BATCH = SLOTS * U;
+    const int P = s.P;
+    int alpha, part;
+    {
+        const int w = blockIdx.x;
+        const int item = (w % 8) * a.per_xcd + (w / 8);
+        if (item >= a.items) return;   // not part of any source's group: touches no counter
+        alpha = item / P;
+        part = item - alpha * P;
+    }
+    extern __shared__ double lds[];
+    __shared__ unsigned s_xmask;
+    const SrcDev sd = a.src[alpha];
+    const uint64_t* __restrict__ meta = DIR == kFwd ? sd.fmeta : sd.rmeta;
+    const V* __restrict__ wts = (const V*)(DIR == kFwd ? sd.fwts : sd.rwts);
+    const V* __restrict__ ovf_base = wts + a.N * 4;
+    const int L = DIR == kFwd ? sd.L_f : sd.L_r;
+    const int sub = threadIdx.x % LPN;
+    const int slot0 = threadIdx.x / LPN;
+    const int64_t NB = a.N * B;
+    Ctx cx;
+    cx.B = B;
+    cx.rhs0 = sub * VW;
+    cx.R = a.R;
+    cx.st1 = a.st1;
+    cx.st2 = a.st2;
+    cx.N = a.N;
+    cx.rcv_in = DIR == kRev && a.in_mode == FM_W_RECEIVERS;
+    const V* __restrict__ in;
+    V* __restrict__ X = (V*)a.work + (size_t)alpha * NB;
+    V* __restrict__ outp = nullptr;
+    if (DIR == kFwd) {
+        in = (const V*)a.in + (a.in_mode == FM_DS_PER_PAIR ? (size_t)alpha * NB : 0);
+    } else {
+        in = (const V*)a.in + (cx.rcv_in ? (size_t)alpha * a.R * B : (size_t)alpha * NB);
+        if (a.out_mode == FM_JT_PER_SOURCE) outp = (V*)a.out + (size_t)alpha * NB;
+    }
+    double* __restrict__ stage = (double*)s.stage + (size_t)alpha * s.stage_rows * B;
+    // byte-offset views of the same arrays (each spans < 4 GiB, checked on the host)
+    constexpr uint32_t ROWB = B * sizeof(V);
+    const uint32_t lane_off = (uint32_t)(cx.rhs0 * sizeof(V));
+    const char* __restrict__ Xc = reinterpret_cast<const char*>(X);
+    char* __restrict__ Xw = reinterpret_cast<char*>(X);
+    const char* __restrict__ inc = reinterpret_cast<const char*>(in);
+    const char* __restrict__ wtc = reinterpret_cast<const char*>(wts);
+    Strides32 sx;
+    sx.a0 = (int32_t)ROWB;
+    sx.a1 = (int32_t)(a.st1 * ROWB);
+    sx.a2 = (int32_t)(a.st2 * ROWB);
+
+    GroupSync g;
+    g.ctr = s.ctr + (size_t)alpha * kCtrStride;
+    g.abort_w = s.abort_w;
+    g.target = 0;
+    g.agent = true;          // until the XCD check at the first barrier
+    g.inv_l1 = s.inv_l1 != 0;
+    g.dead = false;
+    if (threadIdx.x == 0)
+        s_xmask = __hip_atomic_fetch_or(s.xmask + (size_t)alpha * kCtrStride, 1u << xcc_id(), __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+    bool first = true;
+
+    // The meta words of the next batch (possibly the next level's first)
+    // are requested before the current batch's operands; a batch then waits
+    // on one round trip for its records, inputs and neighbour values.  The
+    // batch (SLOTS * U nodes) is sized so that a workgroup's share of a
+    // typical level is one batch.
+    auto meta_of = [&](const Cursor& c, uint64_t mw[U]) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int u = c.base + slot0 + q * SLOTS;
+            mw[q] = (c.l < L && u < c.hi) ? __builtin_nontemporal_load(meta + c.d.p0 + u) : ~0ull;
+        }
+    };
+
+    Cursor cC;
+    cC.l = 0;
+    cC.d = load_desc<DIR>(sd, 0);
+    share(cC.d.nsc, P, part, cC.lo, cC.hi);
+    cC.base = cC.lo;
+    Cursor cN = cC;
+    cursor_next<DIR, BATCH>(cN, sd, L, P, part);
+    uint64_t mC[U];
+    meta_of(cC, mC);
+    for (;;) {
+        const bool last = cC.base + BATCH >= cC.hi;          // last batch of level cC.l
+        const bool blocks = last && cC.d.b1 > cC.d.b0;
+        uint64_t mN[U];
+        meta_of(cN, mN);
+        {
+            Node32<V, VW> ops[U];
+            Pack<V, VW> xv[U][3];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                ops[q].ok = mC[q] != ~0ull;
+                if (ops[q].ok)
+                    fetch32<DIR, V, VW>(ops[q], mC[q], cC.d.p0 + cC.base + slot0 + q * SLOTS, wtc, inc, ROWB, lane_off,
+                                        cx, sd, cC.d, in);
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q)
+                if (ops[q].ok) nbrs32<V, VW>(ops[q], Xc, sx, xv[q]);
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (ops[q].ok) {
+                    Pack<V, VW> o;
+                    acc32<DIR, V, VW>(ops[q], xv[q], ovf_base, Xc, sx, o.v);
+                    st<V, VW>(reinterpret_cast<V*>(Xw + ops[q].row), o);
+                    if (DIR == kRev && outp) {
+#pragma unroll
+                        for (int v = 0; v < VW; ++v) o.v[v] = ops[q].rec.v[0] * o.v[v];
+                        st<V, VW>(reinterpret_cast<V*>(reinterpret_cast<char*>(outp) + ops[q].row), o);
+                    }
+                }
+            }
+        }
+        if (last) {
+            if (blocks) split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wts, in, X, stage, cx, P, part, slot0);
+            group_barrier(g, P);
+            if (first) {
+                first = false;
+                const unsigned xm = __hip_atomic_load(s.xmask + (size_t)alpha * kCtrStride, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                g.agent = __builtin_popcount(xm) != 1;
+            }
+            if (blocks) {
+                split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part, s.lds_rows, lds);
+                group_barrier(g, P);
+            }
+            if (cC.l + 1 >= L) break;
+        }
+        cC = cN;
+#pragma unroll
+        for (int q = 0; q < U; ++q) mC[q] = mN[q];
+        cursor_next<DIR, BATCH>(cN, sd, L, P, part);
+    }
+}
+
+// Counters and XCD masks start from zero at every launch (a kernel, not a
+// memset, so that the launch can be captured in a graph).  The abort word is
+// left alone: it stays set until the host has read it.
+__global__ void k_split_reset(SplitArgs s, int S) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S; t += gridDim.x * blockDim.x) {
+        s.ctr[(size_t)t * kCtrStride] = 0u;
+        s.xmask[(size_t)t * kCtrStride] = 0u;
+    }
+}
+
+}  // namespace fm

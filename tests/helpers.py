@@ -63,7 +63,7 @@ def gpu_run(fm, torch, states, B, prec, direction, inp, in_mode, out_mode, tunin
         shape = (S, N, B) if out_mode == fm.FM_JT_PER_SOURCE else (N, B)
         out = torch.full(shape, float("nan"), device=dev, dtype=dt)
         batch.apply_JT(x, in_mode, out, out_mode)
-    torch.cuda.synchronize()
+    batch.status()
     res = out.cpu().numpy().astype(np.float64)
     batch.free()
     return res

@@ -135,20 +135,21 @@ def test_multisource_2d_ragged_batches(multi2d, B, rg):
 def test_schedules_are_bit_identical(curved):
     """Each node's sum runs in a fixed order whatever the schedule, so every
     schedule must give the same bits; a difference would mean a value was read
-    before it was written."""
+    before it was written.  The schedules cover the rhs-group kernel and the
+    node split (several workgroups per source meeting at every level)."""
     wl, states, ops = curved
     B = 8
     ds = seeded_ds(wl, B, 33)
     w = np.random.default_rng(34).standard_normal((1, wl.N, B))
     outs_J, outs_T = [], []
-    for rg in (1, 2, 4, 8):
-        for nt in (256, 1024):
-            for xcd in (1, -1):
-                tun = {"rhs_per_group": rg, "threads": nt, "xcd_aware": xcd}
-                outs_J.append(gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR,
-                                      fm.FM_OUT_NODES, tun))
-                outs_T.append(gpu_run(fm, torch, states, B, fm.FM_FP64, "JT", w, fm.FM_W_NODES,
-                                      fm.FM_JT_PER_SOURCE, tun))
+    schedules = [{"rhs_per_group": rg, "threads": nt, "xcd_aware": xcd, "split": 1}
+                 for rg in (1, 2, 4, 8) for nt in (256, 1024) for xcd in (1, -1)]
+    schedules += [{"split": p, "unroll": u} for p in (2, 4, 8, 16) for u in (2, 3, 4)]
+    schedules += [{"split": 4, "threads": 1024, "unroll": 2}]
+    for tun in schedules:
+        print(f"schedule {tun}", flush=True)
+        outs_J.append(gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, tun))
+        outs_T.append(gpu_run(fm, torch, states, B, fm.FM_FP64, "JT", w, fm.FM_W_NODES, fm.FM_JT_PER_SOURCE, tun))
     for o in outs_J[1:]:
         assert np.array_equal(o, outs_J[0])
     for o in outs_T[1:]:

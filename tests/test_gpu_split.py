@@ -1,0 +1,161 @@
+"""The node-split kernels: P workgroups share one source and all B
+right-hand sides and meet at the end of every level (Section 4.1: the nodes
+of a level are independent; Section 4.3: block right-hand sides, then the
+block solve).
+
+* every mode (nodes / receivers in, per-source / summed out, per-pair /
+  broadcast) against the oracle at the FP64 bar, for several P;
+* bit-identical to the rhs-group kernel (each node's sum runs in the same
+  order; a difference would mean a value read before it was written or a
+  stale cache line);
+* rows shorter than a cache line (FP64 B=8, FP32 B=16) and an output array
+  that does not start on a cache line take the invalidating barrier; FP32
+  against the oracle at 1e-4;
+* the batch status reports no timed-out wait.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import gpu_run, oracle_J, oracle_JT, oracle_ops, rel_l2, rel_l2_pairs, seeded_ds, states_for
+
+torch = pytest.importorskip("torch")
+fm = pytest.importorskip("paper_2609_14982_amd")
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-11
+TOL32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def curved():
+    wl = W.curved_state(41, 41, 25, A=500.0, eps_T=0.05)
+    wl.rcv = np.array([wl.node(i, j, 0) for j in range(0, 41, 4) for i in range(0, 41, 4)]
+                      + [wl.node(20, 20, 0)], dtype=np.int64)
+    return wl, states_for(fm, wl), oracle_ops(wl)
+
+
+@pytest.fixture(scope="module")
+def multi2d():
+    wl = W.grids.deformed_2d(161, 81, 2024, 0.4, 5, S=6, B=16, R=40, name="c2-family 161x81")
+    W.eikonal(wl)
+    return wl, states_for(fm, wl), oracle_ops(wl)
+
+
+def test_tuning_reports_split(curved):
+    wl, states, ops = curved
+    b = fm.Batch(states, 16, fm.FM_FP64)
+    assert b.tuning()["split"] > 1
+    b.free()
+    b = fm.Batch(states, 16, fm.FM_FP64, tuning={"split": 1})
+    assert b.tuning()["split"] == 1
+    b.free()
+    b = fm.Batch(states, 3, fm.FM_FP64)
+    assert b.tuning()["split"] == 1     # rows of 3 values: no node-split kernel
+    b.free()
+    with pytest.raises(fm.FmError):
+        fm.Batch(states, 3, fm.FM_FP64, tuning={"split": 4})
+    with pytest.raises(fm.FmError):
+        fm.Batch(states, 16, fm.FM_FP64, tuning={"split": 3})
+
+
+@pytest.mark.parametrize("P", [2, 4, 8, 16])
+def test_curved_all_modes_fp64(curved, P):
+    wl, states, ops = curved
+    B = 16
+    R = wl.rcv.shape[0]
+    print(f"case split curved 41x41x25 (6 SCCs) B={B} P={P}", flush=True)
+    tun = {"split": P}
+    ds = seeded_ds(wl, B, 500 + P)
+    x = gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, tun)
+    assert rel_l2_pairs(x, oracle_J(ops, ds, True)) <= TOL64
+    x1 = gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, {"split": 1})
+    assert np.array_equal(x, x1)
+    p = seeded_ds(wl, B, 600 + P, per_pair=False)
+    xr = gpu_run(fm, torch, states, B, fm.FM_FP64, "J", p, fm.FM_DS_BROADCAST, fm.FM_OUT_RECEIVERS, tun)
+    assert rel_l2_pairs(xr, oracle_J(ops, p, False, out="receivers")) <= TOL64
+    w = np.random.default_rng(700 + P).standard_normal((1, wl.N, B))
+    g = gpu_run(fm, torch, states, B, fm.FM_FP64, "JT", w, fm.FM_W_NODES, fm.FM_JT_PER_SOURCE, tun)
+    assert rel_l2_pairs(g, oracle_JT(ops, w)) <= TOL64
+    g1 = gpu_run(fm, torch, states, B, fm.FM_FP64, "JT", w, fm.FM_W_NODES, fm.FM_JT_PER_SOURCE, {"split": 1})
+    assert np.array_equal(g, g1)
+    y = np.random.default_rng(800 + P).standard_normal((1, R, B))
+    gs = gpu_run(fm, torch, states, B, fm.FM_FP64, "JT", y, fm.FM_W_RECEIVERS, fm.FM_JT_SUMMED, tun)
+    assert rel_l2(gs, O.apply_JT_summed(ops, list(y), "receivers")) <= TOL64
+    a, b = float(np.sum(xr * y)), float(np.sum(p * gs))
+    assert abs(a - b) / max(abs(a), abs(b)) <= 1e-12
+
+
+def test_multisource_2d_summed(multi2d):
+    wl, states, ops = multi2d
+    B = 16
+    print("case split c2-family 161x81 S=6 B=16", flush=True)
+    p = seeded_ds(wl, B, 901, per_pair=False)
+    xb = gpu_run(fm, torch, states, B, fm.FM_FP64, "J", p, fm.FM_DS_BROADCAST, fm.FM_OUT_RECEIVERS)
+    assert rel_l2_pairs(xb, oracle_J(ops, p, False, out="receivers")) <= TOL64
+    y = np.random.default_rng(902).standard_normal((wl.S, wl.rcv.shape[0], B))
+    gs = gpu_run(fm, torch, states, B, fm.FM_FP64, "JT", y, fm.FM_W_RECEIVERS, fm.FM_JT_SUMMED)
+    assert rel_l2(gs, O.apply_JT_summed(ops, list(y), "receivers")) <= TOL64
+    gs1 = gpu_run(fm, torch, states, B, fm.FM_FP64, "JT", y, fm.FM_W_RECEIVERS, fm.FM_JT_SUMMED, {"split": 1})
+    assert np.array_equal(gs, gs1)
+
+
+@pytest.mark.parametrize("prec,B", [("fp64", 8), ("fp32", 16), ("fp32", 32)])
+def test_short_rows_and_fp32(curved, prec, B):
+    wl, states, ops = curved
+    print(f"case split curved {prec} B={B}", flush=True)
+    pr = fm.FM_FP64 if prec == "fp64" else fm.FM_FP32
+    tol = TOL64 if prec == "fp64" else TOL32
+    ds = seeded_ds(wl, B, 1000 + B)
+    x = gpu_run(fm, torch, states, B, pr, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, {"split": 4})
+    assert rel_l2_pairs(x, oracle_J(ops, ds, True)) <= tol
+    x1 = gpu_run(fm, torch, states, B, pr, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, {"split": 1})
+    assert np.array_equal(x, x1)
+    w = np.random.default_rng(1100 + B).standard_normal((1, wl.N, B))
+    g = gpu_run(fm, torch, states, B, pr, "JT", w, fm.FM_W_NODES, fm.FM_JT_PER_SOURCE, {"split": 4})
+    assert rel_l2_pairs(g, oracle_JT(ops, w)) <= tol
+    g1 = gpu_run(fm, torch, states, B, pr, "JT", w, fm.FM_W_NODES, fm.FM_JT_PER_SOURCE, {"split": 1})
+    assert np.array_equal(g, g1)
+
+
+def test_unaligned_node_output(curved):
+    """J with nodal output writes X into the caller's array; one that starts
+    16 bytes past a cache line makes two nodes share lines."""
+    wl, states, ops = curved
+    B = 16
+    dev = torch.device("cuda:0")
+    ds = seeded_ds(wl, B, 1200)
+    batch = fm.Batch(states, B, fm.FM_FP64, tuning={"split": 4})
+    buf = torch.full((wl.N * B + 2,), float("nan"), device=dev, dtype=torch.float64)
+    out = buf[2:].view(1, wl.N, B)
+    assert out.data_ptr() % 128 == 16
+    batch.apply_J(torch.from_numpy(ds).to(dev), fm.FM_DS_PER_PAIR, out, fm.FM_OUT_NODES)
+    batch.status()
+    x = out.cpu().numpy()
+    batch.free()
+    assert rel_l2_pairs(x, oracle_J(ops, ds, True)) <= TOL64
+    x1 = gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, {"split": 1})
+    assert np.array_equal(x, x1)
+
+
+def test_repeated_applies_reuse_counters(curved):
+    """Counters restart at every launch: many applies in a row on one batch
+    give the same bits."""
+    wl, states, ops = curved
+    B = 16
+    dev = torch.device("cuda:0")
+    batch = fm.Batch(states, B, fm.FM_FP64, tuning={"split": 8})
+    ds = torch.from_numpy(seeded_ds(wl, B, 1300)).to(dev)
+    outs = []
+    for _ in range(5):
+        o = torch.empty((1, wl.N, B), device=dev, dtype=torch.float64)
+        batch.apply_J(ds, fm.FM_DS_PER_PAIR, o, fm.FM_OUT_NODES)
+        g = torch.empty((1, wl.N, B), device=dev, dtype=torch.float64)
+        batch.apply_JT(o, fm.FM_W_NODES, g, fm.FM_JT_PER_SOURCE)
+        outs.append((o, g))
+    batch.status()
+    for o, g in outs[1:]:
+        assert torch.equal(o, outs[0][0]) and torch.equal(g, outs[0][1])
+    batch.free()
