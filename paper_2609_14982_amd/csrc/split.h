@@ -104,113 +104,6 @@ __device__ __forceinline__ void share(int n, int P, int p, int& lo, int& hi) {
     hi = lo + q + (p < r ? 1 : 0);
 }
 
-// Phase 1 of the level's blocks: b_C of this workgroup's share of every
-// block's members into the staging rows (LPN lanes per member).
-template <int DIR, typename V, int LPN, int NT>
-__device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
-                                                const V* __restrict__ wts, const V* __restrict__ in,
-                                                const V* __restrict__ X, double* __restrict__ stage, const Ctx& cx,
-                                                int P, int part, int slot0) {
-    constexpr int VW = 16 / (int)sizeof(V);
-    constexpr int SLOTS = NT / LPN;
-    const V* ovf_base = wts + cx.N * 4;
-    for (int bi = d.b0; bi < d.b1; ++bi) {
-        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
-        const int k = sd.blk_k[blk];
-        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
-        const int64_t moff = sd.blk_moff[blk];
-        int lo, hi;
-        share(k, P, part, lo, hi);
-        for (int mi = lo + slot0; mi < hi; mi += SLOTS) {
-            NodeOps<V, VW> p;
-            fetch_static<DIR, V, VW>(p, meta[bp + mi], bp + mi, wts, in, cx, sd, d);
-            Pack<double, VW> o;
-            combine<DIR, V, VW, double>(p, ovf_base, X, cx, o.v);
-            st<double, VW>(stage + (moff + mi) * cx.B + cx.rhs0, o);
-        }
-    }
-}
-
-// Phase 2: rows of this workgroup's share of each block,
-// x_i = sum_j Minv(i, j) b_j (primal, column-major inverse) or
-// y_j = sum_i Minv(i, j) b_i (transpose, row-major copy), in ascending
-// order of the summation index.  A row's B right-hand sides are split over
-// NH threads of RP each (consecutive threads take consecutive rows, so a
-// wave reads a contiguous piece of each matrix column); every thread keeps G
-// matrix entries in flight.
-template <int DIR, typename V, int B, int NT>
-__device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
-                                                  const V* __restrict__ wts, const double* __restrict__ stage,
-                                                  V* __restrict__ X, V* __restrict__ outp, int P, int part,
-                                                  int lds_rows, double* lds) {
-    constexpr int RP = B < 8 ? B : 8;
-    constexpr int NH = B / RP;
-    constexpr int ROWS = NT / NH;
-    constexpr int G = 16;
-    const int h = (int)threadIdx.x / ROWS;
-    const int tr = (int)threadIdx.x % ROWS;
-    for (int bi = d.b0; bi < d.b1; ++bi) {
-        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
-        const int k = sd.blk_k[blk];
-        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
-        const int64_t moff = sd.blk_moff[blk];
-        const double* __restrict__ Mx = DIR == kFwd ? sd.inv + sd.blk_inv[blk] : sd.invt + sd.blk_inv[blk];
-        const double* __restrict__ bsrc = stage + moff * B;
-        int lo, hi;
-        share(k, P, part, lo, hi);
-        // every thread of the workgroup passes the same barriers: the row
-        // loop runs the same number of times in all of them
-        for (int r0 = lo; r0 < hi; r0 += ROWS) {
-            const int i = r0 + tr;
-            const bool own = i < hi;
-            double acc[RP];
-#pragma unroll
-            for (int rr = 0; rr < RP; ++rr) acc[rr] = 0.0;
-            for (int j0 = 0; j0 < k; j0 += lds_rows) {
-                const int jn = min(lds_rows, k - j0);
-                __syncthreads();
-                for (int t = threadIdx.x; t < jn * B; t += NT) lds[t] = bsrc[(int64_t)j0 * B + t];
-                __syncthreads();
-                if (own) {
-                    const double* __restrict__ col = Mx + (size_t)j0 * k + i;
-                    const double* __restrict__ bl = lds + h * RP;
-                    int j = 0;
-                    for (; j + G <= jn; j += G) {
-                        double m[G];
-#pragma unroll
-                        for (int t = 0; t < G; ++t) m[t] = col[(size_t)(j + t) * k];
-#pragma unroll
-                        for (int t = 0; t < G; ++t) {
-                            const double* bj = bl + (j + t) * B;
-#pragma unroll
-                            for (int rr = 0; rr < RP; ++rr) acc[rr] += m[t] * bj[rr];
-                        }
-                    }
-                    for (; j < jn; ++j) {
-                        const double m = col[(size_t)j * k];
-                        const double* bj = bl + j * B;
-#pragma unroll
-                        for (int rr = 0; rr < RP; ++rr) acc[rr] += m * bj[rr];
-                    }
-                }
-            }
-            if (own) {
-                const uint64_t mw = meta[bp + i];
-                const int64_t node = (int64_t)(mw & kNodeMask);
-                const V c = wts[(size_t)(bp + i) * 4];
-                V* dst = X + node * B + h * RP;
-#pragma unroll
-                for (int rr = 0; rr < RP; ++rr) dst[rr] = (V)acc[rr];
-                if (DIR == kRev && outp) {
-                    V* o = outp + node * B + h * RP;
-#pragma unroll
-                    for (int rr = 0; rr < RP; ++rr) o[rr] = c * (V)acc[rr];
-                }
-            }
-        }
-    }
-}
-
 // Streaming loads: records, meta words and inputs are read once per launch,
 // so they are loaded non-temporally and leave the L2 to the node values that
 // later levels read again.
@@ -222,74 +115,6 @@ __device__ __forceinline__ Pack<V, VW> ld_stream(const V* p) {
 #pragma unroll
     for (int v = 0; v < VW; ++v) r.v[v] = x[v];
     return r;
-}
-
-// Record and input of one node (as fetch_static, streaming loads).
-template <int DIR, typename V, int VW>
-__device__ __forceinline__ void fetch_stream(NodeOps<V, VW>& p, uint64_t m, int pos, const V* __restrict__ wts,
-                                             const V* __restrict__ in, const Ctx& cx, const SrcDev& sd,
-                                             const LevelDesc& d) {
-    p.node = (int64_t)(m & kNodeMask);
-    p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
-    p.mask = (uint32_t)(m >> kMaskShift);
-    p.rec = ld_stream<V, 4>(wts + (size_t)pos * 4);
-    if (DIR == kFwd || !cx.rcv_in) {
-        p.inp = ld_stream<V, VW>(in + p.node * cx.B + cx.rhs0);
-    } else {
-#pragma unroll
-        for (int v = 0; v < VW; ++v) p.inp.v[v] = (V)0;
-        if (m & kRcvFlag)
-            for (int e = d.e0; e < d.e1; ++e)
-                if (sd.rcv_pos[e] == pos) {
-                    const Pack<V, VW> y = ld<V, VW>(in + (int64_t)sd.rcv_idx[e] * cx.B + cx.rhs0);
-#pragma unroll
-                    for (int v = 0; v < VW; ++v) p.inp.v[v] += y.v[v];
-                }
-    }
-}
-
-// The first three neighbour values of a node, by set-bit rank (the k-th set
-// mask bit, ascending slot, is the k-th weight of the record).
-template <typename V, int VW>
-__device__ __forceinline__ void load_nbrs(const NodeOps<V, VW>& p, const V* __restrict__ X, const Ctx& cx,
-                                          Pack<V, VW> xv[3]) {
-    uint32_t m = p.mask;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        if (m != 0u) {
-            const int sl = __builtin_ctz(m);
-            xv[t] = ld<V, VW>(X + (p.node + slot_off(sl, cx.st1, cx.st2)) * cx.B + cx.rhs0);
-        }
-        m &= m - 1u;
-    }
-}
-
-// x_node = c*ds + sum_j w_j x_j (primal) or r + sum_i w_i lambda_i
-// (transpose) in ascending slot order (the order of the rhs-group kernel:
-// same bits); neighbours past the third (rare) are loaded here.
-template <int DIR, typename V, int VW, typename T>
-__device__ __forceinline__ void accumulate(const NodeOps<V, VW>& p, const Pack<V, VW> xv[3],
-                                           const V* __restrict__ ovf_base, const V* __restrict__ X, const Ctx& cx,
-                                           T acc[VW]) {
-    uint32_t m = p.mask;
-#pragma unroll
-    for (int v = 0; v < VW; ++v) acc[v] = (DIR == kFwd) ? (T)p.rec.v[0] * (T)p.inp.v[v] : (T)p.inp.v[v];
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        if (m != 0u) {
-#pragma unroll
-            for (int v = 0; v < VW; ++v) acc[v] += (T)p.rec.v[1 + t] * (T)xv[t].v[v];
-        }
-        m &= m - 1u;
-    }
-    for (int t = 3; m != 0u; ++t) {
-        const int sl = __builtin_ctz(m);
-        m &= m - 1u;
-        const Pack<V, VW> x = ld<V, VW>(X + (p.node + slot_off(sl, cx.st1, cx.st2)) * cx.B + cx.rhs0);
-        const T w = (T)ovf_base[p.ovf + (t - 3)];
-#pragma unroll
-        for (int v = 0; v < VW; ++v) acc[v] += w * (T)x.v[v];
-    }
 }
 
 // Singleton operands with 32-bit byte offsets: every array of one source
@@ -368,26 +193,226 @@ __device__ __forceinline__ void nbrs32(const Node32<V, VW>& p, const char* __res
 // x_node = c*ds + sum_j w_j x_j (primal) or r + sum_i w_i lambda_i
 // (transpose) in ascending slot order (the order of the rhs-group kernel,
 // hence the same bits); neighbours past the third (rare) are loaded here.
-template <int DIR, typename V, int VW>
+template <int DIR, typename V, int VW, typename T>
 __device__ __forceinline__ void acc32(const Node32<V, VW>& p, const Pack<V, VW> xv[3], const V* __restrict__ ovf_base,
-                                      const char* __restrict__ Xc, const Strides32 sx, V acc[VW]) {
+                                      const char* __restrict__ Xc, const Strides32 sx, T acc[VW]) {
     uint32_t m = p.mask;
 #pragma unroll
-    for (int v = 0; v < VW; ++v) acc[v] = (DIR == kFwd) ? p.rec.v[0] * p.inp.v[v] : p.inp.v[v];
+    for (int v = 0; v < VW; ++v) acc[v] = (DIR == kFwd) ? (T)p.rec.v[0] * (T)p.inp.v[v] : (T)p.inp.v[v];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
         if (m != 0u) {
 #pragma unroll
-            for (int v = 0; v < VW; ++v) acc[v] += p.rec.v[1 + t] * xv[t].v[v];
+            for (int v = 0; v < VW; ++v) acc[v] += (T)p.rec.v[1 + t] * (T)xv[t].v[v];
         }
         m &= m - 1u;
     }
     for (int t = 3; m != 0u; ++t) {
         const Pack<V, VW> x = ldb<V, VW>(Xc, nbr_row(p.row, __builtin_ctz(m), sx.a0, sx.a1, sx.a2));
         m &= m - 1u;
-        const V w = ovf_base[p.ovf + (t - 3)];
+        const T w = (T)ovf_base[p.ovf + (t - 3)];
 #pragma unroll
-        for (int v = 0; v < VW; ++v) acc[v] += w * x.v[v];
+        for (int v = 0; v < VW; ++v) acc[v] += w * (T)x.v[v];
+    }
+}
+
+// Phase 1 of the level's blocks: b_C of this workgroup's share of every
+// block's members into the staging rows (LPN lanes per member), summed in
+// FP64 whatever the vector precision.
+template <int DIR, typename V, int LPN, int NT>
+__device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
+                                                const char* __restrict__ wtc, const char* __restrict__ inc,
+                                                const V* __restrict__ in, const V* __restrict__ ovf_base,
+                                                const char* __restrict__ Xc, const Strides32 sx, uint32_t lane_off,
+                                                double* __restrict__ stage, const Ctx& cx, int P, int part,
+                                                int slot0) {
+    constexpr int VW = 16 / (int)sizeof(V);
+    constexpr int SLOTS = NT / LPN;
+    constexpr uint32_t ROWB = LPN * VW * sizeof(V);
+    for (int bi = d.b0; bi < d.b1; ++bi) {
+        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
+        const int k = sd.blk_k[blk];
+        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
+        const int64_t moff = sd.blk_moff[blk];
+        int lo, hi;
+        share(k, P, part, lo, hi);
+        for (int mi = lo + slot0; mi < hi; mi += SLOTS) {
+            Node32<V, VW> p;
+            fetch32<DIR, V, VW>(p, meta[bp + mi], bp + mi, wtc, inc, ROWB, lane_off, cx, sd, d, in);
+            Pack<V, VW> xv[3];
+            nbrs32<V, VW>(p, Xc, sx, xv);
+            Pack<double, VW> o;
+            acc32<DIR, V, VW, double>(p, xv, ovf_base, Xc, sx, o.v);
+            st<double, VW>(stage + (moff + mi) * cx.B + cx.rhs0, o);
+        }
+    }
+}
+
+// Phase 2: rows of this workgroup's share of each block,
+// x_i = sum_j Minv(i, j) b_j (primal, column-major inverse) or
+// y_j = sum_i Minv(i, j) b_i (transpose, row-major copy), in ascending
+// order of the summation index.  Each thread owns a row and all B
+// right-hand sides (consecutive threads take consecutive rows, so a wave
+// reads a contiguous piece of each matrix column) and keeps G matrix entries
+// in flight; b_C streams through LDS in chunks that every thread loads with
+// all its requests issued at once.
+// Phase 2 on the matrix cores (B a multiple of 16): the share's rows of
+// X_C = Minv * B_C form a (rows x k) by (k x 16) FP64 product per 16
+// right-hand sides, computed with v_mfma_f64_16x16x4f64.  Lane layout of that
+// instruction: A(16 x 4) lane l holds A[l % 16][l / 16], B(4 x 16) lane l
+// holds B[l / 16][l % 16], and D(16 x 16) lane l register r holds
+// D[4 r + l / 16][l % 16].  A wave owns TW tiles of 16 rows; per step of 4
+// columns it loads one matrix entry per lane and tile (a contiguous 128-byte
+// piece of each column) and one staged right-hand-side value per lane, with
+// clamped in-range addresses and a zero select past the last column, so the
+// loop has no divergent branches.  The four products of a step are summed by
+// the instruction, steps in ascending column order (a fixed order for every
+// schedule of the node split).
+template <int DIR, typename V, int B, int NT>
+__device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const LevelDesc& d,
+                                                       const uint64_t* __restrict__ meta, const V* __restrict__ wts,
+                                                       const double* __restrict__ stage, V* __restrict__ X,
+                                                       V* __restrict__ outp, int P, int part) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
+    constexpr int WAVES = NT / 64;
+    constexpr int TW = 4;                       // 16-row tiles per wave
+    constexpr int G = 2;                        // column steps in flight
+    constexpr int ROWS = WAVES * TW * 16;       // rows per pass
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = (int)threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int bi = d.b0; bi < d.b1; ++bi) {
+        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
+        const int k = sd.blk_k[blk];
+        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
+        const int64_t moff = sd.blk_moff[blk];
+        const double* __restrict__ Mx = DIR == kFwd ? sd.inv + sd.blk_inv[blk] : sd.invt + sd.blk_inv[blk];
+        int lo, hi;
+        share(k, P, part, lo, hi);
+        for (int r0 = lo; r0 < hi; r0 += ROWS) {
+            for (int ct = 0; ct < B; ct += 16) {
+                const double* __restrict__ bsrc = stage + moff * B + ct + lr;
+                int rowc[TW];
+#pragma unroll
+                for (int t = 0; t < TW; ++t) rowc[t] = min(r0 + (wave * TW + t) * 16 + lr, hi - 1);
+                d4 acc[TW];
+#pragma unroll
+                for (int t = 0; t < TW; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+                for (int j = 0; j < k; j += 4 * G) {
+                    double av[G][TW], bv[G];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const int col = j + 4 * g + lk;
+                        const int cc = min(col, k - 1);
+                        bv[g] = bsrc[(int64_t)cc * B];
+#pragma unroll
+                        for (int t = 0; t < TW; ++t) av[g][t] = Mx[(size_t)cc * k + rowc[t]];
+                    }
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const bool in = j + 4 * g + lk < k;
+                        const double b = in ? bv[g] : 0.0;
+#pragma unroll
+                        for (int t = 0; t < TW; ++t) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[g][t], b, acc[t], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < TW; ++t) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int i = r0 + (wave * TW + t) * 16 + 4 * r + lk;
+                        if (i < hi) {
+                            const uint64_t mw = meta[bp + i];
+                            const int64_t node = (int64_t)(mw & kNodeMask);
+                            X[node * B + ct + lr] = (V)acc[t][r];
+                            if (DIR == kRev && outp) outp[node * B + ct + lr] = wts[(size_t)(bp + i) * 4] * (V)acc[t][r];
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int DIR, typename V, int B, int NT>
+__device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
+                                                  const V* __restrict__ wts, const double* __restrict__ stage,
+                                                  V* __restrict__ X, V* __restrict__ outp, int P, int part,
+                                                  int lds_rows, double* lds) {
+    constexpr int G = 16;
+    constexpr int CH = 8;    // staged values per thread and round
+    for (int bi = d.b0; bi < d.b1; ++bi) {
+        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
+        const int k = sd.blk_k[blk];
+        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
+        const int64_t moff = sd.blk_moff[blk];
+        const double* __restrict__ Mx = DIR == kFwd ? sd.inv + sd.blk_inv[blk] : sd.invt + sd.blk_inv[blk];
+        const double* __restrict__ bsrc = stage + moff * B;
+        int lo, hi;
+        share(k, P, part, lo, hi);
+        // every thread of the workgroup passes the same barriers: the row
+        // loop runs the same number of times in all of them
+        for (int r0 = lo; r0 < hi; r0 += NT) {
+            const int i = r0 + (int)threadIdx.x;
+            const bool own = i < hi;
+            double acc[B];
+#pragma unroll
+            for (int rr = 0; rr < B; ++rr) acc[rr] = 0.0;
+            for (int j0 = 0; j0 < k; j0 += lds_rows) {
+                const int jn = min(lds_rows, k - j0);
+                const int nv = jn * B;
+                const double* __restrict__ bs = bsrc + (int64_t)j0 * B;
+                __syncthreads();
+                for (int t0 = 0; t0 < nv; t0 += NT * CH) {
+                    double v[CH];
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        const int t = t0 + c * NT + (int)threadIdx.x;
+                        v[c] = t < nv ? bs[t] : 0.0;
+                    }
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        const int t = t0 + c * NT + (int)threadIdx.x;
+                        if (t < nv) lds[t] = v[c];
+                    }
+                }
+                __syncthreads();
+                if (own) {
+                    const double* __restrict__ col = Mx + (size_t)j0 * k + i;
+                    int j = 0;
+                    for (; j + G <= jn; j += G) {
+                        double m[G];
+#pragma unroll
+                        for (int t = 0; t < G; ++t) m[t] = col[(size_t)(j + t) * k];
+#pragma unroll
+                        for (int t = 0; t < G; ++t) {
+                            const double* bj = lds + (j + t) * B;
+#pragma unroll
+                            for (int rr = 0; rr < B; ++rr) acc[rr] += m[t] * bj[rr];
+                        }
+                    }
+                    for (; j < jn; ++j) {
+                        const double m = col[(size_t)j * k];
+                        const double* bj = lds + j * B;
+#pragma unroll
+                        for (int rr = 0; rr < B; ++rr) acc[rr] += m * bj[rr];
+                    }
+                }
+            }
+            if (own) {
+                const uint64_t mw = meta[bp + i];
+                const int64_t node = (int64_t)(mw & kNodeMask);
+                const V c = wts[(size_t)(bp + i) * 4];
+                V* dst = X + node * B;
+#pragma unroll
+                for (int rr = 0; rr < B; ++rr) dst[rr] = (V)acc[rr];
+                if (DIR == kRev && outp) {
+                    V* o = outp + node * B;
+#pragma unroll
+                    for (int rr = 0; rr < B; ++rr) o[rr] = c * (V)acc[rr];
+                }
+            }
+        }
     }
 }
 
@@ -523,7 +548,7 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
             for (int q = 0; q < U; ++q) {
                 if (ops[q].ok) {
                     Pack<V, VW> o;
-                    acc32<DIR, V, VW>(ops[q], xv[q], ovf_base, Xc, sx, o.v);
+                    acc32<DIR, V, VW, V>(ops[q], xv[q], ovf_base, Xc, sx, o.v);
                     st<V, VW>(reinterpret_cast<V*>(Xw + ops[q].row), o);
                     if (DIR == kRev && outp) {
 #pragma unroll
@@ -534,7 +559,9 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
             }
         }
         if (last) {
-            if (blocks) split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wts, in, X, stage, cx, P, part, slot0);
+            if (blocks)
+                split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, lane_off, stage, cx, P,
+                                                 part, slot0);
             group_barrier(g, P);
             if (first) {
                 first = false;
@@ -543,7 +570,10 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
                 g.agent = __builtin_popcount(xm) != 1;
             }
             if (blocks) {
-                split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part, s.lds_rows, lds);
+                if constexpr (B % 16 == 0)
+                    split_block_solve_mfma<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part);
+                else
+                    split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part, s.lds_rows, lds);
                 group_barrier(g, P);
             }
             if (cC.l + 1 >= L) break;
