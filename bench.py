@@ -49,16 +49,16 @@ def algorithmic_bytes(stats_list, B, vbytes, wbytes):
     return total
 
 
-KERNEL_SOURCES = ("paper_2609_14982_amd/csrc/sweep.h", "paper_2609_14982_amd/csrc/device.hip",
-                  "paper_2609_14982_amd/csrc/setup.cpp")
+KERNEL_SOURCES = ("paper_2609_14982_amd/csrc/sweep.h", "paper_2609_14982_amd/csrc/split.h",
+                  "paper_2609_14982_amd/csrc/device.hip", "paper_2609_14982_amd/csrc/setup.cpp")
 
 
-def measured_traffic(config, precision):
+def measured_traffic(kernel, config, precision):
     """HBM bytes per launch of the primal sweep kernel from the committed
     counter profile, or None when that profile is for another workload or for
     different kernel sources."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"traffic_k_sweep_{config}_{precision}.json")
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{config}_{precision}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--sources", type=int, default=0, help="use only the first S sources (0: all)")
     ap.add_argument("--rhs-per-group", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--split", type=int, default=0, help="workgroups per source (0: library choice, 1: rhs groups)")
+    ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=4)
     ap.add_argument("--no-sweep", action="store_true", help="skip the directional-sweeping comparison")
@@ -168,6 +170,10 @@ def main():
         tuning["rhs_per_group"] = args.rhs_per_group
     if args.threads:
         tuning["threads"] = args.threads
+    if args.split:
+        tuning["split"] = args.split
+    if args.unroll:
+        tuning["unroll"] = args.unroll
     S, N, B, R = wl.S, wl.N, wl.B, wl.rcv.shape[0]
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
@@ -227,15 +233,18 @@ def main():
     tT = np.array([e[1].elapsed_time(e[2]) for e in events[1:]])
     log(f"eager applies: J {tJ.mean():.3f} ms, J^T {tT.mean():.3f} ms")
 
-    # roofline of the dominant kernel: the primal sweep (one launch per apply_J;
-    # the receiver gather launched after it moves S*R*B values, <0.01 %)
+    # roofline of the dominant kernel: the primal sweep (one launch per apply_J,
+    # between a counter reset of S words and the receiver gather of S*R*B
+    # values, together <0.1 % of the window)
+    split = batch.tuning()["split"] > 1
+    kname = "k_split" if split else "k_sweep"
     bytes_J = algorithmic_bytes(stats, B, vbytes, vbytes)
     gbs_J = bytes_J / (tJ.mean() * 1e-3) / 1e9
     gbs_T = bytes_J / (tT.mean() * 1e-3) / 1e9
-    traffic = measured_traffic(args.config, args.precision) if not args.sources else None
+    traffic = measured_traffic(kname, args.config, args.precision) if not args.sources else None
     roof = {"bound": "hbm", "achieved": round(gbs_J, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs_J / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": "k_sweep primal (apply_J)", "bytes_per_launch": bytes_J,
+            "kernel": f"{kname} primal (apply_J)", "bytes_per_launch": bytes_J,
             "launch_ms": round(float(tJ.mean()), 4),
             "transpose_GBs_incl_source_sum": round(gbs_T, 1)}
 
@@ -288,6 +297,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.n1}x{wl.n2}x{wl.n3} deformed grid, "
                                f"{S} sources x {B} rhs, {R} receivers",
+                   "schedule": batch.tuning(),
                    "grid": [wl.n1, wl.n2, wl.n3], "sources": S, "rhs": B, "receivers": R,
                    "setup_s": round(setup_wall, 2),
                    "levels_fwd_max": max(s["levels_fwd"] for s in stats),
