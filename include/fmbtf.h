@@ -96,7 +96,7 @@ typedef struct fm_tuning {
     int32_t min_lds_bytes;  /* LDS reserved per workgroup (limits workgroups per CU) */
     int32_t xcd_aware;      /* 1 or 0 (default): keep the groups of one source on one XCD; -1: off */
     int32_t unroll;         /* nodes per thread in flight inside a level: 1, 2 or 4 (rhs groups);
-                               2, 3, 4 (split, 4 lanes per node) or 2, 4, 6 (split, 8 lanes) */
+                               2, 3, 4 (split, 4 lanes per node) or 2, 4, 5 (split, 8 lanes) */
     int32_t split;          /* workgroups sharing one source and all B rhs (node split):
                                0 = choose (the rhs-group kernel when no split fits),
                                1 = off (rhs groups), 2, 4, 8, 16 = that many */

@@ -69,6 +69,7 @@ struct fm_batch {
     int32_t* cycles_dev = nullptr;   // [items]
     // node split (tun.split > 1)
     int32_t split_grid = 0, split_per_xcd = 0, split_items = 0, split_lds_rows = 0;
+    int32_t split_rcv_lds = 0, split_stage_off = 0;
     size_t split_lds = 0;
     int64_t stage_rows = 0;
     void* stage = nullptr;           // [S][stage_rows][B] FP64 block right-hand sides
@@ -85,6 +86,19 @@ namespace fm {
             return FM_EHIP;                                                              \
         }                                                                                \
     } while (0)
+
+// Loads through the pointers stored in SrcDev: the compiler cannot infer
+// their address space and would emit FLAT loads, which also count against the
+// LDS/scalar wait counter; these name the global address space explicitly.
+template <class T>
+__device__ __forceinline__ T gld(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)(p);
+}
+
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gptr(const T* p) {
+    return (const __attribute__((address_space(1))) T*)(p);
+}
 
 struct ApplyArgs {
     const SrcDev* src;

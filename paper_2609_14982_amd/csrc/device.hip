@@ -354,41 +354,57 @@ static hipError_t launch_sweep(bool fwd, const fm_tuning& t, const ApplyArgs& a,
 }
 
 static constexpr size_t kLdsMax = 160 * 1024;
-template <int DIR, typename V, int LPN, int NT, int U>
+template <int DIR, typename V, int LPN, int NT, int U, int MODE>
 static const void* split_fn() {
-    return (const void*)k_split<DIR, V, LPN, NT, U>;
+    return (const void*)k_split<DIR, V, LPN, NT, U, MODE>;
 }
 
 // The node-split kernels that are built (lanes per node, threads, unroll).
 #define FM_SPLIT_SHAPES(X)                                             \
     X(4, 512, 2) X(4, 512, 3) X(4, 512, 4) X(4, 1024, 2)               \
-    X(8, 512, 2) X(8, 512, 4) X(8, 512, 6) X(8, 1024, 2) X(8, 1024, 3)
+    X(8, 512, 2) X(8, 512, 4) X(8, 512, 5) X(8, 1024, 2)
 
-static const void* split_kernel(bool fwd, bool fp64, int lpn, int nt, int u) {
-#define FM_SPLIT_PTR(L_, N_, U_)                                                               \
-    if (lpn == L_ && nt == N_ && u == U_) {                                                    \
-        if (fwd) return fp64 ? split_fn<kFwd, double, L_, N_, U_>() : split_fn<kFwd, float, L_, N_, U_>(); \
-        return fp64 ? split_fn<kRev, double, L_, N_, U_>() : split_fn<kRev, float, L_, N_, U_>();          \
+// kind 0: primal; 1: transpose from nodes; 2: transpose from receivers
+template <typename V, int L_, int N_, int U_>
+static const void* split_kind(int kind) {
+    switch (kind) {
+        case 0: return split_fn<kFwd, V, L_, N_, U_, 0>();
+        case 1: return split_fn<kRev, V, L_, N_, U_, 0>();
+        case 2: return split_fn<kRev, V, L_, N_, U_, 1>();
     }
+    return nullptr;
+}
+
+static const void* split_kernel(int kind, bool fp64, int lpn, int nt, int u) {
+#define FM_SPLIT_PTR(L_, N_, U_) \
+    if (lpn == L_ && nt == N_ && u == U_) return fp64 ? split_kind<double, L_, N_, U_>(kind) : split_kind<float, L_, N_, U_>(kind);
     FM_SPLIT_SHAPES(FM_SPLIT_PTR)
 #undef FM_SPLIT_PTR
     return nullptr;
 }
 
-template <int DIR, typename V, int LPN, int NT, int U>
+template <int DIR, typename V, int LPN, int NT, int U, int MODE>
 static hipError_t launch_split_one(const ApplyArgs& a, const SplitArgs& s, int grid, size_t lds, hipStream_t st) {
-    hipLaunchKernelGGL((k_split<DIR, V, LPN, NT, U>), dim3(grid), dim3(NT), lds, st, a, s);
+    hipLaunchKernelGGL((k_split<DIR, V, LPN, NT, U, MODE>), dim3(grid), dim3(NT), lds, st, a, s);
     return hipGetLastError();
 }
 
-template <int DIR, typename V>
+template <int DIR, typename V, int MODE>
 static hipError_t launch_split_dir(int lpn, int nt, int u, const ApplyArgs& a, const SplitArgs& s, int grid,
                                    size_t lds, hipStream_t st) {
 #define FM_SPLIT_LAUNCH(L_, N_, U_) \
-    if (lpn == L_ && nt == N_ && u == U_) return launch_split_one<DIR, V, L_, N_, U_>(a, s, grid, lds, st);
+    if (lpn == L_ && nt == N_ && u == U_) return launch_split_one<DIR, V, L_, N_, U_, MODE>(a, s, grid, lds, st);
     FM_SPLIT_SHAPES(FM_SPLIT_LAUNCH)
 #undef FM_SPLIT_LAUNCH
     return hipErrorInvalidValue;
+}
+
+template <typename V>
+static hipError_t launch_split_v(bool fwd, int mode, int lpn, int nt, int u, const ApplyArgs& a, const SplitArgs& s,
+                                 int grid, size_t lds, hipStream_t st) {
+    if (fwd) return launch_split_dir<kFwd, V, 0>(lpn, nt, u, a, s, grid, lds, st);
+    return mode ? launch_split_dir<kRev, V, 1>(lpn, nt, u, a, s, grid, lds, st)
+                : launch_split_dir<kRev, V, 0>(lpn, nt, u, a, s, grid, lds, st);
 }
 
 static int split_lpn(const fm_batch* b) {
@@ -409,17 +425,18 @@ static hipError_t launch_split(const fm_batch* b, bool fwd, const ApplyArgs& a0)
     s.stage_rows = b->stage_rows;
     s.P = b->tun.split;
     s.lds_rows = b->split_lds_rows;
+    s.rcv_lds = b->split_rcv_lds;
+    s.stage_off = b->split_stage_off;
     const size_t vbytes = b->prec == FM_FP64 ? 8 : 4;
     s.inv_l1 = ((size_t)b->B * vbytes) % 128 != 0 || ((uintptr_t)a.work & 127u) != 0;
     hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(256), 0, b->stream, s, b->S);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int lpn = split_lpn(b), nt = b->tun.threads, u = b->tun.unroll;
+    const int mode = !fwd && a.in_mode == FM_W_RECEIVERS ? 1 : 0;
     if (b->prec == FM_FP64)
-        return fwd ? launch_split_dir<kFwd, double>(lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream)
-                   : launch_split_dir<kRev, double>(lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream);
-    return fwd ? launch_split_dir<kFwd, float>(lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream)
-               : launch_split_dir<kRev, float>(lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream);
+        return launch_split_v<double>(fwd, mode, lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream);
+    return launch_split_v<float>(fwd, mode, lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream);
 }
 
 // Choose and prepare the node split of a new batch (tun.split resolved in
@@ -435,9 +452,10 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     // workgroup's share of a typical level in one round trip)
     const int nt = asked.threads ? asked.threads : 512;
     const int u = asked.unroll ? asked.unroll : (lpn == 8 ? 4 : 3);
-    const void* kf = split_kernel(true, fp64, lpn, nt, u);
-    const void* kr = split_kernel(false, fp64, lpn, nt, u);
-    const bool built = kf && kr;
+    const void* kf = split_kernel(0, fp64, lpn, nt, u);
+    const void* kr = split_kernel(1, fp64, lpn, nt, u);
+    const void* kq = split_kernel(2, fp64, lpn, nt, u);
+    const bool built = kf && kr && kq;
     if (t.split != 0 && t.split != 2 && t.split != 4 && t.split != 8 && t.split != 16) {
         set_error("split must be 0, 1, 2, 4, 8 or 16");
         return FM_EINVAL;
@@ -461,7 +479,7 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     int dev = b->device, cus = 0;
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     int occ = 1 << 30;
-    for (const void* k : {kf, kr}) {
+    for (const void* k : {kf, kr, kq}) {
         HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_cap));
         int nb = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, nt, lds));
@@ -493,8 +511,22 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     b->split_per_xcd = (int32_t)(per8 * P);
     b->split_grid = 8 * b->split_per_xcd;
     b->split_items = b->S * P;
-    b->split_lds = lds;
-    b->split_lds_rows = (int32_t)(lds / ((size_t)b->B * sizeof(double)));
+    // receiver inputs of the transpose in LDS when they fit in 64 KB (values
+    // as FP64, then the int32 positions), the block staging area after them
+    const size_t rcv_bytes = (size_t)b->R * b->B * sizeof(double) + (size_t)b->R * sizeof(int32_t);
+    b->split_rcv_lds = b->R > 0 && rcv_bytes <= 64 * 1024;
+    b->split_stage_off = b->split_rcv_lds ? (int32_t)(((rcv_bytes + 255) & ~(size_t)255) / sizeof(double)) : 0;
+    const size_t lds_all = std::min<size_t>(lds + (size_t)b->split_stage_off * sizeof(double), (size_t)lds_cap);
+    b->split_lds = lds_all;
+    b->split_lds_rows = (int32_t)((lds_all - (size_t)b->split_stage_off * sizeof(double)) / ((size_t)b->B * sizeof(double)));
+    for (const void* k : {kf, kr, kq}) {
+        int nb = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, nt, lds_all));
+        if ((int64_t)nb * cus < 8 * per8 * P) {
+            set_error("node split: the workgroups no longer fit with %zu B of LDS", lds_all);
+            return FM_EINVAL;
+        }
+    }
     b->stage_rows = rows;
     if (b->split_lds_rows < 1) { set_error("LDS too small for one staged row"); return FM_EINVAL; }
     const size_t stage = (size_t)b->S * rows * b->B * sizeof(double);

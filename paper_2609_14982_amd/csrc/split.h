@@ -43,8 +43,10 @@ struct SplitArgs {
     void* stage;        // [S][stage_rows][B] block right-hand sides
     int64_t stage_rows;
     int32_t P;          // workgroups per source
-    int32_t lds_rows;   // rows of b_C per LDS chunk
+    int32_t lds_rows;   // rows of b_C per LDS chunk (vector block path)
     int32_t inv_l1;     // rows are not a multiple of 128 bytes
+    int32_t rcv_lds;    // receiver inputs of the transpose staged in LDS
+    int32_t stage_off;  // first LDS double of the block staging area
 };
 
 constexpr int kCtrStride = 32;                 // words between counters
@@ -107,14 +109,23 @@ __device__ __forceinline__ void share(int n, int P, int p, int& lo, int& hi) {
 // Streaming loads: records, meta words and inputs are read once per launch,
 // so they are loaded non-temporally and leave the L2 to the node values that
 // later levels read again.
+// The pointers are cast to the global address space: a generic pointer
+// would give FLAT loads, which also count against the LDS/scalar wait
+// counter, so every wait for a scalar or LDS access would wait for them too.
 template <typename V, int VW>
 __device__ __forceinline__ Pack<V, VW> ld_stream(const V* p) {
     typedef V vec __attribute__((ext_vector_type(VW)));
-    const vec x = __builtin_nontemporal_load(reinterpret_cast<const vec*>(p));
+    typedef const __attribute__((address_space(1))) vec gvec;
+    const vec x = __builtin_nontemporal_load((gvec*)(p));
     Pack<V, VW> r;
 #pragma unroll
     for (int v = 0; v < VW; ++v) r.v[v] = x[v];
     return r;
+}
+
+__device__ __forceinline__ uint64_t ld_meta(const uint64_t* p) {
+    typedef const __attribute__((address_space(1))) uint64_t gu64;
+    return __builtin_nontemporal_load((gu64*)(p));
 }
 
 // Singleton operands with 32-bit byte offsets: every array of one source
@@ -155,10 +166,20 @@ __device__ __forceinline__ Pack<V, VW> ldb_stream(const char* base, uint32_t off
     return ld_stream<V, VW>(reinterpret_cast<const V*>(base + off));
 }
 
+// Receiver inputs of the transpose (r = P^T y, duplicates added in entry
+// order), either from the LDS copy made at kernel start (rv values per entry,
+// rpos reverse positions) or from global memory.
+struct RcvLds {
+    const double* rv;
+    const int32_t* rpos;
+    bool on;
+};
+
 template <int DIR, typename V, int VW>
 __device__ __forceinline__ void fetch32(Node32<V, VW>& p, uint64_t m, int pos, const char* __restrict__ wtc,
                                         const char* __restrict__ inc, uint32_t rowb, uint32_t lane_off,
-                                        const Ctx& cx, const SrcDev& sd, const LevelDesc& d, const V* in) {
+                                        const Ctx& cx, const SrcDev& sd, const LevelDesc& d, const V* in,
+                                        const RcvLds& rl) {
     const uint32_t node = (uint32_t)(m & kNodeMask);
     p.row = node * rowb + lane_off;
     p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
@@ -169,13 +190,34 @@ __device__ __forceinline__ void fetch32(Node32<V, VW>& p, uint64_t m, int pos, c
     } else {
 #pragma unroll
         for (int v = 0; v < VW; ++v) p.inp.v[v] = (V)0;
-        if (m & kRcvFlag)
-            for (int e = d.e0; e < d.e1; ++e)
-                if (sd.rcv_pos[e] == pos) {
-                    const Pack<V, VW> y = ld<V, VW>(in + (int64_t)sd.rcv_idx[e] * cx.B + cx.rhs0);
+        // with the LDS copy the receiver values are added later by
+        // rcv_add, after every load of the batch has been issued
+        if (!rl.on && (m & kRcvFlag)) {
+            {
+                for (int e = d.e0; e < d.e1; ++e)
+                    if (gld(sd.rcv_pos + (e)) == pos) {
+                        const Pack<V, VW> y = ld<V, VW>(in + (int64_t)gld(sd.rcv_idx + (e)) * cx.B + cx.rhs0);
 #pragma unroll
-                    for (int v = 0; v < VW; ++v) p.inp.v[v] += y.v[v];
-                }
+                        for (int v = 0; v < VW; ++v) p.inp.v[v] += y.v[v];
+                    }
+            }
+        }
+    }
+}
+
+// Receiver inputs from the LDS copy (duplicates in entry order): every lane
+// walks the level's few receiver entries (uniform bounds) and keeps the
+// matching ones.
+template <typename V, int VW>
+__device__ __forceinline__ void rcv_add(Node32<V, VW>& p, int pos, const LevelDesc& d, const RcvLds& rl, int B,
+                                        int rhs0) {
+    for (int e = d.e0; e < d.e1; ++e) {
+        const bool hit = rl.rpos[e] == pos;
+#pragma unroll
+        for (int v = 0; v < VW; ++v) {
+            const V y = (V)rl.rv[e * B + rhs0 + v];
+            p.inp.v[v] = hit ? p.inp.v[v] + y : p.inp.v[v];
+        }
     }
 }
 
@@ -210,7 +252,7 @@ __device__ __forceinline__ void acc32(const Node32<V, VW>& p, const Pack<V, VW> 
     for (int t = 3; m != 0u; ++t) {
         const Pack<V, VW> x = ldb<V, VW>(Xc, nbr_row(p.row, __builtin_ctz(m), sx.a0, sx.a1, sx.a2));
         m &= m - 1u;
-        const T w = (T)ovf_base[p.ovf + (t - 3)];
+        const T w = (T)gld(ovf_base + p.ovf + (t - 3));
 #pragma unroll
         for (int v = 0; v < VW; ++v) acc[v] += w * (T)x.v[v];
     }
@@ -225,22 +267,23 @@ __device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDes
                                                 const V* __restrict__ in, const V* __restrict__ ovf_base,
                                                 const char* __restrict__ Xc, const Strides32 sx, uint32_t lane_off,
                                                 double* __restrict__ stage, const Ctx& cx, int P, int part,
-                                                int slot0) {
+                                                int slot0, const RcvLds& rl) {
     constexpr int VW = 16 / (int)sizeof(V);
     constexpr int SLOTS = NT / LPN;
     constexpr uint32_t ROWB = LPN * VW * sizeof(V);
     for (int bi = d.b0; bi < d.b1; ++bi) {
-        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
-        const int k = sd.blk_k[blk];
-        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
-        const int64_t moff = sd.blk_moff[blk];
+        const int blk = DIR == kFwd ? gld(sd.fblk_id + (bi)) : gld(sd.rblk_id + (bi));
+        const int k = gld(sd.blk_k + (blk));
+        const int bp = DIR == kFwd ? gld(sd.blk_fpos + (blk)) : gld(sd.blk_rpos + (blk));
+        const int64_t moff = gld(sd.blk_moff + (blk));
         int lo, hi;
         share(k, P, part, lo, hi);
         for (int mi = lo + slot0; mi < hi; mi += SLOTS) {
             Node32<V, VW> p;
-            fetch32<DIR, V, VW>(p, meta[bp + mi], bp + mi, wtc, inc, ROWB, lane_off, cx, sd, d, in);
+            fetch32<DIR, V, VW>(p, ld_meta(meta + bp + mi), bp + mi, wtc, inc, ROWB, lane_off, cx, sd, d, in, rl);
             Pack<V, VW> xv[3];
             nbrs32<V, VW>(p, Xc, sx, xv);
+            if (DIR == kRev && cx.rcv_in && rl.on) rcv_add<V, VW>(p, bp + mi, d, rl, cx.B, cx.rhs0);
             Pack<double, VW> o;
             acc32<DIR, V, VW, double>(p, xv, ovf_base, Xc, sx, o.v);
             st<double, VW>(stage + (moff + mi) * cx.B + cx.rhs0, o);
@@ -282,11 +325,12 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
     const int wave = (int)threadIdx.x >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     for (int bi = d.b0; bi < d.b1; ++bi) {
-        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
-        const int k = sd.blk_k[blk];
-        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
-        const int64_t moff = sd.blk_moff[blk];
-        const double* __restrict__ Mx = DIR == kFwd ? sd.inv + sd.blk_inv[blk] : sd.invt + sd.blk_inv[blk];
+        const int blk = DIR == kFwd ? gld(sd.fblk_id + (bi)) : gld(sd.rblk_id + (bi));
+        const int k = gld(sd.blk_k + (blk));
+        const int bp = DIR == kFwd ? gld(sd.blk_fpos + (blk)) : gld(sd.blk_rpos + (blk));
+        const int64_t moff = gld(sd.blk_moff + (blk));
+        const __attribute__((address_space(1))) double* __restrict__ Mx =
+            gptr(DIR == kFwd ? sd.inv + gld(sd.blk_inv + (blk)) : sd.invt + gld(sd.blk_inv + (blk)));
         int lo, hi;
         share(k, P, part, lo, hi);
         for (int r0 = lo; r0 < hi; r0 += ROWS) {
@@ -322,10 +366,10 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
                     for (int r = 0; r < 4; ++r) {
                         const int i = r0 + (wave * TW + t) * 16 + 4 * r + lk;
                         if (i < hi) {
-                            const uint64_t mw = meta[bp + i];
+                            const uint64_t mw = gld(meta + bp + i);
                             const int64_t node = (int64_t)(mw & kNodeMask);
                             X[node * B + ct + lr] = (V)acc[t][r];
-                            if (DIR == kRev && outp) outp[node * B + ct + lr] = wts[(size_t)(bp + i) * 4] * (V)acc[t][r];
+                            if (DIR == kRev && outp) outp[node * B + ct + lr] = gld(wts + (size_t)(bp + i) * 4) * (V)acc[t][r];
                         }
                     }
                 }
@@ -342,11 +386,12 @@ __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelD
     constexpr int G = 16;
     constexpr int CH = 8;    // staged values per thread and round
     for (int bi = d.b0; bi < d.b1; ++bi) {
-        const int blk = DIR == kFwd ? sd.fblk_id[bi] : sd.rblk_id[bi];
-        const int k = sd.blk_k[blk];
-        const int bp = DIR == kFwd ? sd.blk_fpos[blk] : sd.blk_rpos[blk];
-        const int64_t moff = sd.blk_moff[blk];
-        const double* __restrict__ Mx = DIR == kFwd ? sd.inv + sd.blk_inv[blk] : sd.invt + sd.blk_inv[blk];
+        const int blk = DIR == kFwd ? gld(sd.fblk_id + (bi)) : gld(sd.rblk_id + (bi));
+        const int k = gld(sd.blk_k + (blk));
+        const int bp = DIR == kFwd ? gld(sd.blk_fpos + (blk)) : gld(sd.blk_rpos + (blk));
+        const int64_t moff = gld(sd.blk_moff + (blk));
+        const __attribute__((address_space(1))) double* __restrict__ Mx =
+            gptr(DIR == kFwd ? sd.inv + gld(sd.blk_inv + (blk)) : sd.invt + gld(sd.blk_inv + (blk)));
         const double* __restrict__ bsrc = stage + moff * B;
         int lo, hi;
         share(k, P, part, lo, hi);
@@ -378,7 +423,7 @@ __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelD
                 }
                 __syncthreads();
                 if (own) {
-                    const double* __restrict__ col = Mx + (size_t)j0 * k + i;
+                    const __attribute__((address_space(1))) double* __restrict__ col = Mx + (size_t)j0 * k + i;
                     int j = 0;
                     for (; j + G <= jn; j += G) {
                         double m[G];
@@ -400,9 +445,9 @@ __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelD
                 }
             }
             if (own) {
-                const uint64_t mw = meta[bp + i];
+                const uint64_t mw = gld(meta + bp + i);
                 const int64_t node = (int64_t)(mw & kNodeMask);
-                const V c = wts[(size_t)(bp + i) * 4];
+                const V c = gld(wts + (size_t)(bp + i) * 4);
                 V* dst = X + node * B;
 #pragma unroll
                 for (int rr = 0; rr < B; ++rr) dst[rr] = (V)acc[rr];
@@ -437,8 +482,14 @@ __device__ __forceinline__ void cursor_next(Cursor& c, const SrcDev& sd, int L, 
     }
 }
 
-template <int DIR, typename V, int LPN, int NT, int U>
+// RCV (transpose only): input given at the receivers.  The two input modes
+// are separate kernels; with a run-time choice between them inside the batch
+// loop the compiler placed its memory waits for one path only, and the
+// receiver path ran 15 % slower.  (The optional per-source output stays a
+// run-time choice: compiled out, the same loop measured slower.)
+template <int DIR, typename V, int LPN, int NT, int U, int RCV_>
 __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
+    constexpr bool RCV = DIR == kRev && RCV_ != 0;
     constexpr int VW = 16 / (int)sizeof(V);
     constexpr int B = LPN * VW;
     constexpr int SLOTS = NT / LPN;
@@ -469,7 +520,7 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
     cx.st1 = a.st1;
     cx.st2 = a.st2;
     cx.N = a.N;
-    cx.rcv_in = DIR == kRev && a.in_mode == FM_W_RECEIVERS;
+    cx.rcv_in = RCV;
     const V* __restrict__ in;
     V* __restrict__ X = (V*)a.work + (size_t)alpha * NB;
     V* __restrict__ outp = nullptr;
@@ -491,6 +542,22 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
     sx.a0 = (int32_t)ROWB;
     sx.a1 = (int32_t)(a.st1 * ROWB);
     sx.a2 = (int32_t)(a.st2 * ROWB);
+    // transpose from receiver data: copy this source's R x B inputs (in the
+    // receiver-entry order of the reverse levels) and their positions to LDS
+    RcvLds rl;
+    rl.on = DIR == kRev && cx.rcv_in && s.rcv_lds != 0;
+    rl.rv = lds;
+    rl.rpos = reinterpret_cast<const int32_t*>(lds + (size_t)a.R * B);
+    if (rl.on) {
+        double* rv = lds;
+        int32_t* rpos = reinterpret_cast<int32_t*>(lds + (size_t)a.R * B);
+        for (int t = threadIdx.x; t < a.R * B; t += NT) {
+            const int e = t / B, b = t - e * B;
+            rv[t] = (double)in[(int64_t)gld(sd.rcv_idx + (e)) * B + b];
+        }
+        for (int t = threadIdx.x; t < a.R; t += NT) rpos[t] = gld(sd.rcv_pos + (t));
+        __syncthreads();
+    }
 
     GroupSync g;
     g.ctr = s.ctr + (size_t)alpha * kCtrStride;
@@ -513,7 +580,7 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int u = c.base + slot0 + q * SLOTS;
-            mw[q] = (c.l < L && u < c.hi) ? __builtin_nontemporal_load(meta + c.d.p0 + u) : ~0ull;
+            mw[q] = (c.l < L && u < c.hi) ? ld_meta(meta + c.d.p0 + u) : ~0ull;
         }
     };
 
@@ -539,11 +606,16 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
                 ops[q].ok = mC[q] != ~0ull;
                 if (ops[q].ok)
                     fetch32<DIR, V, VW>(ops[q], mC[q], cC.d.p0 + cC.base + slot0 + q * SLOTS, wtc, inc, ROWB, lane_off,
-                                        cx, sd, cC.d, in);
+                                        cx, sd, cC.d, in, rl);
             }
 #pragma unroll
             for (int q = 0; q < U; ++q)
                 if (ops[q].ok) nbrs32<V, VW>(ops[q], Xc, sx, xv[q]);
+            if (RCV && rl.on) {
+#pragma unroll
+                for (int q = 0; q < U; ++q)
+                    if (ops[q].ok) rcv_add<V, VW>(ops[q], cC.d.p0 + cC.base + slot0 + q * SLOTS, cC.d, rl, B, cx.rhs0);
+            }
 #pragma unroll
             for (int q = 0; q < U; ++q) {
                 if (ops[q].ok) {
@@ -561,7 +633,7 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
         if (last) {
             if (blocks)
                 split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, lane_off, stage, cx, P,
-                                                 part, slot0);
+                                                 part, slot0, rl);
             group_barrier(g, P);
             if (first) {
                 first = false;
@@ -573,7 +645,8 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
                 if constexpr (B % 16 == 0)
                     split_block_solve_mfma<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part);
                 else
-                    split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part, s.lds_rows, lds);
+                    split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part, s.lds_rows,
+                                                     lds + s.stage_off);
                 group_barrier(g, P);
             }
             if (cC.l + 1 >= L) break;

@@ -29,18 +29,18 @@ template <int DIR>
 __device__ __forceinline__ LevelDesc load_desc(const SrcDev& sd, int l) {
     LevelDesc d;
     if (DIR == kFwd) {
-        d.p0 = sd.flvl_ptr[l];
-        d.nsc = sd.flvl_nsc[l];
-        d.b0 = sd.fblk_ptr[l];
-        d.b1 = sd.fblk_ptr[l + 1];
+        d.p0 = gld(sd.flvl_ptr + (l));
+        d.nsc = gld(sd.flvl_nsc + (l));
+        d.b0 = gld(sd.fblk_ptr + (l));
+        d.b1 = gld(sd.fblk_ptr + (l + 1));
         d.e0 = d.e1 = 0;
     } else {
-        d.p0 = sd.rlvl_ptr[l];
-        d.nsc = sd.rlvl_nsc[l];
-        d.b0 = sd.rblk_ptr[l];
-        d.b1 = sd.rblk_ptr[l + 1];
-        d.e0 = sd.rcvlvl_ptr[l];
-        d.e1 = sd.rcvlvl_ptr[l + 1];
+        d.p0 = gld(sd.rlvl_ptr + (l));
+        d.nsc = gld(sd.rlvl_nsc + (l));
+        d.b0 = gld(sd.rblk_ptr + (l));
+        d.b1 = gld(sd.rblk_ptr + (l + 1));
+        d.e0 = gld(sd.rcvlvl_ptr + (l));
+        d.e1 = gld(sd.rcvlvl_ptr + (l + 1));
     }
     return d;
 }
