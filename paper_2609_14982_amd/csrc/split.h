@@ -593,21 +593,26 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
     cursor_next<DIR, BATCH>(cN, sd, L, P, part);
     uint64_t mC[U];
     meta_of(cC, mC);
+    // records and inputs of a batch (static data)
+    Node32<V, VW> ops[U];
+    auto fetch_batch = [&](const Cursor& c, const uint64_t mw[U]) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            ops[q].ok = mw[q] != ~0ull;
+            if (ops[q].ok)
+                fetch32<DIR, V, VW>(ops[q], mw[q], c.d.p0 + c.base + slot0 + q * SLOTS, wtc, inc, ROWB, lane_off, cx,
+                                    sd, c.d, in, rl);
+        }
+    };
+    bool pre = false;   // ops already hold the current batch's static data
     for (;;) {
         const bool last = cC.base + BATCH >= cC.hi;          // last batch of level cC.l
         const bool blocks = last && cC.d.b1 > cC.d.b0;
         uint64_t mN[U];
         meta_of(cN, mN);
         {
-            Node32<V, VW> ops[U];
             Pack<V, VW> xv[U][3];
-#pragma unroll
-            for (int q = 0; q < U; ++q) {
-                ops[q].ok = mC[q] != ~0ull;
-                if (ops[q].ok)
-                    fetch32<DIR, V, VW>(ops[q], mC[q], cC.d.p0 + cC.base + slot0 + q * SLOTS, wtc, inc, ROWB, lane_off,
-                                        cx, sd, cC.d, in, rl);
-            }
+            if (!pre) fetch_batch(cC, mC);
 #pragma unroll
             for (int q = 0; q < U; ++q)
                 if (ops[q].ok) nbrs32<V, VW>(ops[q], Xc, sx, xv[q]);
@@ -631,9 +636,15 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
             }
         }
         if (last) {
+            // The next level's first batch reads records and inputs that no
+            // level writes: they are requested before the level's last
+            // barrier, whose wait for this level's stores then covers them.
+            const bool more = cC.l + 1 < L;
             if (blocks)
                 split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, lane_off, stage, cx, P,
                                                  part, slot0, rl);
+            else if (more)
+                fetch_batch(cN, mN);
             group_barrier(g, P);
             if (first) {
                 first = false;
@@ -647,10 +658,12 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
                 else
                     split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part, s.lds_rows,
                                                      lds + s.stage_off);
+                if (more) fetch_batch(cN, mN);
                 group_barrier(g, P);
             }
-            if (cC.l + 1 >= L) break;
+            if (!more) break;
         }
+        pre = last;
         cC = cN;
 #pragma unroll
         for (int q = 0; q < U; ++q) mC[q] = mN[q];
