@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--split", type=int, default=0, help="workgroups per source (0: library choice, 1: rhs groups)")
     ap.add_argument("--unroll", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the schedule search (fm_autotune) and use the library's choice or the flags")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=4)
     ap.add_argument("--no-sweep", action="store_true", help="skip the directional-sweeping comparison")
@@ -177,17 +179,26 @@ def main():
     S, N, B, R = wl.S, wl.N, wl.B, wl.rcv.shape[0]
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    t1 = time.perf_counter()
-    batch = fm.Batch(states, B, prec, tuning=tuning or None, stream=stream)
-    torch.cuda.synchronize()
-    log(f"batch create + upload: {time.perf_counter() - t1:.1f}s, tuning {batch.tuning()}")
-
     gen = torch.Generator(device=dev)
     gen.manual_seed(4000)
     p = torch.randn((N, B), device=dev, dtype=dt, generator=gen)
     y = torch.randn((S, R, B), device=dev, dtype=dt, generator=gen)
     d = torch.empty((S, R, B), device=dev, dtype=dt)
     g = torch.empty((N, B), device=dev, dtype=dt)
+    tune_table = None
+    if not args.no_autotune and not tuning:
+        # schedule search on this batch's own data (outside the timed region)
+        t1 = time.perf_counter()
+        tuning, tune_table = fm.autotune(states, B, prec, p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS,
+                                         y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=2, stream=stream)
+        for t, ms in tune_table:
+            log(f"autotune: split {t['split']} threads {t['threads']} unroll {t['unroll']} "
+                f"rhs_per_group {t['rhs_per_group']}: {ms:.2f} ms per J + J^T")
+        log(f"autotune: {time.perf_counter() - t1:.1f}s, best {tuning}")
+    t1 = time.perf_counter()
+    batch = fm.Batch(states, B, prec, tuning=tuning or None, stream=stream)
+    torch.cuda.synchronize()
+    log(f"batch create + upload: {time.perf_counter() - t1:.1f}s, tuning {batch.tuning()}")
 
     # the timed loop: LSQR iterations replayed from a captured graph
     GRAPH_ITERS = 30
@@ -298,6 +309,8 @@ def main():
         "config": {"workload": f"{args.config}: {wl.n1}x{wl.n2}x{wl.n3} deformed grid, "
                                f"{S} sources x {B} rhs, {R} receivers",
                    "schedule": batch.tuning(),
+                   "schedule_search": ([{"split": t["split"], "threads": t["threads"], "unroll": t["unroll"],
+                                         "ms": round(ms, 3)} for t, ms in tune_table] if tune_table else None),
                    "grid": [wl.n1, wl.n2, wl.n3], "sources": S, "rhs": B, "receivers": R,
                    "setup_s": round(setup_wall, 2),
                    "levels_fwd_max": max(s["levels_fwd"] for s in stats),

@@ -161,6 +161,25 @@ void fm_state_free(fm_state* st);
 int fm_batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precision,
                     const fm_tuning* tuning, void* hip_stream, fm_batch** out);
 
+/*
+ * Schedule search (the autotuned level chunks of the batching step, §4.4):
+ * for the rhs-group kernel and every built node-split shape (threads, nodes
+ * per thread in flight) with 2, 4, 8 or 16 workgroups per source that fits
+ * the device, create a batch of the given states, run fm_apply_J and
+ * fm_apply_JT once, then time reps more pairs with HIP events on hip_stream,
+ * and free the batch.  *best receives the fastest schedule (pass it to
+ * fm_batch_create); candidates / ms (optional, max_out entries) receive
+ * every schedule measured and its milliseconds per J + J^T pair, *n_out the
+ * count.  ds, j_out, w, jt_out are device buffers laid out per the modes, as
+ * for fm_apply_J / fm_apply_JT (j_out and jt_out are overwritten).  Each
+ * candidate allocates its own scratch: call it once, before the Krylov loop,
+ * not under graph capture.  Errors: FM_EINVAL, FM_ENOMEM, FM_EHIP.
+ */
+int fm_autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* hip_stream,
+                const void* ds, int32_t ds_mode, void* j_out, int32_t out_mode, const void* w, int32_t w_mode,
+                void* jt_out, int32_t jt_mode, int32_t reps, fm_tuning* best, fm_tuning* candidates, float* ms,
+                int32_t max_out, int32_t* n_out);
+
 /* Change the stream later applies are enqueued on. */
 int fm_batch_set_stream(fm_batch* b, void* hip_stream);
 

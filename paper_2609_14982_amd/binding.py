@@ -26,7 +26,7 @@ SYMBOLS = (
     "fm_apply_J",
     "fm_apply_JT", "fm_apply_J_sweep", "fm_apply_JT_sweep", "fm_batch_free", "fm_last_error",
     "fm_lsqr_create", "fm_lsqr_start", "fm_lsqr_iterate", "fm_lsqr_capture", "fm_lsqr_replay",
-    "fm_lsqr_buffers", "fm_lsqr_free",
+    "fm_lsqr_buffers", "fm_lsqr_free", "fm_autotune",
 )
 
 
@@ -80,6 +80,8 @@ def load():
         "fm_state_free": (None, [vp]),
         "fm_batch_create": (C.c_int, [vp, i32, i32, i32, vp, vp, vp]),
         "fm_batch_set_stream": (C.c_int, [vp, vp]),
+        "fm_autotune": (C.c_int, [vp, i32, i32, i32, vp, vp, i32, vp, i32, vp, i32, vp, i32, i32, vp, vp, vp, i32,
+                                  vp]),
         "fm_batch_tuning": (C.c_int, [vp, vp]),
         "fm_batch_status": (C.c_int, [vp]),
         "fm_batch_split_info": (C.c_int, [vp, vp]),
@@ -229,6 +231,35 @@ def _dptr(t, dtype, shape, what):
     if not t.is_contiguous():
         raise ValueError(f"{what} must be contiguous")
     return C.c_void_p(t.data_ptr())
+
+
+def autotune(states, B, precision, ds, ds_mode, j_out, out_mode, w, w_mode, jt_out, jt_mode, reps=2, stream=None):
+    """fm_autotune on device tensors: returns (best tuning dict, [(tuning dict, ms per J + J^T pair), ...])."""
+    import torch
+    lib = load()
+    states = list(states)
+    S = len(states)
+    arr = (C.c_void_p * S)(*[st.ptr.value for st in states])
+    dt = torch.float64 if precision == FM_FP64 else torch.float32
+    N, R = states[0].N, states[0].R
+    B = int(B)
+    ds_shape = (S, N, B) if ds_mode == FM_DS_PER_PAIR else (N, B)
+    o_shape = (S, N, B) if out_mode == FM_OUT_NODES else (S, R, B)
+    w_shape = (S, N, B) if w_mode == FM_W_NODES else (S, R, B)
+    g_shape = (S, N, B) if jt_mode == FM_JT_PER_SOURCE else (N, B)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    best = fm_tuning()
+    n_max = 64
+    cands = (fm_tuning * n_max)()
+    ms = (C.c_float * n_max)()
+    n = C.c_int32(0)
+    _check(lib.fm_autotune(arr, S, B, int(precision), C.c_void_p(stream.cuda_stream),
+                           _dptr(ds, dt, ds_shape, "ds"), int(ds_mode), _dptr(j_out, dt, o_shape, "j_out"),
+                           int(out_mode), _dptr(w, dt, w_shape, "w"), int(w_mode), _dptr(jt_out, dt, g_shape, "jt_out"),
+                           int(jt_mode), int(reps), C.byref(best), cands, ms, n_max, C.byref(n)))
+    as_dict = lambda t: {k: getattr(t, k) for k, _ in fm_tuning._fields_}
+    return as_dict(best), [(as_dict(cands[i]), float(ms[i])) for i in range(n.value)]
 
 
 class Batch:

@@ -990,6 +990,66 @@ int batch_split_info(fm_batch* b, int32_t* xcd_masks) {
     return FM_OK;
 }
 
+// Schedule search over the built kernels on the caller's own data (the
+// level-chunk autotuning of the batching step).
+int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* stream, const void* ds,
+             int32_t ds_mode, void* j_out, int32_t out_mode, const void* w, int32_t w_mode, void* jt_out,
+             int32_t jt_mode, int32_t reps, fm_tuning* best, fm_tuning* cands, float* ms, int32_t max_out,
+             int32_t* n_out) {
+    if (!best) { set_error("null output pointer"); return FM_EINVAL; }
+    if (reps < 1) { set_error("reps must be >= 1"); return FM_EINVAL; }
+    std::vector<fm_tuning> list;
+    list.push_back(fm_tuning{0, 0, 0, 0, 0, 1});   // rhs groups, library defaults
+    const int vw = precision == FM_FP64 ? 2 : 4;
+    const int lpn = B % vw == 0 ? B / vw : 0;
+#define FM_SPLIT_CAND(L_, N_, U_)                                           \
+    if (lpn == L_)                                                          \
+        for (int P : {2, 4, 8, 16}) list.push_back(fm_tuning{0, N_, 0, 0, U_, P});
+    FM_SPLIT_SHAPES(FM_SPLIT_CAND)
+#undef FM_SPLIT_CAND
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best_ms = -1.0f;
+    int32_t n = 0;
+    int rc = FM_OK;
+    for (const fm_tuning& t : list) {
+        fm_batch* b = nullptr;
+        if (batch_create(states, S, B, precision, &t, stream, &b) != FM_OK) continue;   // does not fit
+        if (t.split > 1 && b->tun.split != t.split) { batch_free(b); continue; }
+        float m = -1.0f;
+        rc = apply_J(b, ds, ds_mode, j_out, out_mode);
+        if (rc == FM_OK) rc = apply_JT(b, w, w_mode, jt_out, jt_mode);
+        if (rc == FM_OK && hipEventRecord(e0, st) == hipSuccess) {
+            for (int r = 0; r < reps && rc == FM_OK; ++r) {
+                rc = apply_J(b, ds, ds_mode, j_out, out_mode);
+                if (rc == FM_OK) rc = apply_JT(b, w, w_mode, jt_out, jt_mode);
+            }
+            if (rc == FM_OK && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                hipEventElapsedTime(&m, e0, e1) == hipSuccess)
+                m /= (float)reps;
+        }
+        if (rc == FM_OK) rc = batch_status(b);
+        const fm_tuning used = b->tun;
+        batch_free(b);
+        if (rc != FM_OK) break;
+        if (m >= 0.0f) {
+            if (cands && n < max_out) cands[n] = used;
+            if (ms && n < max_out) ms[n] = m;
+            ++n;
+            if (best_ms < 0.0f || m < best_ms) { best_ms = m; *best = used; }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_out) *n_out = n;
+    if (rc != FM_OK) return rc;
+    if (best_ms < 0.0f) { set_error("no schedule could be created for these states"); return FM_EINVAL; }
+    clear_error();
+    return FM_OK;
+}
+
 int batch_set_stream(fm_batch* b, void* stream) {
     if (!b) { set_error("null batch"); return FM_EINVAL; }
     b->stream = (hipStream_t)stream;

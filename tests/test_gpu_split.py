@@ -185,3 +185,26 @@ def test_repeated_applies_reuse_counters(curved):
     for o, g in outs[1:]:
         assert torch.equal(o, outs[0][0]) and torch.equal(g, outs[0][1])
     batch.free()
+
+
+def test_autotune_picks_a_measured_schedule(curved):
+    """The schedule search measures the rhs-group kernel and every node-split
+    shape that fits, returns the fastest, and that schedule reproduces the
+    oracle."""
+    wl, states, ops = curved
+    B = 16
+    R = wl.rcv.shape[0]
+    dev = torch.device("cuda:0")
+    p = torch.from_numpy(seeded_ds(wl, B, 1500, per_pair=False)).to(dev)
+    y = torch.from_numpy(np.random.default_rng(1501).standard_normal((1, R, B))).to(dev)
+    d = torch.empty((1, R, B), device=dev, dtype=torch.float64)
+    g = torch.empty((wl.N, B), device=dev, dtype=torch.float64)
+    best, table = fm.autotune(states, B, fm.FM_FP64, p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS,
+                              y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=2)
+    for t, ms in table:
+        print(f"{t} {ms:.3f} ms", flush=True)
+    assert any(t["split"] == 1 for t, _ in table)
+    assert any(t["split"] > 1 for t, _ in table)
+    assert min(ms for _, ms in table) == [ms for t, ms in table if t == best][0]
+    x = gpu_run(fm, torch, states, B, fm.FM_FP64, "J", p.cpu().numpy(), fm.FM_DS_BROADCAST, fm.FM_OUT_RECEIVERS, best)
+    assert rel_l2_pairs(x, oracle_J(ops, p.cpu().numpy(), False, out="receivers")) <= TOL64
