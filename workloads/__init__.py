@@ -18,6 +18,7 @@ from .grids import (  # noqa: F401
     manufactured,
     metric_from_coords,
     mu_g,
+    perturbed_model,
     smooth_noise,
     small_3d,
     traveltime_solver,

@@ -172,6 +172,21 @@ def traveltime_solver(wl: Workload, init_radius: int = 2, nthreads: int | None =
     return solve
 
 
+def perturbed_model(wl: Workload, seed: int, n: int = 6, amp: float = 0.05, sigma_km: float = 0.4) -> np.ndarray:
+    """A "true" slowness for a Gauss-Newton test: s * (1 + sum of n seeded
+    Gaussian anomalies of relative amplitude U[-amp, amp] and width sigma_km,
+    centred inside the domain)."""
+    rng = np.random.default_rng(seed)
+    X = wl.X
+    lo, hi = X.min(axis=0), X.max(axis=0)
+    f = np.zeros(X.shape[0])
+    for _ in range(n):
+        c = lo + (0.2 + 0.6 * rng.random(X.shape[1])) * (hi - lo)
+        a = rng.uniform(-amp, amp)
+        f += a * np.exp(-np.sum((X - c) ** 2, axis=1) / (2 * sigma_km ** 2))   # coordinates in km
+    return wl.s * (1.0 + f)
+
+
 # --------------------------------------------------------------------------
 # seeded vectors
 # --------------------------------------------------------------------------
