@@ -2,7 +2,7 @@
 sides, the primal and transpose frozen full-metric tangent transport through
 the SCC condensation graph (Algorithm 1, Phase III), on one MI355X.
 
-One step = one LSQR iteration of the Krylov inner loop (Algorithm 1, line 20)
+One step = one LSQR iteration of the Krylov inner loop (Algorithm 1, Section 4.5)
 over the whole batch: J from the model block [N][B] (broadcast to every
 source) to receiver data [S][R][B], J^T back to the source-summed model block
 (Section 4.4), and the LSQR vector updates.  The iterations run from a HIP

@@ -103,7 +103,7 @@ typedef struct fm_tuning {
 } fm_tuning;
 
 /*
- * Build the frozen state of one source (Algorithm 1, Phase I, lines 7-10):
+ * Build the frozen state of one source (Algorithm 1, Phase I):
  * face-upwind coefficients and row normalisation (Section 3.1), calibration
  * c = (A T) / s (Section 3.2), dependency graph (Section 3.3), SCCs and a
  * topological level schedule of the condensation DAG (Section 4.1), and a
@@ -209,8 +209,8 @@ int fm_batch_status(fm_batch* b);
 int fm_batch_split_info(fm_batch* b, int32_t* xcd_masks);
 
 /*
- * Primal action dT = J ds for every (source, rhs) pair (Algorithm 1, lines
- * 15-16): q = c * ds, forward traversal of the condensation DAG, then P.
+ * Primal action dT = J ds for every (source, rhs) pair (Algorithm 1,
+ * Phase III): q = c * ds, forward traversal of the condensation DAG, then P.
  *   ds   device, layout per ds_mode (FM_DS_PER_PAIR or FM_DS_BROADCAST)
  *   out  device, layout per out_mode (FM_OUT_NODES or FM_OUT_RECEIVERS),
  *        fully overwritten
@@ -220,7 +220,7 @@ int fm_batch_split_info(fm_batch* b, int32_t* xcd_masks);
 int fm_apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode);
 
 /*
- * Transpose action (Algorithm 1, lines 17-18): r = w (FM_W_NODES) or P^T w
+ * Transpose action (Algorithm 1, Phase III): r = w (FM_W_NODES) or P^T w
  * (FM_W_RECEIVERS), reverse traversal solving A^T lambda = r (singletons by
  * transposed substitution, SCC blocks with the transpose of the same
  * factors), then c * lambda per source (FM_JT_PER_SOURCE) or summed over the
@@ -249,7 +249,7 @@ int fm_apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, i
 
 /*
  * LSQR over the paired actions: the Krylov least-squares inner loop of
- * Algorithm 1 (line 20; Section 4.5), which applies J and J^T once per
+ * Algorithm 1 (Section 4.5), which applies J and J^T once per
  * iteration at the same frozen state.  It solves min ||J x - d||_2 for each
  * of the B columns independently: x is a model block [N][B] shared by all
  * sources (FM_DS_BROADCAST), d is stacked receiver data [S][R][B], J^T sums

@@ -13,7 +13,7 @@ the solver agree with it to discretisation accuracy (exactly along the
 uniform scaling direction ds = s, where both give T).
 
 gauss_newton_step computes the Gauss-Newton increment of the data misfit
-0.5 ||P T(s) - d||^2 by CGLS on J (Algorithm 1, lines 15-20, with CGLS in
+0.5 ||P T(s) - d||^2 by CGLS on J (Algorithm 1, with CGLS in
 place of LSMR and no regularisation).
 """
 from __future__ import annotations

@@ -1,5 +1,5 @@
 // LSQR inner loop over the paired actions (the Krylov least-squares solve of
-// Algorithm 1, line 20, which calls J and J^T once per iteration at the same
+// Algorithm 1, which calls J and J^T once per iteration at the same
 // frozen state, Section 4.5).  The harness solves min ||J x - d|| column by
 // column for the B right-hand sides of a batch: model-space vectors are
 // [N][B] (one model block shared by all sources, FM_DS_BROADCAST), data-space

@@ -1,4 +1,4 @@
-// Host setup of one frozen source state (Algorithm 1, Phase I, lines 7-10).
+// Host setup of one frozen source state (Algorithm 1, Phase I).
 //
 //  1. face-upwind coefficients, row normalisation      Section 3.1, eq. (discrete-row)
 //  2. calibration c = (A T) / s                          Section 3.2

@@ -2,7 +2,7 @@
 64 sources x 400 receivers): a true model with six seeded +-5 % slowness
 anomalies gives d_obs = P T(s_true) by the first-arrival solver; one
 matrix-free Gauss-Newton step (CGLS, 30 iterations of J and the
-source-summed J^T on the GPU, Algorithm 1 lines 15-20) must reduce the
+source-summed J^T on the GPU, Algorithm 1) must reduce the
 nonlinear data misfit, and the CGLS residual norms must not increase."""
 import numpy as np
 import pytest

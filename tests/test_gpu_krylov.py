@@ -1,5 +1,5 @@
-"""The LSQR harness (Krylov inner loop over the paired actions, Algorithm 1
-line 20, Section 4.5) on the GPU.
+"""The LSQR harness (Krylov inner loop over the paired actions, Algorithm 1,
+Section 4.5) on the GPU.
 
 * Its iterates match scipy's LSQR run on the oracle's J and J^T (stacked
   sources, source-summed transpose) column by column.
