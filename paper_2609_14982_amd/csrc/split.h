@@ -319,7 +319,7 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
     typedef double d4 __attribute__((ext_vector_type(4)));
     constexpr int WAVES = NT / 64;
     constexpr int TW = 4;                       // 16-row tiles per wave
-    constexpr int G = 2;                        // column steps in flight
+    constexpr int G = 4;                        // column steps in flight
     constexpr int ROWS = WAVES * TW * 16;       // rows per pass
     const int lane = (int)threadIdx.x & 63;
     const int wave = (int)threadIdx.x >> 6;
