@@ -92,11 +92,14 @@ typedef struct fm_stats {
 /* Launch schedule of a batch; zero fields take the library default. */
 typedef struct fm_tuning {
     int32_t rhs_per_group;  /* right-hand sides handled by one workgroup: 1,2,4,8,16 */
-    int32_t threads;        /* workgroup size: 256, 512 or 1024 */
-    int32_t min_lds_bytes;  /* LDS reserved per workgroup (limits workgroups per CU) */
+    int32_t threads;        /* workgroup size: 256, 512 or 1024 (rhs groups); 256 or 512 (split) */
+    int32_t min_lds_bytes;  /* LDS reserved per workgroup (limits workgroups per CU); the split
+                               reserves this (default 16 KB) plus the receiver inputs of J^T */
     int32_t xcd_aware;      /* 1 or 0 (default): keep the groups of one source on one XCD; -1: off */
     int32_t unroll;         /* nodes per thread in flight inside a level: 1, 2 or 4 (rhs groups);
-                               2, 3, 4 (split, 4 lanes per node) or 2, 4, 5 (split, 8 lanes) */
+                               split, 4 lanes per node (FP64 B=8, FP32 B=16): 2, 3, 4 with
+                               512 threads, 4 with 256; 8 lanes per node (FP64 B=16, FP32 B=32):
+                               2, 4 with 512 threads, 3, 4 with 256 */
     int32_t split;          /* workgroups sharing one source and all B rhs (node split):
                                0 = choose (the rhs-group kernel when no split fits),
                                1 = off (rhs groups), 2, 4, 8, 16 = that many */

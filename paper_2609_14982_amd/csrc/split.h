@@ -487,8 +487,11 @@ __device__ __forceinline__ void cursor_next(Cursor& c, const SrcDev& sd, int L, 
 // loop the compiler placed its memory waits for one path only, and the
 // receiver path ran 15 % slower.  (The optional per-source output stays a
 // run-time choice: compiled out, the same loop measured slower.)
+// At least two waves per SIMD (at most 256 registers per lane), so that two
+// 256-thread workgroups of different sources share a CU and one streams
+// while the other waits at a level barrier.
 template <int DIR, typename V, int LPN, int NT, int U, int RCV_>
-__global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_split(ApplyArgs a, SplitArgs s) {
     constexpr bool RCV = DIR == kRev && RCV_ != 0;
     constexpr int VW = 16 / (int)sizeof(V);
     constexpr int B = LPN * VW;
@@ -608,6 +611,7 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
     for (;;) {
         const bool last = cC.base + BATCH >= cC.hi;          // last batch of level cC.l
         const bool blocks = last && cC.d.b1 > cC.d.b0;
+        const bool more = cC.l + 1 < L;
         uint64_t mN[U];
         meta_of(cN, mN);
         {
@@ -621,30 +625,42 @@ __global__ __launch_bounds__(NT) void k_split(ApplyArgs a, SplitArgs s) {
                 for (int q = 0; q < U; ++q)
                     if (ops[q].ok) rcv_add<V, VW>(ops[q], cC.d.p0 + cC.base + slot0 + q * SLOTS, cC.d, rl, B, cx.rhs0);
             }
+            Pack<V, VW> o[U];
+            uint32_t orow[U];
+            V oscale[U];
+            bool ook[U];
 #pragma unroll
             for (int q = 0; q < U; ++q) {
-                if (ops[q].ok) {
-                    Pack<V, VW> o;
-                    acc32<DIR, V, VW, V>(ops[q], xv[q], ovf_base, Xc, sx, o.v);
-                    st<V, VW>(reinterpret_cast<V*>(Xw + ops[q].row), o);
-                    if (DIR == kRev && outp) {
+                ook[q] = ops[q].ok;
+                orow[q] = ops[q].row;
+                oscale[q] = ops[q].rec.v[0];
+                if (ook[q]) acc32<DIR, V, VW, V>(ops[q], xv[q], ovf_base, Xc, sx, o[q].v);
+            }
+            // The next level's first batch reads records and inputs that no
+            // level writes.  At the end of a level without blocks they are
+            // requested before this batch's stores (its meta words arrived
+            // with the neighbour values), so that the barrier's wait for the
+            // stores and the wait for these loads are one round trip.
+            if (last && !blocks && more) fetch_batch(cN, mN);
 #pragma unroll
-                        for (int v = 0; v < VW; ++v) o.v[v] = ops[q].rec.v[0] * o.v[v];
-                        st<V, VW>(reinterpret_cast<V*>(reinterpret_cast<char*>(outp) + ops[q].row), o);
+            for (int q = 0; q < U; ++q) {
+                if (ook[q]) {
+                    st<V, VW>(reinterpret_cast<V*>(Xw + orow[q]), o[q]);
+                    if (DIR == kRev && outp) {
+                        Pack<V, VW> os;
+#pragma unroll
+                        for (int v = 0; v < VW; ++v) os.v[v] = oscale[q] * o[q].v[v];
+                        st<V, VW>(reinterpret_cast<V*>(reinterpret_cast<char*>(outp) + orow[q]), os);
                     }
                 }
             }
         }
         if (last) {
-            // The next level's first batch reads records and inputs that no
-            // level writes: they are requested before the level's last
-            // barrier, whose wait for this level's stores then covers them.
-            const bool more = cC.l + 1 < L;
+            // a level with blocks fetches the next level's first batch after
+            // its block products (that state is not kept live across them)
             if (blocks)
                 split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, lane_off, stage, cx, P,
                                                  part, slot0, rl);
-            else if (more)
-                fetch_batch(cN, mN);
             group_barrier(g, P);
             if (first) {
                 first = false;

@@ -145,7 +145,7 @@ def test_schedules_are_bit_identical(curved):
     schedules = [{"rhs_per_group": rg, "threads": nt, "xcd_aware": xcd, "split": 1}
                  for rg in (1, 2, 4, 8) for nt in (256, 1024) for xcd in (1, -1)]
     schedules += [{"split": p, "unroll": u} for p in (2, 4, 8, 16) for u in (2, 3, 4)]
-    schedules += [{"split": 4, "threads": 1024, "unroll": 2}]
+    schedules += [{"split": p, "threads": 256, "unroll": 4} for p in (4, 8)]
     for tun in schedules:
         print(f"schedule {tun}", flush=True)
         outs_J.append(gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, tun))

@@ -158,7 +158,9 @@ def test_split_schedules_bit_identical_b16(curved):
     ds = seeded_ds(wl, B, 1400)
     w = np.random.default_rng(1401).standard_normal((1, wl.N, B))
     outs = []
-    for tun in [{"split": p, "unroll": u} for p in (2, 4, 8, 16) for u in (2, 4)]:
+    scheds = [{"split": p, "unroll": u} for p in (2, 4, 8, 16) for u in (2, 4)]
+    scheds += [{"split": p, "threads": 256, "unroll": u} for p in (4, 8) for u in (3, 4)]
+    for tun in scheds:
         print(f"schedule {tun}", flush=True)
         outs.append((gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, tun),
                      gpu_run(fm, torch, states, B, fm.FM_FP64, "JT", w, fm.FM_W_NODES, fm.FM_JT_PER_SOURCE, tun)))
