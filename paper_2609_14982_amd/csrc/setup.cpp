@@ -449,7 +449,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         }
 
         // ---- 7: level-ordered packing ----
-        // order of components inside a level: singletons by node id, then blocks
+        // order of components inside a level: singletons (see below), then blocks
         auto pack_direction = [&](bool fwd, std::vector<uint64_t>& meta, std::vector<double>& wts,
                                   std::vector<int32_t>& lvl_ptr, std::vector<int32_t>& lvl_nsc,
                                   std::vector<int32_t>& blk_ptr, std::vector<int32_t>& blk_id,
@@ -493,11 +493,19 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                     for (int32_t m = 0; m < k; m++) pos_of[st->cnodes[st->cptr[c] + m]] = next_bl[l]++;
                 }
             }
-            // node ids of each level's singleton run in ascending order
+            // each level's singleton run: nodes with at most three neighbours
+            // in ascending node id, then those with more (their further
+            // weights are a dependent load, on which a whole wave waits, so
+            // they are kept together in the level's last batches)
             std::vector<int32_t> order(N);
             for (int64_t p = 0; p < N; p++) order[pos_of[p]] = (int32_t)p;
+            auto many = [&](int32_t v) { return __builtin_popcount(fwd ? st->pmask[v] : st->smask[v]) > 3; };
             for (int32_t l = 0; l < L; l++) {
-                std::sort(order.begin() + lvl_ptr[l], order.begin() + lvl_ptr[l] + lvl_nsc[l]);
+                std::sort(order.begin() + lvl_ptr[l], order.begin() + lvl_ptr[l] + lvl_nsc[l],
+                          [&](int32_t a, int32_t b) {
+                              const bool ma = many(a), mb = many(b);
+                              return ma != mb ? mb : a < b;
+                          });
                 for (int32_t q = lvl_ptr[l]; q < lvl_ptr[l] + lvl_nsc[l]; q++) pos_of[order[q]] = q;
             }
             // records: a fixed [c, w1, w2, w3] per position, further weights of

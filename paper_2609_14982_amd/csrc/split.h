@@ -77,8 +77,9 @@ __device__ __forceinline__ void group_barrier(GroupSync& g, int P) {
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned dead = g.dead ? 1u : 0u;
-        __hip_atomic_fetch_add(g.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (!dead) {
+        // the last workgroup to arrive learns it from the add and does not poll
+        const unsigned old = __hip_atomic_fetch_add(g.ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!dead && (int)(old + 1u - g.target) < 0) {
             const uint64_t t0 = wall_clock64();
             for (;;) {
                 const unsigned c = __hip_atomic_load(g.ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
