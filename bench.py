@@ -258,6 +258,25 @@ def main():
             "kernel": f"{kname} primal (apply_J)", "bytes_per_launch": bytes_J,
             "launch_ms": round(float(tJ.mean()), 4),
             "transpose_GBs_incl_source_sum": round(gbs_T, 1)}
+    # what a plain device copy sustains on this GPU (2 GiB read + 2 GiB
+    # written per copy), and the primal kernel's counted bytes per second
+    nc = 1 << 28
+    ca = torch.ones(nc, dtype=torch.float64, device=dev)
+    cb = torch.empty_like(ca)
+    cevs = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    cb.copy_(ca)
+    cevs[0].record(stream)
+    for _ in range(5):
+        cb.copy_(ca)
+    cevs[1].record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nc * 8 * 5 / (cevs[0].elapsed_time(cevs[1]) * 1e-3) / 1e9
+    del ca, cb
+    roof["copy_GBs"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(gbs_J / copy_gbs, 4)
+    if traffic is not None:
+        roof["traffic_GBs"] = round(traffic / (tJ.mean() * 1e-3) / 1e9, 1)
+    log(f"device copy {copy_gbs:.0f} GB/s; primal kernel {gbs_J:.0f} GB/s algorithmic = {gbs_J / copy_gbs:.3f} of it")
 
     sweep = None
     if not args.no_sweep:

@@ -234,11 +234,12 @@ __global__ void k_gather_receivers(ApplyArgs a) {
 // g[n][b] = sum_alpha c_alpha[n] lambda_alpha[n][b], sources in ascending
 // order (Section 4.4).  A streaming reduction: each thread takes VW
 // consecutive values of one node (one 16-byte access per source) and keeps
-// the accesses of SU sources in flight.
+// the accesses of SU sources in flight; lambda is read once, so its loads
+// are non-temporal, and every load names the global address space.
 template <typename V>
 __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
     constexpr int VW = 16 / (int)sizeof(V);
-    constexpr int SU = 8;
+    constexpr int SU = 16;
     const int64_t NB = a.N * a.B;
     const V* __restrict__ work = (const V*)a.work;
     V* __restrict__ out = (V*)a.out;
@@ -256,8 +257,8 @@ __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
 #pragma unroll
                 for (int u = 0; u < SU; ++u) {
                     if (a0 + u < a.S) {
-                        x[u] = ld<V, VW>(work + (int64_t)(a0 + u) * NB + e0);
-                        c[u] = ((const V*)cal[a0 + u])[node];
+                        x[u] = ld_stream<V, VW>(work + (int64_t)(a0 + u) * NB + e0);
+                        c[u] = gld((const V*)gld(cal + (a0 + u)) + node);
                     }
                 }
 #pragma unroll
