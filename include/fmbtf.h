@@ -130,6 +130,28 @@ int fm_build_frozen_states(const fm_grid* g, int32_t S, const double* T, const d
                            const int64_t* src_nodes, const int64_t* rcv_nodes, int32_t n_rcv,
                            int32_t nthreads, fm_state** out);
 
+/*
+ * The same with interpolating receivers (P_alpha of Section 4.4 samples the
+ * transported perturbation at receiver locations between nodes): receiver r
+ * of a state samples sum_k w[r][k] x[node[r][k]] over k_per_rcv entries, and
+ * P_alpha^T adds w[r][k] y_r at node[r][k].
+ *   rcv_nodes    host [n_rcv][k_per_rcv] (per state; [S][n_rcv][k_per_rcv] for the batch builder)
+ *   rcv_weights  host, same shape, finite (NULL: every weight 1); entries of
+ *                weight 0 are dropped
+ *   k_per_rcv    1..64 (1 with NULL weights is the plain selection above)
+ * Every state of a batch needs the same n_rcv.  The transpose from receiver
+ * data stages the weighted inputs in LDS when a source's entries fit in 64 KB
+ * (entries x (8 B + 8 B x B)); otherwise it reads them from global memory.
+ * Errors: as fm_build_frozen_state; FM_EINVAL for k_per_rcv out of range or
+ * a weight that is not finite.
+ */
+int fm_build_frozen_state_w(const fm_grid* g, const double* T, const double* s, int64_t src_node,
+                            const int64_t* rcv_nodes, const double* rcv_weights, int32_t n_rcv, int32_t k_per_rcv,
+                            fm_state** out);
+int fm_build_frozen_states_w(const fm_grid* g, int32_t S, const double* T, const double* s,
+                             const int64_t* src_nodes, const int64_t* rcv_nodes, const double* rcv_weights,
+                             int32_t n_rcv, int32_t k_per_rcv, int32_t nthreads, fm_state** out);
+
 /* Structural statistics of a state (Section 5.2, eq. (graph-fractions)). */
 int fm_state_stats(const fm_state* st, fm_stats* out);
 

@@ -113,10 +113,24 @@ class OracleOperator:
     rcv: np.ndarray
     T: np.ndarray
     s: np.ndarray
+    rcv_w: np.ndarray | None = None
 
     @property
     def N(self):
         return self.n1 * self.n2 * self.n3
+
+    def P(self) -> sp.csr_matrix:
+        """The receiver sampling P_alpha (Section 4.4) as an R x N matrix:
+        row r holds weight w[r][k] at node rcv[r][k] (entries at one node
+        added); on-grid receivers, rcv of shape [R] without weights, give the
+        selection rows e_rcv[r]."""
+        nodes = np.asarray(self.rcv, dtype=np.int64)
+        if nodes.ndim == 1:
+            nodes = nodes[:, None]
+        w = np.ones(nodes.shape) if self.rcv_w is None else np.asarray(self.rcv_w, dtype=np.float64)
+        R, K = nodes.shape
+        rows = np.repeat(np.arange(R), K)
+        return sp.csr_matrix((w.reshape(-1), (rows, nodes.reshape(-1))), shape=(R, self.N))
 
     def A(self):
         return (sp.identity(self.N, format="csr") - self.W).tocsr()
@@ -125,7 +139,7 @@ class OracleOperator:
         return self.W.T.tocsr()
 
 
-def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None) -> OracleOperator:
+def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None, rcv_w=None) -> OracleOperator:
     """Assemble W and c (Section 3.1 eq. (discrete-row), Section 3.2).
 
     parity: pinned by the manufactured tangent test (first-order convergence to
@@ -191,10 +205,11 @@ def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None) -> OracleOperator:
     if rcv is None:
         rcv = np.zeros(0, dtype=np.int64)
     return OracleOperator(dim=dim, n1=n1, n2=n2, n3=n3, W=W, c=c, src=int(src),
-                          rcv=np.asarray(rcv, dtype=np.int64), T=T, s=s)
+                          rcv=np.asarray(rcv, dtype=np.int64), T=T, s=s,
+                          rcv_w=None if rcv_w is None else np.asarray(rcv_w, dtype=np.float64))
 
 
 def assemble_workload(wl, alpha: int) -> OracleOperator:
     """Assemble the operator of source alpha of a workloads.Workload."""
     return assemble(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T[alpha], wl.s, int(wl.src[alpha]),
-                    wl.rcv)
+                    wl.rcv, getattr(wl, "rcv_w", None))

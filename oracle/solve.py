@@ -4,8 +4,10 @@ J_alpha  = P_alpha A_alpha^{-1} C_alpha              (eq. (source-jacobian), M =
 J_alpha^T y = C_alpha^T A_alpha^{-T} P_alpha^T y      (eq. (source-transpose))
 J^T y    = sum_alpha J_alpha^T y_alpha                (Section 4.4, multi-source stacking)
 
-The on-grid source and on-grid receivers make D_alpha = 0 and P_alpha a
-selection (its transpose scatters and adds duplicate receivers).
+The on-grid source makes D_alpha = 0.  P_alpha samples at the receivers:
+a selection for on-grid receivers, or interpolation weights over a few nodes
+per receiver; either way it is the explicit sparse matrix OracleOperator.P()
+and its transpose scatters and adds.
 
 Three independent solvers for A x = q and A^T y = r:
   * gs_solve      Gauss-Seidel directional sweeping to convergence (Section 3.6),
@@ -132,16 +134,14 @@ def apply_J(op, ds: np.ndarray, out: str = "nodes", solver: str = "superlu") -> 
     if out == "nodes":
         return x
     if out == "receivers":
-        return x[op.rcv]
+        return op.P() @ x
     raise ValueError(out)
 
 
 def scatter_receivers(op, y: np.ndarray) -> np.ndarray:
-    """P^T y: receiver values placed at their nodes, duplicates added."""
+    """P^T y: each receiver value times its weights, added at its nodes."""
     y = np.asarray(y, dtype=np.float64)
-    r = np.zeros((op.N,) + y.shape[1:])
-    np.add.at(r, op.rcv, y)
-    return r
+    return op.P().T @ y
 
 
 def apply_JT(op, w: np.ndarray, w_mode: str = "nodes", solver: str = "superlu") -> np.ndarray:

@@ -20,7 +20,8 @@ _ERRNAMES = {FM_EINVAL: "FM_EINVAL", FM_ESINGULAR: "FM_ESINGULAR", FM_ENOMEM: "F
              FM_EHIP: "FM_EHIP", FM_ESTATE: "FM_ESTATE"}
 
 SYMBOLS = (
-    "fm_build_frozen_state", "fm_build_frozen_states", "fm_state_stats",
+    "fm_build_frozen_state", "fm_build_frozen_states", "fm_build_frozen_state_w", "fm_build_frozen_states_w",
+    "fm_state_stats",
     "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
     "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_batch_status", "fm_batch_split_info",
     "fm_apply_J",
@@ -74,6 +75,8 @@ def load():
     sig = {
         "fm_build_frozen_state": (C.c_int, [vp, vp, vp, i64, vp, i32, vp]),
         "fm_build_frozen_states": (C.c_int, [vp, i32, vp, vp, vp, vp, i32, i32, vp]),
+        "fm_build_frozen_state_w": (C.c_int, [vp, vp, vp, i64, vp, vp, i32, i32, vp]),
+        "fm_build_frozen_states_w": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, i32, i32, i32, vp]),
         "fm_state_stats": (C.c_int, [vp, vp]),
         "fm_state_export_operator": (C.c_int, [vp, vp, vp, vp, vp]),
         "fm_state_export_graph": (C.c_int, [vp, vp, vp, vp]),
@@ -184,24 +187,59 @@ class State:
             pass
 
 
-def build_frozen_state(dim, n1, n2, n3, G, T, s, src_node, rcv_nodes=()) -> State:
-    """fm_build_frozen_state with numpy host inputs."""
+def build_frozen_state(dim, n1, n2, n3, G, T, s, src_node, rcv_nodes=(), rcv_weights=None) -> State:
+    """fm_build_frozen_state with numpy host inputs.  With rcv_weights, the
+    receivers interpolate: rcv_nodes and rcv_weights are [R][K] and receiver r
+    samples sum_k rcv_weights[r][k] x[rcv_nodes[r][k]] (fm_build_frozen_state_w)."""
     lib = load()
     G, T, s = _f64(G), _f64(T), _f64(s)
-    rcv = _i64(rcv_nodes)
     g = _grid(dim, n1, n2, n3, G)
     out = C.c_void_p()
-    _check(lib.fm_build_frozen_state(C.byref(g), T.ctypes.data, s.ctypes.data, int(src_node),
-                                     rcv.ctypes.data if rcv.size else None, int(rcv.size), C.byref(out)))
-    return State(out.value, int(n1) * int(n2) * int(n3), dim, (n1, n2, n3), int(rcv.size))
+    if rcv_weights is None:
+        rcv = _i64(rcv_nodes)
+        _check(lib.fm_build_frozen_state(C.byref(g), T.ctypes.data, s.ctypes.data, int(src_node),
+                                         rcv.ctypes.data if rcv.size else None, int(rcv.size), C.byref(out)))
+        R = int(rcv.size)
+    else:
+        rcv = np.ascontiguousarray(rcv_nodes, dtype=np.int64)
+        w = np.ascontiguousarray(rcv_weights, dtype=np.float64)
+        if rcv.ndim != 2 or w.shape != rcv.shape:
+            raise ValueError("interpolating receivers need rcv_nodes and rcv_weights of one shape [R][K]")
+        R, K = rcv.shape
+        _check(lib.fm_build_frozen_state_w(C.byref(g), T.ctypes.data, s.ctypes.data, int(src_node),
+                                           rcv.ctypes.data if rcv.size else None, w.ctypes.data if w.size else None,
+                                           int(R), int(K), C.byref(out)))
+    return State(out.value, int(n1) * int(n2) * int(n3), dim, (n1, n2, n3), int(R))
 
 
-def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nthreads=None):
-    """fm_build_frozen_states: T [S][N]; rcv_nodes [R] (shared) or [S][R]."""
+def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nthreads=None, rcv_weights=None):
+    """fm_build_frozen_states: T [S][N]; rcv_nodes [R] (shared) or [S][R].
+    With rcv_weights (fm_build_frozen_states_w): rcv_nodes and rcv_weights of
+    one shape, [R][K] (shared) or [S][R][K], interpolating receivers."""
     lib = load()
     G, T, s = _f64(G), _f64(T), _f64(s)
     src = _i64(src_nodes)
     S = int(src.shape[0])
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
+    g = _grid(dim, n1, n2, n3, G)
+    outs = (C.c_void_p * S)()
+    N = int(n1) * int(n2) * int(n3)
+    if rcv_weights is not None:
+        rcv = np.asarray(rcv_nodes, dtype=np.int64)
+        w = np.asarray(rcv_weights, dtype=np.float64)
+        if w.shape != rcv.shape or rcv.ndim not in (2, 3):
+            raise ValueError("interpolating receivers need rcv_nodes and rcv_weights of one shape, "
+                             "[R][K] or [S][R][K]")
+        if rcv.ndim == 2:
+            rcv = np.broadcast_to(rcv[None], (S,) + rcv.shape)
+            w = np.broadcast_to(w[None], (S,) + w.shape)
+        rcv, w = np.ascontiguousarray(rcv), np.ascontiguousarray(w)
+        R, K = int(rcv.shape[1]), int(rcv.shape[2])
+        _check(lib.fm_build_frozen_states_w(C.byref(g), S, T.ctypes.data, s.ctypes.data, src.ctypes.data,
+                                            rcv.ctypes.data if rcv.size else None,
+                                            w.ctypes.data if w.size else None, R, K, int(nthreads), outs))
+        return [State(outs[a], N, dim, (n1, n2, n3), R) for a in range(S)]
     if rcv_nodes is None:
         rcv = np.zeros((S, 0), dtype=np.int64)
     else:
@@ -209,14 +247,9 @@ def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nth
         if rcv.ndim == 1:
             rcv = np.broadcast_to(rcv[None, :], (S, rcv.shape[0]))
         rcv = np.ascontiguousarray(rcv)
-    if nthreads is None:
-        nthreads = min(16, os.cpu_count() or 1)
-    g = _grid(dim, n1, n2, n3, G)
-    outs = (C.c_void_p * S)()
     _check(lib.fm_build_frozen_states(C.byref(g), S, T.ctypes.data, s.ctypes.data, src.ctypes.data,
                                       rcv.ctypes.data if rcv.size else None, int(rcv.shape[1]),
                                       int(nthreads), outs))
-    N = int(n1) * int(n2) * int(n3)
     return [State(outs[a], N, dim, (n1, n2, n3), int(rcv.shape[1])) for a in range(S)]
 
 

@@ -30,11 +30,14 @@ struct SrcDev {
     const double* inv;
     const double* invt;
     const void* cal_nat;
-    const int32_t* rcv_node;
-    const int32_t* rcvlvl_ptr;
-    const int32_t* rcv_pos;
-    const int32_t* rcv_idx;
-    int32_t L_f, L_r, n_rcv, pad;
+    const int32_t* rcv_ptr;     // [R + 1] entries of each receiver
+    const int32_t* rcv_node;    // [E] node of each entry
+    const double* rcv_wt;       // [E] weight of each entry
+    const int32_t* rcvlvl_ptr;  // [L_r + 1] sorted entries per reverse level
+    const int32_t* rcv_pos;     // [E] reverse position of each sorted entry
+    const int32_t* rcv_idx;     // [E] receiver of each sorted entry
+    const double* rcv_ew;       // [E] weight of each sorted entry
+    int32_t L_f, L_r, n_rcv, n_ent;
 };
 
 struct DeviceState {

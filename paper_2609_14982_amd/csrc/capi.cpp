@@ -55,19 +55,33 @@ extern "C" {
 
 int fm_build_frozen_state(const fm_grid* g, const double* T, const double* s, int64_t src_node,
                           const int64_t* rcv_nodes, int32_t n_rcv, fm_state** out) {
+    return fm_build_frozen_state_w(g, T, s, src_node, rcv_nodes, nullptr, n_rcv, 1, out);
+}
+
+int fm_build_frozen_state_w(const fm_grid* g, const double* T, const double* s, int64_t src_node,
+                            const int64_t* rcv_nodes, const double* rcv_weights, int32_t n_rcv, int32_t k_per_rcv,
+                            fm_state** out) {
     fm::clear_error();
     if (!out) { fm::set_error("null output pointer"); return FM_EINVAL; }
     *out = nullptr;
-    return fm::build_state(g, T, s, src_node, rcv_nodes, n_rcv, out);
+    return fm::build_state(g, T, s, src_node, rcv_nodes, rcv_weights, n_rcv, k_per_rcv, out);
 }
 
 int fm_build_frozen_states(const fm_grid* g, int32_t S, const double* T, const double* s,
                            const int64_t* src_nodes, const int64_t* rcv_nodes, int32_t n_rcv,
                            int32_t nthreads, fm_state** out) {
+    return fm_build_frozen_states_w(g, S, T, s, src_nodes, rcv_nodes, nullptr, n_rcv, 1, nthreads, out);
+}
+
+int fm_build_frozen_states_w(const fm_grid* g, int32_t S, const double* T, const double* s,
+                             const int64_t* src_nodes, const int64_t* rcv_nodes, const double* rcv_weights,
+                             int32_t n_rcv, int32_t k_per_rcv, int32_t nthreads, fm_state** out) {
     fm::clear_error();
     if (!g || !T || !s || !src_nodes || !out || S < 1) { fm::set_error("bad arguments"); return FM_EINVAL; }
     if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) { fm::set_error("grid sizes must be >= 1"); return FM_EINVAL; }
+    if (k_per_rcv < 1) { fm::set_error("entries per receiver must be >= 1"); return FM_EINVAL; }
     const int64_t N = g->n1 * g->n2 * g->n3;
+    const size_t per_src = (size_t)(n_rcv > 0 ? n_rcv : 0) * (size_t)k_per_rcv;
     std::vector<fm_state*> res(S, nullptr);
     std::vector<int> rcs(S, FM_OK);
     std::vector<std::string> msgs(S);
@@ -78,8 +92,10 @@ int fm_build_frozen_states(const fm_grid* g, int32_t S, const double* T, const d
             int32_t a = next.fetch_add(1);
             if (a >= S) break;
             fm_state* st = nullptr;
-            int rc = fm_build_frozen_state(g, T + (size_t)a * N, s, src_nodes[a],
-                                           n_rcv > 0 ? rcv_nodes + (size_t)a * n_rcv : nullptr, n_rcv, &st);
+            int rc = fm_build_frozen_state_w(g, T + (size_t)a * N, s, src_nodes[a],
+                                             n_rcv > 0 ? rcv_nodes + (size_t)a * per_src : nullptr,
+                                             n_rcv > 0 && rcv_weights ? rcv_weights + (size_t)a * per_src : nullptr,
+                                             n_rcv, k_per_rcv, &st);
             rcs[a] = rc;
             res[a] = st;
             if (rc != FM_OK) msgs[a] = fm_last_error();

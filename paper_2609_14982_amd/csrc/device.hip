@@ -92,10 +92,13 @@ int upload_state(HostState* st) {
     size_t o_inv = ar.add<double>(pk.inv.size());
     size_t o_invt = ar.add<double>(pk.invt.size());
     size_t o_cal = ar.add<double>(pk.cal_nat.size());
+    size_t o_rptr = ar.add<int32_t>(pk.rcv_ptr.size());
     size_t o_rn = ar.add<int32_t>(pk.rcv_node.size());
+    size_t o_rwt = ar.add<double>(pk.rcv_wt.size());
     size_t o_rlv = ar.add<int32_t>(pk.rcvlvl_ptr.size());
     size_t o_rp = ar.add<int32_t>(pk.rcv_pos.size());
     size_t o_ri = ar.add<int32_t>(pk.rcv_idx.size());
+    size_t o_rew = ar.add<double>(pk.rcv_ew.size());
     size_t total = ar.add<char>(0) + 256;
     DeviceState* ds = new DeviceState();
     hipError_t e = hipMalloc(&ds->blob, total);
@@ -126,10 +129,13 @@ int upload_state(HostState* st) {
     rc = rc ? rc : put(b, o_inv, pk.inv);
     rc = rc ? rc : put(b, o_invt, pk.invt);
     rc = rc ? rc : put(b, o_cal, pk.cal_nat);
+    rc = rc ? rc : put(b, o_rptr, pk.rcv_ptr);
     rc = rc ? rc : put(b, o_rn, pk.rcv_node);
+    rc = rc ? rc : put(b, o_rwt, pk.rcv_wt);
     rc = rc ? rc : put(b, o_rlv, pk.rcvlvl_ptr);
     rc = rc ? rc : put(b, o_rp, pk.rcv_pos);
     rc = rc ? rc : put(b, o_ri, pk.rcv_idx);
+    rc = rc ? rc : put(b, o_rew, pk.rcv_ew);
     if (rc != FM_OK) {
         (void)hipFree(ds->blob);
         delete ds;
@@ -156,13 +162,17 @@ int upload_state(HostState* st) {
     d.inv = (const double*)(b + o_inv);
     d.invt = (const double*)(b + o_invt);
     d.cal_nat = b + o_cal;
+    d.rcv_ptr = (const int32_t*)(b + o_rptr);
     d.rcv_node = (const int32_t*)(b + o_rn);
+    d.rcv_wt = (const double*)(b + o_rwt);
     d.rcvlvl_ptr = (const int32_t*)(b + o_rlv);
     d.rcv_pos = (const int32_t*)(b + o_rp);
     d.rcv_idx = (const int32_t*)(b + o_ri);
+    d.rcv_ew = (const double*)(b + o_rew);
     d.L_f = pk.L_f;
     d.L_r = pk.L_r;
-    d.n_rcv = (int32_t)pk.rcv_node.size();
+    d.n_rcv = (int32_t)pk.rcv_ptr.size() - 1;
+    d.n_ent = (int32_t)pk.rcv_node.size();
     ds->device = dev;
     st->dev = ds;
     return FM_OK;
@@ -217,7 +227,9 @@ void free_device_state(HostState* st) {
 
 namespace fm {
 
-// out[alpha][r][b] = X[alpha][rcv_alpha(r)][b]  (P_alpha, Section 4.4)
+// out[alpha][r][b] = sum_e w_e X[alpha][node_e][b] over receiver r's
+// entries, in entry order (P_alpha, Section 4.4; a selection when each
+// receiver has one entry of weight 1)
 template <typename V>
 __global__ void k_gather_receivers(ApplyArgs a) {
     const int64_t total = (int64_t)a.S * a.R * a.B;
@@ -226,8 +238,12 @@ __global__ void k_gather_receivers(ApplyArgs a) {
         const int64_t b = t % a.B;
         const int64_t rr = (t / a.B) % a.R;
         const int64_t alpha = t / ((int64_t)a.B * a.R);
-        const int32_t node = a.src[alpha].rcv_node[rr];
-        ((V*)a.out)[t] = ((const V*)a.work)[(alpha * a.N + node) * a.B + b];
+        const SrcDev& sd = a.src[alpha];
+        const V* x = (const V*)a.work + alpha * a.N * a.B + b;
+        V acc = (V)0;
+        for (int32_t e = sd.rcv_ptr[rr]; e < sd.rcv_ptr[rr + 1]; ++e)
+            acc += (V)sd.rcv_wt[e] * x[(int64_t)sd.rcv_node[e] * a.B];
+        ((V*)a.out)[t] = acc;
     }
 }
 
@@ -516,8 +532,10 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     b->split_items = b->S * P;
     // receiver inputs of the transpose in LDS when they fit in 64 KB (values
     // as FP64, then the int32 positions), the block staging area after them
-    const size_t rcv_bytes = (size_t)b->R * b->B * sizeof(double) + (size_t)b->R * sizeof(int32_t);
-    b->split_rcv_lds = b->R > 0 && rcv_bytes <= 64 * 1024;
+    size_t n_ent = 0;
+    for (HostState* st : b->states) n_ent = std::max(n_ent, st->pk.rcv_node.size());
+    const size_t rcv_bytes = n_ent * b->B * sizeof(double) + n_ent * sizeof(int32_t);
+    b->split_rcv_lds = n_ent > 0 && rcv_bytes <= 64 * 1024;
     b->split_stage_off = b->split_rcv_lds ? (int32_t)(((rcv_bytes + 255) & ~(size_t)255) / sizeof(double)) : 0;
     const size_t lds_all = std::min<size_t>(lds + (size_t)b->split_stage_off * sizeof(double), (size_t)lds_cap);
     b->split_lds = lds_all;
@@ -556,13 +574,13 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     if (precision != FM_FP64 && precision != FM_FP32) { set_error("precision must be 64 or 32"); return FM_EINVAL; }
     HostState* s0 = static_cast<HostState*>(states[0]);
     if (!s0) { set_error("null state"); return FM_EINVAL; }
-    int32_t R = (int32_t)s0->pk.rcv_node.size();
+    int32_t R = (int32_t)s0->pk.rcv_ptr.size() - 1;
     int32_t maxk = 0;
     for (int32_t i = 0; i < S; i++) {
         HostState* si = static_cast<HostState*>(states[i]);
         if (!si) { set_error("null state %d", i); return FM_EINVAL; }
         if (!si->same_grid(*s0)) { set_error("state %d has another grid shape", i); return FM_EINVAL; }
-        if ((int32_t)si->pk.rcv_node.size() != R) { set_error("state %d has another receiver count", i); return FM_EINVAL; }
+        if ((int32_t)si->pk.rcv_ptr.size() - 1 != R) { set_error("state %d has another receiver count", i); return FM_EINVAL; }
         maxk = std::max(maxk, si->pk.max_blk_k);
     }
     fm_tuning t{};

@@ -62,11 +62,15 @@ struct Packed {
     std::vector<double> inv;           // A_C^{-1}, column-major (entry (i,j) at j*k + i)
     std::vector<double> invt;          // the same matrix row-major (entry (i,j) at i*k + j)
     std::vector<double> cal_nat;       // [N] calibration in natural order
-    // receivers
-    std::vector<int32_t> rcv_node;     // [R]
-    std::vector<int32_t> rcvlvl_ptr;   // [L_r + 1] range of receiver entries per reverse level
-    std::vector<int32_t> rcv_pos;      // reverse position of each entry (sorted)
-    std::vector<int32_t> rcv_idx;      // receiver index of each entry
+    // receivers: receiver r samples sum_e rcv_wt[e] x[rcv_node[e]] over its
+    // entries e in [rcv_ptr[r], rcv_ptr[r+1]) (a selection: one entry of weight 1)
+    std::vector<int32_t> rcv_ptr;      // [R + 1]
+    std::vector<int32_t> rcv_node;     // [E] node of each entry
+    std::vector<double> rcv_wt;        // [E] weight of each entry
+    std::vector<int32_t> rcvlvl_ptr;   // [L_r + 1] range of the sorted entries per reverse level
+    std::vector<int32_t> rcv_pos;      // [E] reverse position of each entry (sorted)
+    std::vector<int32_t> rcv_idx;      // [E] receiver of each sorted entry
+    std::vector<double> rcv_ew;        // [E] weight of each sorted entry
     int32_t max_blk_k = 0;
     int64_t max_level_nodes = 0;
 };
@@ -105,8 +109,10 @@ struct fm_state : fm::HostState {};
 namespace fm {
 
 // Host setup (setup.cpp).  Returns FM_OK or an FM_E* code with the message set.
+// Receiver r is sum_k rcv_w[r*K + k] x[rcv[r*K + k]] (rcv_w NULL: weights 1);
+// entries of weight 0 are dropped.
 int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
-                const int64_t* rcv, int32_t n_rcv, fm_state** out);
+                const int64_t* rcv, const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out);
 
 // Natural-order records of the full operator (W for fwd, W^T otherwise) in
 // the packed record format, for the directional-sweeping comparison baseline.

@@ -162,7 +162,7 @@ void lu_inverse(int k, const double* lu, const int32_t* piv, double* x) {
 }
 
 int validate(const fm_grid* g, const double* T, const double* s, int64_t src, const int64_t* rcv,
-             int32_t n_rcv, Grid& gr) {
+             const double* rcv_w, int32_t n_rcv, int32_t K, Grid& gr) {
     if (!g || !g->G || !T || !s) { set_error("null argument"); return FM_EINVAL; }
     if (g->dim != 2 && g->dim != 3) { set_error("dim must be 2 or 3, got %d", g->dim); return FM_EINVAL; }
     if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) { set_error("grid sizes must be >= 1"); return FM_EINVAL; }
@@ -180,8 +180,18 @@ int validate(const fm_grid* g, const double* T, const double* s, int64_t src, co
     if (gr.N >= (int64_t)kNodeMask) { set_error("grid too large: %lld nodes", (long long)gr.N); return FM_EINVAL; }
     if (src < 0 || src >= gr.N) { set_error("source node %lld out of range", (long long)src); return FM_EINVAL; }
     if (n_rcv < 0 || (n_rcv > 0 && !rcv)) { set_error("bad receiver list"); return FM_EINVAL; }
-    for (int32_t r = 0; r < n_rcv; r++)
-        if (rcv[r] < 0 || rcv[r] >= gr.N) { set_error("receiver %d node %lld out of range", r, (long long)rcv[r]); return FM_EINVAL; }
+    if (K < 1 || K > 64) { set_error("entries per receiver must be 1 to 64, got %d", K); return FM_EINVAL; }
+    for (int64_t e = 0; e < (int64_t)n_rcv * K; e++) {
+        if (rcv[e] < 0 || rcv[e] >= gr.N) {
+            set_error("receiver %lld entry %lld: node %lld out of range", (long long)(e / K), (long long)(e % K),
+                      (long long)rcv[e]);
+            return FM_EINVAL;
+        }
+        if (rcv_w && !std::isfinite(rcv_w[e])) {
+            set_error("receiver %lld entry %lld: weight is not finite", (long long)(e / K), (long long)(e % K));
+            return FM_EINVAL;
+        }
+    }
     for (int64_t p = 0; p < gr.N; p++) {
         if (!std::isfinite(T[p])) { set_error("T[%lld] is not finite", (long long)p); return FM_EINVAL; }
         if (!(s[p] > 0.0) || !std::isfinite(s[p])) { set_error("s[%lld] must be finite and > 0", (long long)p); return FM_EINVAL; }
@@ -198,12 +208,12 @@ int validate(const fm_grid* g, const double* T, const double* s, int64_t src, co
 }  // namespace
 
 int build_state(const fm_grid* g, const double* T, const double* s, int64_t src, const int64_t* rcv,
-                int32_t n_rcv, fm_state** out) {
+                const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out) {
     auto t0 = std::chrono::steady_clock::now();
     if (!out) { set_error("null output pointer"); return FM_EINVAL; }
     *out = nullptr;
     Grid gr;
-    int rc = validate(g, T, s, src, rcv, n_rcv, gr);
+    int rc = validate(g, T, s, src, rcv, rcv_w, n_rcv, K, gr);
     if (rc != FM_OK) return rc;
     fm_state* st = new (std::nothrow) fm_state();
     if (!st) { set_error("out of host memory"); return FM_ENOMEM; }
@@ -553,23 +563,45 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                        pk.blk_rpos, rpos_of, L_r);
         pk.cal_nat = st->cal;
 
-        // receivers: P^T entries sorted by reverse position, grouped per reverse level
-        pk.rcv_node.resize(n_rcv);
-        std::vector<std::pair<int32_t, int32_t>> ent(n_rcv);
+        // receivers (P_alpha, Section 4.4): the entries of each receiver in
+        // receiver order for the primal gather; for P^T the same entries
+        // sorted by reverse position (stable: receiver order within a node),
+        // grouped per reverse level
+        pk.rcv_ptr.assign((size_t)n_rcv + 1, 0);
+        pk.rcv_node.clear();
+        pk.rcv_wt.clear();
+        std::vector<int32_t> ent_rcv;
         for (int32_t r = 0; r < n_rcv; r++) {
-            pk.rcv_node[r] = (int32_t)rcv[r];
-            ent[r] = {rpos_of[rcv[r]], r};
-            pk.rmeta[rpos_of[rcv[r]]] |= kRcvFlag;
+            for (int32_t k = 0; k < K; k++) {
+                const int64_t e = (int64_t)r * K + k;
+                const double w = rcv_w ? rcv_w[e] : 1.0;
+                if (w == 0.0) continue;
+                pk.rcv_node.push_back((int32_t)rcv[e]);
+                pk.rcv_wt.push_back(w);
+                ent_rcv.push_back(r);
+            }
+            pk.rcv_ptr[r + 1] = (int32_t)pk.rcv_node.size();
+        }
+        const int32_t n_ent = (int32_t)pk.rcv_node.size();
+        std::vector<std::pair<int32_t, int32_t>> ent(n_ent);
+        for (int32_t e = 0; e < n_ent; e++) {
+            ent[e] = {rpos_of[pk.rcv_node[e]], e};
+            pk.rmeta[rpos_of[pk.rcv_node[e]]] |= kRcvFlag;
         }
         std::sort(ent.begin(), ent.end());
-        pk.rcv_pos.resize(n_rcv);
-        pk.rcv_idx.resize(n_rcv);
-        for (int32_t e = 0; e < n_rcv; e++) { pk.rcv_pos[e] = ent[e].first; pk.rcv_idx[e] = ent[e].second; }
+        pk.rcv_pos.resize(n_ent);
+        pk.rcv_idx.resize(n_ent);
+        pk.rcv_ew.resize(n_ent);
+        for (int32_t e = 0; e < n_ent; e++) {
+            pk.rcv_pos[e] = ent[e].first;
+            pk.rcv_idx[e] = ent_rcv[ent[e].second];
+            pk.rcv_ew[e] = pk.rcv_wt[ent[e].second];
+        }
         pk.rcvlvl_ptr.assign(L_r + 1, 0);
         {
             int32_t e = 0;
             for (int32_t l = 0; l < L_r; l++) {
-                while (e < n_rcv && pk.rcv_pos[e] < pk.rlvl_ptr[l + 1]) e++;
+                while (e < n_ent && pk.rcv_pos[e] < pk.rlvl_ptr[l + 1]) e++;
                 pk.rcvlvl_ptr[l + 1] = e;
             }
         }

@@ -198,8 +198,9 @@ __device__ __forceinline__ void fetch32(Node32<V, VW>& p, uint64_t m, int pos, c
                 for (int e = d.e0; e < d.e1; ++e)
                     if (gld(sd.rcv_pos + (e)) == pos) {
                         const Pack<V, VW> y = ld<V, VW>(in + (int64_t)gld(sd.rcv_idx + (e)) * cx.B + cx.rhs0);
+                        const V w = (V)gld(sd.rcv_ew + (e));
 #pragma unroll
-                        for (int v = 0; v < VW; ++v) p.inp.v[v] += y.v[v];
+                        for (int v = 0; v < VW; ++v) p.inp.v[v] += w * y.v[v];
                     }
             }
         }
@@ -546,20 +547,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     sx.a0 = (int32_t)ROWB;
     sx.a1 = (int32_t)(a.st1 * ROWB);
     sx.a2 = (int32_t)(a.st2 * ROWB);
-    // transpose from receiver data: copy this source's R x B inputs (in the
-    // receiver-entry order of the reverse levels) and their positions to LDS
+    // transpose from receiver data: copy this source's receiver entries (in
+    // the order of the reverse levels), each input value times the entry's
+    // weight, and their positions to LDS
     RcvLds rl;
     rl.on = DIR == kRev && cx.rcv_in && s.rcv_lds != 0;
     rl.rv = lds;
-    rl.rpos = reinterpret_cast<const int32_t*>(lds + (size_t)a.R * B);
+    rl.rpos = reinterpret_cast<const int32_t*>(lds + (size_t)sd.n_ent * B);
     if (rl.on) {
         double* rv = lds;
-        int32_t* rpos = reinterpret_cast<int32_t*>(lds + (size_t)a.R * B);
-        for (int t = threadIdx.x; t < a.R * B; t += NT) {
+        int32_t* rpos = reinterpret_cast<int32_t*>(lds + (size_t)sd.n_ent * B);
+        for (int t = threadIdx.x; t < sd.n_ent * B; t += NT) {
             const int e = t / B, b = t - e * B;
-            rv[t] = (double)in[(int64_t)gld(sd.rcv_idx + (e)) * B + b];
+            rv[t] = gld(sd.rcv_ew + (e)) * (double)in[(int64_t)gld(sd.rcv_idx + (e)) * B + b];
         }
-        for (int t = threadIdx.x; t < a.R; t += NT) rpos[t] = gld(sd.rcv_pos + (t));
+        for (int t = threadIdx.x; t < sd.n_ent; t += NT) rpos[t] = gld(sd.rcv_pos + (t));
         __syncthreads();
     }
 

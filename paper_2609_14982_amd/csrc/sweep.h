@@ -101,8 +101,9 @@ __device__ __forceinline__ void fetch_static(NodeOps<V, VW>& p, uint64_t m, int 
             for (int e = d.e0; e < d.e1; ++e)
                 if (sd.rcv_pos[e] == pos) {
                     const Pack<V, VW> y = ld<V, VW>(in + (int64_t)sd.rcv_idx[e] * cx.B + cx.rhs0);
+                    const V w = (V)sd.rcv_ew[e];
 #pragma unroll
-                    for (int v = 0; v < VW; ++v) p.inp.v[v] += y.v[v];
+                    for (int v = 0; v < VW; ++v) p.inp.v[v] += w * y.v[v];
                 }
     }
 }

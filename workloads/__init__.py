@@ -15,6 +15,7 @@ from .grids import (  # noqa: F401
     curved_state,
     eikonal,
     flat_radial,
+    interpolating_receivers,
     manufactured,
     metric_from_coords,
     mu_g,

@@ -67,6 +67,9 @@ class Workload:
     seed: int = 0
     T: np.ndarray | None = None   # [S][N] background traveltime
     meta: dict = field(default_factory=dict)
+    # interpolating receivers: rcv is then [R][K] nodes and rcv_w [R][K]
+    # weights (receiver r samples sum_k rcv_w[r][k] x[rcv[r][k]])
+    rcv_w: np.ndarray | None = None
 
     @property
     def N(self) -> int:
@@ -224,6 +227,29 @@ def data_noise(shape, rng: np.random.Generator) -> np.ndarray:
 # --------------------------------------------------------------------------
 # grids
 # --------------------------------------------------------------------------
+
+def interpolating_receivers(wl: Workload, R: int, seed: int):
+    """R receivers at seeded points of the surface (logical k = 0) between
+    nodes: logical coordinates uniform over the surface, each receiver
+    sampling the bilinear (3-D, 4 nodes) or linear (2-D, 2 nodes) interpolant
+    of the surface cell around it, in logical coordinates.  Returns
+    (nodes [R][K] int64, weights [R][K], coordinates [R][dim-1])."""
+    rng = np.random.default_rng(seed)
+    xi = rng.uniform(0.0, wl.n1 - 1, R)
+    i0 = np.minimum(np.floor(xi).astype(np.int64), wl.n1 - 2)
+    fx = xi - i0
+    if wl.dim == 2:
+        nodes = np.stack([i0, i0 + 1], axis=1)
+        w = np.stack([1.0 - fx, fx], axis=1)
+        return nodes, w, xi[:, None]
+    eta = rng.uniform(0.0, wl.n2 - 1, R)
+    j0 = np.minimum(np.floor(eta).astype(np.int64), wl.n2 - 2)
+    fy = eta - j0
+    n1 = wl.n1
+    nodes = np.stack([i0 + n1 * j0, i0 + 1 + n1 * j0, i0 + n1 * (j0 + 1), i0 + 1 + n1 * (j0 + 1)], axis=1)
+    w = np.stack([(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy), (1.0 - fx) * fy, fx * fy], axis=1)
+    return nodes, w, np.stack([xi, eta], axis=1)
+
 
 def _lattice(n: int, m: int) -> np.ndarray:
     return np.rint((np.arange(m) + 0.5) * (n - 1) / m).astype(np.int64)
