@@ -301,6 +301,39 @@ int fm_lsqr_replay(fm_lsqr* L);
 int fm_lsqr_buffers(const fm_lsqr* L, void** x, void** u, void** v, double** scalars);
 void fm_lsqr_free(fm_lsqr* L);
 
+/*
+ * Cell-velocity model map M_alpha (Section 4.4, eq. (source-jacobian)): the
+ * model is one velocity per cell of the logical grid (hexahedra between
+ * nodes, quadrilaterals in 2-D; cell id ci + (n1-1) (cj + (n2-1) ck), 2-D
+ * ci + (n1-1) ck), and a node's slowness is the reciprocal of the mean
+ * velocity of the 1, 2, 4 or 8 cells that share it.  The map linearises this
+ * at the given velocities:
+ *   (M dv)_p  = a_p sum_{cells c of node p} dv_c,   a_p = -1 / (n_p vbar_p^2)
+ *   (M^T g)_c = sum_{nodes p of cell c} a_p g_p
+ * M is shared by all sources, so J M is fm_apply_J of the broadcast block
+ * M dv, and M^T follows fm_apply_JT's summed output.
+ *   create     dim, n1, n2, n3 as in fm_grid (every axis of the grid >= 2
+ *              nodes); v_cell host [n_cells] finite and > 0 (copied);
+ *              hip_stream: where the applies run; uses the current device
+ *   sizes      node and cell counts
+ *   slowness   host s_out [N]: the background nodal slowness 1 / vbar
+ *   apply      device dv [n_cells][B] -> ds [N][B]; apply_T device
+ *              g [N][B] -> out [n_cells][B]; FP64 or FP32 (precision as in
+ *              fm_batch_create); asynchronous on the map's stream; no
+ *              allocation; outputs fully overwritten
+ * Errors: FM_EINVAL (shape, velocity not finite or <= 0, null pointer, B < 1),
+ * FM_ESTATE (another current device), FM_ENOMEM, FM_EHIP.
+ */
+typedef struct fm_model_map fm_model_map;
+int fm_model_map_create(int32_t dim, int64_t n1, int64_t n2, int64_t n3, const double* v_cell, void* hip_stream,
+                        fm_model_map** out);
+int fm_model_map_sizes(const fm_model_map* m, int64_t* n_nodes, int64_t* n_cells);
+int fm_model_map_slowness(const fm_model_map* m, double* s_out);
+int fm_model_map_set_stream(fm_model_map* m, void* hip_stream);
+int fm_model_map_apply(fm_model_map* m, int32_t B, int32_t precision, const void* dv, void* ds);
+int fm_model_map_apply_T(fm_model_map* m, int32_t B, int32_t precision, const void* g, void* dv_out);
+void fm_model_map_free(fm_model_map* m);
+
 /* Free a batch (its scratch); the states stay valid. */
 void fm_batch_free(fm_batch* b);
 

@@ -21,6 +21,7 @@ from .binding import (  # noqa: F401
     autotune,
     FmError,
     Lsqr,
+    ModelMap,
     State,
     build_frozen_state,
     build_frozen_states,

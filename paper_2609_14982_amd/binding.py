@@ -28,6 +28,8 @@ SYMBOLS = (
     "fm_apply_JT", "fm_apply_J_sweep", "fm_apply_JT_sweep", "fm_batch_free", "fm_last_error",
     "fm_lsqr_create", "fm_lsqr_start", "fm_lsqr_iterate", "fm_lsqr_capture", "fm_lsqr_replay",
     "fm_lsqr_buffers", "fm_lsqr_free", "fm_autotune",
+    "fm_model_map_create", "fm_model_map_sizes", "fm_model_map_slowness", "fm_model_map_set_stream",
+    "fm_model_map_apply", "fm_model_map_apply_T", "fm_model_map_free",
 )
 
 
@@ -101,6 +103,13 @@ def load():
         "fm_lsqr_buffers": (C.c_int, [vp, vp, vp, vp, vp]),
         "fm_lsqr_free": (None, [vp]),
         "fm_last_error": (C.c_char_p, []),
+        "fm_model_map_create": (C.c_int, [i32, i64, i64, i64, vp, vp, vp]),
+        "fm_model_map_sizes": (C.c_int, [vp, vp, vp]),
+        "fm_model_map_slowness": (C.c_int, [vp, vp]),
+        "fm_model_map_set_stream": (C.c_int, [vp, vp]),
+        "fm_model_map_apply": (C.c_int, [vp, i32, i32, vp, vp]),
+        "fm_model_map_apply_T": (C.c_int, [vp, i32, i32, vp, vp]),
+        "fm_model_map_free": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -385,6 +394,60 @@ class Batch:
     def free(self):
         if getattr(self, "_ptr", None) is not None and self._ptr.value:
             load().fm_batch_free(self._ptr)
+            self._ptr = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class ModelMap:
+    """fm_model_map*: cell velocities -> nodal slowness, linearised (M of
+    Section 4.4, eq. (source-jacobian)) and its transpose, on the GPU."""
+
+    def __init__(self, dim, n1, n2, n3, v_cell, stream=None):
+        import torch
+        lib = load()
+        v = _f64(v_cell)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        out = C.c_void_p()
+        _check(lib.fm_model_map_create(int(dim), int(n1), int(n2), int(n3), v.ctypes.data,
+                                       C.c_void_p(stream.cuda_stream), C.byref(out)))
+        self._ptr = out
+        nn, nc = C.c_int64(), C.c_int64()
+        _check(lib.fm_model_map_sizes(out, C.byref(nn), C.byref(nc)))
+        self.N, self.n_cells = int(nn.value), int(nc.value)
+
+    def slowness(self) -> np.ndarray:
+        s = np.empty(self.N, dtype=np.float64)
+        _check(load().fm_model_map_slowness(self._ptr, s.ctypes.data))
+        return s
+
+    def set_stream(self, stream):
+        _check(load().fm_model_map_set_stream(self._ptr, C.c_void_p(stream.cuda_stream)))
+
+    def _prec(self, t):
+        import torch
+        return FM_FP64 if t.dtype == torch.float64 else FM_FP32
+
+    def apply(self, dv, ds):
+        """ds [N][B] = M dv [n_cells][B] (device tensors of one dtype)."""
+        B = int(dv.shape[1])
+        _check(load().fm_model_map_apply(self._ptr, B, self._prec(dv), _dptr(dv, dv.dtype, (self.n_cells, B), "dv"),
+                                         _dptr(ds, dv.dtype, (self.N, B), "ds")))
+
+    def apply_T(self, g, out):
+        """out [n_cells][B] = M^T g [N][B]."""
+        B = int(g.shape[1])
+        _check(load().fm_model_map_apply_T(self._ptr, B, self._prec(g), _dptr(g, g.dtype, (self.N, B), "g"),
+                                           _dptr(out, g.dtype, (self.n_cells, B), "out")))
+
+    def free(self):
+        if self._ptr and self._ptr.value:
+            load().fm_model_map_free(self._ptr)
             self._ptr = C.c_void_p(None)
 
     def __del__(self):

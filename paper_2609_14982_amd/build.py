@@ -40,7 +40,7 @@ def build(verbose: bool = False) -> str:
         _run(["g++", *HOST_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj],
              verbose)
         objs.append(obj)
-    for src in ("device.hip", "krylov.hip"):
+    for src in ("device.hip", "krylov.hip", "model_map.hip"):
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         _run([HIPCC, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj],
              verbose)

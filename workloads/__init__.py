@@ -11,6 +11,7 @@ perturbation / data vectors.
 from .grids import (  # noqa: F401
     Workload,
     build,
+    cell_velocities,
     config,
     curved_state,
     eikonal,

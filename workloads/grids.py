@@ -228,6 +228,21 @@ def data_noise(shape, rng: np.random.Generator) -> np.ndarray:
 # grids
 # --------------------------------------------------------------------------
 
+def cell_velocities(wl: Workload) -> np.ndarray:
+    """A cell-velocity model from the workload's nodal slowness: each cell
+    (hexahedron, or quadrilateral in 2-D, between logical neighbours; cell id
+    ci + (n1-1) (cj + (n2-1) ck)) gets the mean of 1/s over its corners."""
+    v = 1.0 / np.asarray(wl.s, dtype=np.float64)
+    if wl.dim == 3:
+        g = v.reshape(wl.n3, wl.n2, wl.n1)
+        c = sum(g[k:k + wl.n3 - 1, j:j + wl.n2 - 1, i:i + wl.n1 - 1]
+                for k in (0, 1) for j in (0, 1) for i in (0, 1)) / 8.0
+    else:
+        g = v.reshape(wl.n3, wl.n1)
+        c = sum(g[k:k + wl.n3 - 1, i:i + wl.n1 - 1] for k in (0, 1) for i in (0, 1)) / 4.0
+    return np.ascontiguousarray(c.reshape(-1))
+
+
 def interpolating_receivers(wl: Workload, R: int, seed: int):
     """R receivers at seeded points of the surface (logical k = 0) between
     nodes: logical coordinates uniform over the surface, each receiver
