@@ -55,7 +55,7 @@ class fm_stats(C.Structure):
 class fm_tuning(C.Structure):
     _fields_ = [("rhs_per_group", C.c_int32), ("threads", C.c_int32),
                 ("min_lds_bytes", C.c_int32), ("xcd_aware", C.c_int32), ("unroll", C.c_int32),
-                ("split", C.c_int32)]
+                ("split", C.c_int32), ("balance", C.c_int32)]
 
 
 _lib = None

@@ -77,6 +77,7 @@ struct fm_batch {
     int64_t stage_rows = 0;
     void* stage = nullptr;           // [S][stage_rows][B] FP64 block right-hand sides
     unsigned* sync = nullptr;        // counters [S*32], XCD masks [S*32], abort word
+    int32_t* wg_map = nullptr;       // balanced split: [grid] source << 8 | part (-1 idle), then [S] P per source
 };
 
 namespace fm {

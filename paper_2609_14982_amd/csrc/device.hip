@@ -444,6 +444,8 @@ static hipError_t launch_split(const fm_batch* b, bool fwd, const ApplyArgs& a0)
     s.lds_rows = b->split_lds_rows;
     s.rcv_lds = b->split_rcv_lds;
     s.stage_off = b->split_stage_off;
+    s.wg_map = b->wg_map;
+    s.src_P = b->wg_map ? b->wg_map + b->split_grid : nullptr;
     const size_t vbytes = b->prec == FM_FP64 ? 8 : 4;
     s.inv_l1 = ((size_t)b->B * vbytes) % 128 != 0 || ((uintptr_t)a.work & 127u) != 0;
     hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(256), 0, b->stream, s, b->S);
@@ -508,7 +510,77 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     const int64_t per8 = (b->S + 7) / 8;
     auto fits = [&](int P) { return 8 * per8 * P <= cap; };
     int P = t.split;
-    if (P == 0) {
+    std::vector<int32_t> wg_map, src_P;     // balanced split only
+    if (asked.balance) {
+        const int64_t slots = cap / 8;          // resident workgroups per XCD
+        if (slots < 2 * per8) {
+            set_error("balanced split: %lld sources per XCD need 2 workgroups each; an XCD holds %lld",
+                      (long long)per8, (long long)slots);
+            return FM_EINVAL;
+        }
+        // predicted time of a source on p workgroups: node work / p (a
+        // workgroup streams ~0.094 * threads nodes per us), ~3 us per level,
+        // block products (8 sum k^2 bytes at ~18 GB/s per 512 threads) / p
+        const double h = 0.094 * nt;
+        std::vector<double> fixed(b->S), work(b->S);
+        for (int32_t i = 0; i < b->S; i++) {
+            const HostState* st = b->states[i];
+            fixed[i] = 3.0 * (double)std::max(st->stats.levels_fwd, st->stats.levels_rev);
+            work[i] = (double)st->N / h + 8.0 * (double)st->stats.sum_k2 / (35.0 * nt);
+        }
+        auto cost = [&](int32_t i, int p) { return work[i] / p + fixed[i]; };
+        // deal the sources to the XCDs in snake order of cost at the mean split
+        std::vector<int32_t> order(b->S);
+        for (int32_t i = 0; i < b->S; i++) order[i] = i;
+        const int pm = (int)std::max<int64_t>(2, slots / per8);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost(x, pm) > cost(y, pm); });
+        std::vector<std::vector<int32_t>> on(8);
+        for (int32_t r = 0; r < b->S; r++) {
+            const int32_t lap = r / 8, pos = r % 8;
+            on[lap % 2 == 0 ? pos : 7 - pos].push_back(order[r]);
+        }
+        src_P.assign(b->S, 0);
+        wg_map.assign((size_t)8 * slots, -1);
+        for (int x = 0; x < 8; x++) {
+            std::vector<int32_t>& v = on[x];
+            if (v.empty()) continue;
+            const int64_t n = (int64_t)v.size();
+            const int pmax = 16;
+            for (int32_t i : v) src_P[i] = (int32_t)std::min<int64_t>(pmax, slots / n);
+            int64_t used = 0;
+            for (int32_t i : v) used += src_P[i];
+            // hand out the remaining slots to the slowest sources, then move
+            // workgroups from the fastest to the slowest while that helps
+            for (;;) {
+                int32_t worst = -1;
+                for (int32_t i : v)
+                    if (src_P[i] < pmax && (worst < 0 || cost(i, src_P[i]) > cost(worst, src_P[worst]))) worst = i;
+                if (worst < 0 || used >= slots) break;
+                src_P[worst]++;
+                used++;
+            }
+            for (int it = 0; it < 1024; it++) {
+                int32_t hi = v[0], lo = -1;
+                for (int32_t i : v)
+                    if (cost(i, src_P[i]) > cost(hi, src_P[hi])) hi = i;
+                for (int32_t i : v)
+                    if (i != hi && src_P[i] > 2 && (lo < 0 || cost(i, src_P[i] - 1) < cost(lo, src_P[lo] - 1))) lo = i;
+                if (lo < 0 || src_P[hi] >= pmax) break;
+                if (std::max(cost(hi, src_P[hi] + 1), cost(lo, src_P[lo] - 1)) >= cost(hi, src_P[hi])) break;
+                src_P[hi]++;
+                src_P[lo]--;
+            }
+            int64_t j = 0;
+            for (int32_t i : v)
+                for (int32_t q = 0; q < src_P[i]; q++, j++) wg_map[(size_t)(x + 8 * j)] = (i << 8) | q;
+        }
+        int64_t tot = 0;
+        for (int32_t i = 0; i < b->S; i++) tot += src_P[i];
+        P = (int)((tot + b->S / 2) / b->S);
+        b->split_per_xcd = (int32_t)slots;
+        b->split_grid = (int32_t)(8 * slots);
+        b->split_items = (int32_t)tot;
+    } else if (P == 0) {
         P = 1;
         for (int c : {8, 4, 2})
             if (fits(c)) { P = c; break; }
@@ -527,9 +599,12 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     t.split = P;
     t.threads = nt;
     t.unroll = u;
-    b->split_per_xcd = (int32_t)(per8 * P);
-    b->split_grid = 8 * b->split_per_xcd;
-    b->split_items = b->S * P;
+    t.balance = asked.balance ? 1 : 0;
+    if (!asked.balance) {
+        b->split_per_xcd = (int32_t)(per8 * P);
+        b->split_grid = 8 * b->split_per_xcd;
+        b->split_items = b->S * P;
+    }
     // receiver inputs of the transpose in LDS when they fit in 64 KB (values
     // as FP64, then the int32 positions), the block staging area after them
     size_t n_ent = 0;
@@ -544,7 +619,7 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     for (const void* k : {kf, kr, kq}) {
         int nb = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, nt, lds_all));
-        if ((int64_t)nb * cus < 8 * per8 * P) {
+        if ((int64_t)nb * cus < b->split_grid) {
             set_error("node split: the workgroups no longer fit with %zu B of LDS", lds_all);
             return FM_EINVAL;
         }
@@ -556,6 +631,12 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     hipError_t e = hipMalloc(&b->stage, stage);
     if (e == hipSuccess) e = hipMalloc((void**)&b->sync, sync);
     if (e == hipSuccess) e = hipMemset(b->sync, 0, sync);
+    if (e == hipSuccess && !wg_map.empty()) {
+        wg_map.insert(wg_map.end(), src_P.begin(), src_P.end());
+        e = hipMalloc((void**)&b->wg_map, sizeof(int32_t) * wg_map.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(b->wg_map, wg_map.data(), sizeof(int32_t) * wg_map.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         set_error("node-split buffers (%zu B) failed: %s", stage + sync, hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
@@ -679,6 +760,7 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
 void batch_free(fm_batch* b) {
     if (!b) return;
     if (b->stage) (void)hipFree(b->stage);
+    if (b->wg_map) (void)hipFree(b->wg_map);
     if (b->sync) (void)hipFree(b->sync);
     if (b->nat_dev) (void)hipFree(b->nat_dev);
     if (b->cycles_dev) (void)hipFree(b->cycles_dev);
@@ -1021,12 +1103,14 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
     if (!best) { set_error("null output pointer"); return FM_EINVAL; }
     if (reps < 1) { set_error("reps must be >= 1"); return FM_EINVAL; }
     std::vector<fm_tuning> list;
-    list.push_back(fm_tuning{0, 0, 0, 0, 0, 1});   // rhs groups, library defaults
+    list.push_back(fm_tuning{0, 0, 0, 0, 0, 1, 0});   // rhs groups, library defaults
     const int vw = precision == FM_FP64 ? 2 : 4;
     const int lpn = B % vw == 0 ? B / vw : 0;
 #define FM_SPLIT_CAND(L_, N_, U_)                                           \
-    if (lpn == L_)                                                          \
-        for (int P : {2, 4, 8, 16}) list.push_back(fm_tuning{0, N_, 0, 0, U_, P});
+    if (lpn == L_) {                                                        \
+        for (int P : {2, 4, 8, 16}) list.push_back(fm_tuning{0, N_, 0, 0, U_, P, 0}); \
+        if (N_ == 256) list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, 1});    \
+    }
     FM_SPLIT_SHAPES(FM_SPLIT_CAND)
 #undef FM_SPLIT_CAND
     hipStream_t st = (hipStream_t)stream;
@@ -1039,7 +1123,7 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
     for (const fm_tuning& t : list) {
         fm_batch* b = nullptr;
         if (batch_create(states, S, B, precision, &t, stream, &b) != FM_OK) continue;   // does not fit
-        if (t.split > 1 && b->tun.split != t.split) { batch_free(b); continue; }
+        if (t.split > 1 && !t.balance && b->tun.split != t.split) { batch_free(b); continue; }
         float m = -1.0f;
         rc = apply_J(b, ds, ds_mode, j_out, out_mode);
         if (rc == FM_OK) rc = apply_JT(b, w, w_mode, jt_out, jt_mode);

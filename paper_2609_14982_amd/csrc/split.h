@@ -47,6 +47,8 @@ struct SplitArgs {
     int32_t inv_l1;     // rows are not a multiple of 128 bytes
     int32_t rcv_lds;    // receiver inputs of the transpose staged in LDS
     int32_t stage_off;  // first LDS double of the block staging area
+    const int32_t* wg_map;  // NULL, or per workgroup source << 8 | part (-1: idle)
+    const int32_t* src_P;   // with wg_map: workgroups of each source
 };
 
 constexpr int kCtrStride = 32;                 // words between counters
@@ -499,9 +501,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     constexpr int B = LPN * VW;
     constexpr int SLOTS = NT / LPN;
     constexpr int BATCH = SLOTS * U;
-    const int P = s.P;
+    int P = s.P;
     int alpha, part;
-    {
+    if (s.wg_map) {
+        // balanced split: the host's table (workgroup w runs on XCD w % 8,
+        // where all workgroups of its source are placed)
+        const int code = s.wg_map[blockIdx.x];
+        if (code < 0) return;          // idle slot: touches no counter
+        alpha = code >> 8;
+        part = code & 255;
+        P = s.src_P[alpha];
+    } else {
         const int w = blockIdx.x;
         const int item = (w % 8) * a.per_xcd + (w / 8);
         if (item >= a.items) return;   // not part of any source's group: touches no counter

@@ -210,3 +210,31 @@ def test_autotune_picks_a_measured_schedule(curved):
     assert min(ms for _, ms in table) == [ms for t, ms in table if t == best][0]
     x = gpu_run(fm, torch, states, B, fm.FM_FP64, "J", p.cpu().numpy(), fm.FM_DS_BROADCAST, fm.FM_OUT_RECEIVERS, best)
     assert rel_l2_pairs(x, oracle_J(ops, p.cpu().numpy(), False, out="receivers")) <= TOL64
+
+
+@pytest.mark.parametrize("which", ["curved", "multi2d"])
+def test_balanced_split_bit_identical(which, curved, multi2d):
+    """A different number of workgroups per source (balance = 1) changes only
+    who computes which node, not any node's sum: same bits as the uniform
+    split, in every mode."""
+    wl, states, ops = curved if which == "curved" else multi2d
+    B, R = 16, wl.rcv.shape[0]
+    bal = {"balance": 1, "threads": 256, "unroll": 4}
+    uni = {"split": 4}
+    b = fm.Batch(states, B, fm.FM_FP64, tuning=bal)
+    t = b.tuning()
+    assert t["balance"] == 1 and t["split"] >= 2
+    b.free()
+    print(f"case balanced split {which} S={wl.S}: {t}", flush=True)
+    ds = seeded_ds(wl, B, 1500)
+    p = seeded_ds(wl, B, 1501, per_pair=False)
+    w = np.random.default_rng(1502).standard_normal((wl.S, wl.N, B))
+    y = np.random.default_rng(1503).standard_normal((wl.S, R, B))
+    runs = [("J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES), ("J", p, fm.FM_DS_BROADCAST, fm.FM_OUT_RECEIVERS),
+            ("JT", w, fm.FM_W_NODES, fm.FM_JT_PER_SOURCE), ("JT", y, fm.FM_W_RECEIVERS, fm.FM_JT_SUMMED)]
+    for d, x, im, om in runs:
+        a1 = gpu_run(fm, torch, states, B, fm.FM_FP64, d, x, im, om, bal)
+        a2 = gpu_run(fm, torch, states, B, fm.FM_FP64, d, x, im, om, uni)
+        assert np.array_equal(a1, a2), (d, im, om)
+    assert rel_l2_pairs(gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, bal),
+                        oracle_J(ops, ds, True)) <= TOL64
