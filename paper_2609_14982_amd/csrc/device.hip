@@ -1109,7 +1109,7 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
 #define FM_SPLIT_CAND(L_, N_, U_)                                           \
     if (lpn == L_) {                                                        \
         for (int P : {2, 4, 8, 16}) list.push_back(fm_tuning{0, N_, 0, 0, U_, P, 0}); \
-        if (N_ == 256) list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, 1});    \
+        list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, 1});                   \
     }
     FM_SPLIT_SHAPES(FM_SPLIT_CAND)
 #undef FM_SPLIT_CAND
