@@ -329,7 +329,8 @@ def main():
                                f"{S} sources x {B} rhs, {R} receivers",
                    "schedule": batch.tuning(),
                    "schedule_search": ([{"split": t["split"], "threads": t["threads"], "unroll": t["unroll"],
-                                         "ms": round(ms, 3)} for t, ms in tune_table] if tune_table else None),
+                                         "balance": t.get("balance", 0), "ms": round(ms, 3)}
+                                        for t, ms in tune_table] if tune_table else None),
                    "grid": [wl.n1, wl.n2, wl.n3], "sources": S, "rhs": B, "receivers": R,
                    "setup_s": round(setup_wall, 2),
                    "levels_fwd_max": max(s["levels_fwd"] for s in stats),
