@@ -519,13 +519,16 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
             return FM_EINVAL;
         }
         // predicted time of a source on p workgroups: node work / p (a
-        // workgroup streams ~0.094 * threads nodes per us), ~3 us per level,
-        // block products (8 sum k^2 bytes at ~18 GB/s per 512 threads) / p
+        // workgroup streams ~0.094 * threads nodes per us), a fixed cost per
+        // level (balance 1..5: 3, 4.5, 6, 7.5, 9 us), block products (8 sum k^2
+        // bytes at ~18 GB/s per 512 threads) / p
+        if (asked.balance < 0 || asked.balance > 5) { set_error("balance must be 0 to 5"); return FM_EINVAL; }
+        const double per_level = 1.5 + 1.5 * asked.balance;
         const double h = 0.094 * nt;
         std::vector<double> fixed(b->S), work(b->S);
         for (int32_t i = 0; i < b->S; i++) {
             const HostState* st = b->states[i];
-            fixed[i] = 3.0 * (double)std::max(st->stats.levels_fwd, st->stats.levels_rev);
+            fixed[i] = per_level * (double)std::max(st->stats.levels_fwd, st->stats.levels_rev);
             work[i] = (double)st->N / h + 8.0 * (double)st->stats.sum_k2 / (35.0 * nt);
         }
         auto cost = [&](int32_t i, int p) { return work[i] / p + fixed[i]; };
@@ -599,7 +602,7 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     t.split = P;
     t.threads = nt;
     t.unroll = u;
-    t.balance = asked.balance ? 1 : 0;
+    t.balance = asked.balance;
     if (!asked.balance) {
         b->split_per_xcd = (int32_t)(per8 * P);
         b->split_grid = 8 * b->split_per_xcd;
@@ -1109,7 +1112,8 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
 #define FM_SPLIT_CAND(L_, N_, U_)                                           \
     if (lpn == L_) {                                                        \
         for (int P : {2, 4, 8, 16}) list.push_back(fm_tuning{0, N_, 0, 0, U_, P, 0}); \
-        list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, 1});                   \
+        for (int bl = 1; bl <= (N_ == 256 ? 5 : 1); bl++)                  \
+            list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, bl});             \
     }
     FM_SPLIT_SHAPES(FM_SPLIT_CAND)
 #undef FM_SPLIT_CAND
