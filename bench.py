@@ -112,6 +112,8 @@ def main():
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--split", type=int, default=0, help="workgroups per source (0: library choice, 1: rhs groups)")
     ap.add_argument("--unroll", type=int, default=0)
+    ap.add_argument("--balance", type=int, default=0,
+                    help="node split with workgroups per source from its level count (1-5: per-level weight)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the schedule search (fm_autotune) and use the library's choice or the flags")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -176,6 +178,8 @@ def main():
         tuning["split"] = args.split
     if args.unroll:
         tuning["unroll"] = args.unroll
+    if args.balance:
+        tuning["balance"] = args.balance
     S, N, B, R = wl.S, wl.N, wl.B, wl.rcv.shape[0]
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
@@ -193,7 +197,7 @@ def main():
                                          y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=2, stream=stream)
         for t, ms in tune_table:
             log(f"autotune: split {t['split']} threads {t['threads']} unroll {t['unroll']} "
-                f"rhs_per_group {t['rhs_per_group']}: {ms:.2f} ms per J + J^T")
+                f"balance {t.get('balance', 0)} rhs_per_group {t['rhs_per_group']}: {ms:.2f} ms per J + J^T")
         log(f"autotune: {time.perf_counter() - t1:.1f}s, best {tuning}")
     t1 = time.perf_counter()
     batch = fm.Batch(states, B, prec, tuning=tuning or None, stream=stream)

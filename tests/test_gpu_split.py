@@ -240,3 +240,10 @@ def test_balanced_split_bit_identical(which, curved, multi2d):
         assert np.array_equal(a1, a2), (d, im, om)
     assert rel_l2_pairs(gpu_run(fm, torch, states, B, fm.FM_FP64, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, bal),
                         oracle_J(ops, ds, True)) <= TOL64
+    # FP32 (four lanes per node, 64-byte rows): the same bits as its uniform split
+    a1 = gpu_run(fm, torch, states, B, fm.FM_FP32, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, bal)
+    a2 = gpu_run(fm, torch, states, B, fm.FM_FP32, "J", ds, fm.FM_DS_PER_PAIR, fm.FM_OUT_NODES, uni)
+    assert np.array_equal(a1, a2)
+    a1 = gpu_run(fm, torch, states, B, fm.FM_FP32, "JT", y, fm.FM_W_RECEIVERS, fm.FM_JT_SUMMED, bal)
+    a2 = gpu_run(fm, torch, states, B, fm.FM_FP32, "JT", y, fm.FM_W_RECEIVERS, fm.FM_JT_SUMMED, uni)
+    assert np.array_equal(a1, a2)
