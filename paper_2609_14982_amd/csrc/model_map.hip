@@ -13,6 +13,7 @@
 // cell or node id): deterministic, no atomics.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
