@@ -103,11 +103,14 @@ typedef struct fm_tuning {
     int32_t split;          /* workgroups sharing one source and all B rhs (node split):
                                0 = choose (the rhs-group kernel when no split fits),
                                1 = off (rhs groups), 2, 4, 8, 16 = that many */
-    int32_t balance;        /* 1..5: node split with a different number of workgroups per source
-                               (2..16), chosen from each source's level count and block work so
-                               that the sources finish together, every resident workgroup slot
-                               used (split is then ignored and reports the mean); the value
-                               weights the per-level cost (3, 4.5, 6, 7.5, 9 us); 0: off */
+    int32_t balance;        /* 1..10: node split with a different number of workgroups per
+                               source (2..16), chosen from a cost model of each source (its
+                               levels and block work) so that the sources finish together, every
+                               resident workgroup slot used (split is then ignored and reports
+                               the mean).  1..5: node work / P plus 3, 4.5, 6, 7.5 or 9 us per
+                               level; 6..10: level by level, max(share / rate, t_min) plus a
+                               barrier, (t_min, barrier) = (3, 2), (3, 4), (5, 2), (3, 6),
+                               (4, 4) us.  0: off */
 } fm_tuning;
 
 /*

@@ -518,20 +518,41 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
                       (long long)per8, (long long)slots);
             return FM_EINVAL;
         }
-        // predicted time of a source on p workgroups: node work / p (a
-        // workgroup streams ~0.094 * threads nodes per us), a fixed cost per
-        // level (balance 1..5: 3, 4.5, 6, 7.5, 9 us), block products (8 sum k^2
-        // bytes at ~18 GB/s per 512 threads) / p
-        if (asked.balance < 0 || asked.balance > 5) { set_error("balance must be 0 to 5"); return FM_EINVAL; }
-        const double per_level = 1.5 + 1.5 * asked.balance;
+        // predicted time of a source on p workgroups (us).  balance 1..5:
+        // node work / p (a workgroup streams ~0.094 * threads nodes per us)
+        // plus a fixed cost per level (3, 4.5, 6, 7.5, 9 us); balance 6..10:
+        // level by level, max(share / rate, t_min) plus a barrier each
+        // (t_min, barrier = 3, 2 / 3, 4 / 5, 2 / 3, 6 / 4, 4 us), so that levels smaller
+        // than a round trip do not get faster with more workgroups.  Both add
+        // the block products (8 sum k^2 bytes at ~18 GB/s per 512 threads) / p.
+        if (asked.balance < 0 || asked.balance > 10) { set_error("balance must be 0 to 10"); return FM_EINVAL; }
         const double h = 0.094 * nt;
         std::vector<double> fixed(b->S), work(b->S);
         for (int32_t i = 0; i < b->S; i++) {
             const HostState* st = b->states[i];
-            fixed[i] = per_level * (double)std::max(st->stats.levels_fwd, st->stats.levels_rev);
+            fixed[i] = (1.5 + 1.5 * asked.balance) * (double)std::max(st->stats.levels_fwd, st->stats.levels_rev);
             work[i] = (double)st->N / h + 8.0 * (double)st->stats.sum_k2 / (35.0 * nt);
         }
-        auto cost = [&](int32_t i, int p) { return work[i] / p + fixed[i]; };
+        const bool per_level = asked.balance >= 6;
+        static const double kMin[11] = {0, 0, 0, 0, 0, 0, 3.0, 3.0, 5.0, 3.0, 4.0};
+        static const double kBar[11] = {0, 0, 0, 0, 0, 0, 2.0, 4.0, 2.0, 6.0, 4.0};
+        const double t_min = kMin[asked.balance];
+        const double t_bar = kBar[asked.balance];
+        std::vector<std::vector<double>> lvl_cost;   // [source][p] for p = 0..16
+        if (per_level) {
+            lvl_cost.assign(b->S, std::vector<double>(17, 0.0));
+            for (int32_t i = 0; i < b->S; i++) {
+                const Packed& pk = b->states[i]->pk;
+                for (int p = 1; p <= 16; p++) {
+                    double c = 0.0;
+                    for (int32_t n : pk.flvl_nsc) c += std::max((double)((n + p - 1) / p) / h, t_min) + t_bar;
+                    lvl_cost[i][p] = c + 8.0 * (double)b->states[i]->stats.sum_k2 / (35.0 * nt) / p;
+                }
+            }
+        }
+        auto cost = [&](int32_t i, int p) {
+            return per_level ? lvl_cost[i][std::min(std::max(p, 1), 16)] : work[i] / p + fixed[i];
+        };
         // deal the sources to the XCDs in snake order of cost at the mean split
         std::vector<int32_t> order(b->S);
         for (int32_t i = 0; i < b->S; i++) order[i] = i;
@@ -1112,8 +1133,10 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
 #define FM_SPLIT_CAND(L_, N_, U_)                                           \
     if (lpn == L_) {                                                        \
         for (int P : {2, 4, 8, 16}) list.push_back(fm_tuning{0, N_, 0, 0, U_, P, 0}); \
-        for (int bl = 1; bl <= (N_ == 256 ? 5 : 1); bl++)                  \
-            list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, bl});             \
+        if (N_ == 256)                                                      \
+            for (int bl : {3, 5, 7, 8, 10}) list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, bl}); \
+        else                                                                \
+            list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, 7});               \
     }
     FM_SPLIT_SHAPES(FM_SPLIT_CAND)
 #undef FM_SPLIT_CAND

@@ -219,13 +219,13 @@ def test_balanced_split_bit_identical(which, curved, multi2d):
     split, in every mode."""
     wl, states, ops = curved if which == "curved" else multi2d
     B, R = 16, wl.rcv.shape[0]
-    bal = {"balance": 3, "threads": 256, "unroll": 4}
+    bal = {"balance": 7, "threads": 256, "unroll": 4}
     uni = {"split": 4}
     b = fm.Batch(states, B, fm.FM_FP64, tuning=bal)
     t = b.tuning()
-    assert t["balance"] == 3 and t["split"] >= 2
+    assert t["balance"] == 7 and t["split"] >= 2
     with pytest.raises(fm.FmError):
-        fm.Batch(states, B, fm.FM_FP64, tuning={"balance": 6, "threads": 256, "unroll": 4})
+        fm.Batch(states, B, fm.FM_FP64, tuning={"balance": 11, "threads": 256, "unroll": 4})
     b.free()
     print(f"case balanced split {which} S={wl.S}: {t}", flush=True)
     ds = seeded_ds(wl, B, 1500)
