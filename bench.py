@@ -333,7 +333,8 @@ def main():
                                f"{S} sources x {B} rhs, {R} receivers",
                    "schedule": batch.tuning(),
                    "schedule_search": ([{"split": t["split"], "threads": t["threads"], "unroll": t["unroll"],
-                                         "balance": t.get("balance", 0), "ms": round(ms, 3)}
+                                         "balance": t.get("balance", 0), "min_lds_bytes": t["min_lds_bytes"],
+                                         "ms": round(ms, 3)}
                                         for t, ms in tune_table] if tune_table else None),
                    "grid": [wl.n1, wl.n2, wl.n3], "sources": S, "rhs": B, "receivers": R,
                    "setup_s": round(setup_wall, 2),

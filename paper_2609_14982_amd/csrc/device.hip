@@ -1133,10 +1133,13 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
 #define FM_SPLIT_CAND(L_, N_, U_)                                           \
     if (lpn == L_) {                                                        \
         for (int P : {2, 4, 8, 16}) list.push_back(fm_tuning{0, N_, 0, 0, U_, P, 0}); \
-        if (N_ == 256)                                                      \
+        if (N_ == 256) {                                                    \
             for (int bl : {3, 5, 7, 8, 10}) list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, bl}); \
-        else                                                                \
+            /* one workgroup per CU (the LDS request limits occupancy) */   \
+            list.push_back(fm_tuning{0, N_, 96 * 1024, 0, U_, 0, 7});       \
+        } else {                                                            \
             list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, 7});               \
+        }                                                                   \
     }
     FM_SPLIT_SHAPES(FM_SPLIT_CAND)
 #undef FM_SPLIT_CAND
