@@ -5,11 +5,13 @@ the SCC condensation graph (Algorithm 1, Phase III), on one MI355X.
 One step = one LSQR iteration of the Krylov inner loop (Algorithm 1, Section 4.5)
 over the whole batch: J from the model block [N][B] (broadcast to every
 source) to receiver data [S][R][B], J^T back to the source-summed model block
-(Section 4.4), and the LSQR vector updates.  The iterations run from a HIP
-graph that records 30 of them and is replayed.  Inputs are resident in HBM
-before the timed region.  Setup (Phase I) runs once before timing and is
-reported separately.  The roofline figures use HIP events around eager
-apply_J / apply_JT launches of the same batch on the same stream.
+(Section 4.4), and the LSQR vector updates.  One iteration is captured as a
+HIP graph; --warmup replays run untimed, then exactly --steps replays are
+timed between two device synchronisations, with HIP events around every
+replay for the median and spread.  Inputs are resident in HBM before the timed
+region.  Setup (Phase I) runs once before timing and is reported separately.
+The roofline figures use HIP events around 20 eager apply_J / apply_JT
+launches of the same batch on the same stream.
 
 Prints one JSON line.  Default workload: the 201 x 201 x 101 deformed 3-D grid,
 64 sources x 16 right-hand sides, 400 surface receivers, FP64.
@@ -36,16 +38,31 @@ def log(msg):
 
 
 def algorithmic_bytes(stats_list, B, vbytes, wbytes):
-    """Compulsory HBM bytes of one launch of a sweep kernel, summed over
-    sources: the input and output vectors once per (source, rhs)
-    (2 * vbytes * N * B) plus the source's packed state read once - an 8-byte
-    meta word and a 4-entry value record per node (8 + 4 * wbytes) and the FP64
-    SCC block matrix of that direction (8 * sum k^2).  Predecessor re-reads
-    and the records' overflow entries (<0.5 % of nodes) are not counted."""
+    """Algorithmic bytes of one launch of a sweep kernel, summed over sources:
+    per (source, rhs) the input and output vectors once (2 * vbytes * N), per
+    source its state read once - per node the mean edge count times a weight
+    and a 4-byte index, a calibration weight and two 4-byte indices
+    (N * (ebar * (wbytes + 4) + 4 + wbytes + 4)) - and the FP64 SCC block
+    matrix of that direction (8 * sum k^2).  Predecessor re-reads count as
+    cache hits.  A broadcast input counts once per (source, rhs), as every
+    source reads it."""
     total = 0
     for st in stats_list:
         N, k2 = st["N"], st["sum_k2"]
-        total += 2 * vbytes * N * B + (8 + 4 * wbytes) * N + 8 * k2
+        ebar = st["E"] / N
+        total += 2 * vbytes * N * B + N * (ebar * (wbytes + 4) + 4 + wbytes + 4) + 8 * k2
+    return int(round(total))
+
+
+def layout_bytes(stats_list, B, vbytes, wbytes, broadcast_once=False):
+    """Bytes the kernels move by design: input and output rows per (source,
+    rhs), an 8-byte meta word and a 4-entry value record per node, the block
+    matrix; with broadcast_once the shared input block is counted once."""
+    total = 0
+    for i, st in enumerate(stats_list):
+        N, k2 = st["N"], st["sum_k2"]
+        nin = 0 if (broadcast_once and i > 0) else 1
+        total += (nin + 1) * vbytes * N * B + (8 + 4 * wbytes) * N + 8 * k2
     return total
 
 
@@ -100,11 +117,37 @@ def cpu_baseline(wl, n_src, B, seed):
                       f"{dt:.1f} s"}
 
 
+def level_histogram(states, stats):
+    """Per source: levels, barriers per direction (one per level, one more
+    per level holding SCC blocks), and the level-size distribution of the
+    primal walk (nodes per level, deciles)."""
+    out = []
+    for a, (st, sd) in enumerate(zip(states, stats)):
+        comp, lf, lr = st.export_graph()
+        sizes = np.bincount(lf)
+        szr = np.bincount(lr)
+        # a level holds blocks when one of its components has more than one member
+        ncomp = np.bincount(comp)
+        big = ncomp[comp] > 1
+        blk_f = np.unique(lf[big]).size
+        blk_r = np.unique(lr[big]).size
+        q = np.percentile(sizes, [0, 10, 25, 50, 75, 90, 100]).round(1).tolist()
+        out.append({"source": a, "levels_fwd": int(sd["levels_fwd"]), "levels_rev": int(sd["levels_rev"]),
+                    "barriers_fwd": int(sizes.size + blk_f), "barriers_rev": int(szr.size + blk_r),
+                    "fwd_levels_lt_64_nodes": int(np.sum(sizes < 64)),
+                    "fwd_levels_lt_256_nodes": int(np.sum(sizes < 256)),
+                    "fwd_levels_lt_1024_nodes": int(np.sum(sizes < 1024)),
+                    "fwd_nodes_in_levels_lt_256": int(sizes[sizes < 256].sum()),
+                    "fwd_level_size_pctl_0_10_25_50_75_90_100": q, "n_scc": int(sd["n_scc"]),
+                    "largest_scc": int(sd["largest_scc"]), "sum_k2": int(sd["sum_k2"])})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30, help="LSQR iterations timed (rounded up to 30s)")
-    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=30, help="LSQR iterations timed")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed LSQR iterations before the timed ones")
     ap.add_argument("--config", default="c4", choices=["c2", "c3", "c4"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--sources", type=int, default=0, help="use only the first S sources (0: all)")
@@ -113,15 +156,25 @@ def main():
     ap.add_argument("--split", type=int, default=0, help="workgroups per source (0: library choice, 1: rhs groups)")
     ap.add_argument("--unroll", type=int, default=0)
     ap.add_argument("--balance", type=int, default=0,
-                    help="node split with workgroups per source from its level count (1-5: per-level weight)")
+                    help="node split with workgroups per source from a cost model (1-10, see fm_tuning)")
+    ap.add_argument("--min-lds", type=int, default=0, help="LDS reserved per workgroup (limits occupancy)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the schedule search (fm_autotune) and use the library's choice or the flags")
+    ap.add_argument("--no-tune-cache", action="store_true", help="search even when a cached schedule exists")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=4)
     ap.add_argument("--no-sweep", action="store_true", help="skip the directional-sweeping comparison")
+    ap.add_argument("--roofline-reps", type=int, default=20, help="eager J and J^T launches timed for the roofline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (HBM counter calibration)")
+    ap.add_argument("--level-histogram", action="store_true",
+                    help="only build the states and print the level structure per source (no GPU)")
     args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; a run on several GPUs is not part of it "
+                                   "(--gpus must be 1)", "n_gpus": args.gpus}))
+        sys.exit(2)
 
     if args.copy_calibration:
         import torch
@@ -135,19 +188,10 @@ def main():
                           "copies": 3}))
         return
 
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
-                          "n_gpus": args.gpus}))
-        sys.exit(2)
-
-    import torch
+    import torch  # before the library, so that both use one HIP runtime
 
     import paper_2609_14982_amd as fm
     import workloads as W
-
-    if not torch.cuda.is_available():
-        raise SystemExit("bench.py needs a GPU")
-    dev = torch.device("cuda:0")
 
     t0 = time.perf_counter()
     wl = W.config(args.config, with_T=False)
@@ -165,21 +209,23 @@ def main():
     log(f"setup (host, {min(16, os.cpu_count() or 1)} threads): {setup_wall:.1f}s; "
         f"levels fwd max {max(s['levels_fwd'] for s in stats)}, SCCs {sum(s['n_scc'] for s in stats)}, "
         f"largest {max(s['largest_scc'] for s in stats)}")
+    if args.level_histogram:
+        print(json.dumps({"workload": args.config, "grid": [wl.n1, wl.n2, wl.n3], "N": wl.N,
+                          "per_source": level_histogram(states, stats)}), flush=True)
+        return
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
 
     prec = fm.FM_FP64 if args.precision == "fp64" else fm.FM_FP32
     dt = torch.float64 if prec == fm.FM_FP64 else torch.float32
     vbytes = 8 if prec == fm.FM_FP64 else 4
     tuning = {}
-    if args.rhs_per_group:
-        tuning["rhs_per_group"] = args.rhs_per_group
-    if args.threads:
-        tuning["threads"] = args.threads
-    if args.split:
-        tuning["split"] = args.split
-    if args.unroll:
-        tuning["unroll"] = args.unroll
-    if args.balance:
-        tuning["balance"] = args.balance
+    for k, v in (("rhs_per_group", args.rhs_per_group), ("threads", args.threads), ("split", args.split),
+                 ("unroll", args.unroll), ("balance", args.balance), ("min_lds_bytes", args.min_lds)):
+        if v:
+            tuning[k] = v
     S, N, B, R = wl.S, wl.N, wl.B, wl.rcv.shape[0]
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
@@ -189,64 +235,72 @@ def main():
     y = torch.randn((S, R, B), device=dev, dtype=dt, generator=gen)
     d = torch.empty((S, R, B), device=dev, dtype=dt)
     g = torch.empty((N, B), device=dev, dtype=dt)
-    tune_table = None
+    tune_table, tune_cached = None, False
     if not args.no_autotune and not tuning:
-        # schedule search on this batch's own data (outside the timed region)
+        # schedule search on this batch's own data (outside the timed region),
+        # or the schedule an earlier search stored for the same device, batch
+        # and state structure
         t1 = time.perf_counter()
         tuning, tune_table = fm.autotune(states, B, prec, p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS,
-                                         y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=2, stream=stream)
+                                         y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=2, stream=stream,
+                                         cache=not args.no_tune_cache)
+        tune_cached = not tune_table
         for t, ms in tune_table:
             log(f"autotune: split {t['split']} threads {t['threads']} unroll {t['unroll']} "
                 f"balance {t.get('balance', 0)} rhs_per_group {t['rhs_per_group']}: {ms:.2f} ms per J + J^T")
-        log(f"autotune: {time.perf_counter() - t1:.1f}s, best {tuning}")
+        log(f"autotune: {time.perf_counter() - t1:.1f}s, best {tuning}{' (cached)' if tune_cached else ''}")
     t1 = time.perf_counter()
     batch = fm.Batch(states, B, prec, tuning=tuning or None, stream=stream)
     torch.cuda.synchronize()
     log(f"batch create + upload: {time.perf_counter() - t1:.1f}s, tuning {batch.tuning()}")
 
-    # the timed loop: LSQR iterations replayed from a captured graph
-    GRAPH_ITERS = 30
+    # the timed loop: LSQR iterations, each one replay of a captured graph
     lsqr = fm.Lsqr(batch)
     lsqr.start(y)
-    lsqr.capture(GRAPH_ITERS)
-    n_warm = -(-args.warmup // GRAPH_ITERS)
-    n_rep = max(1, -(-args.steps // GRAPH_ITERS))
-    steps = n_rep * GRAPH_ITERS
-    for _ in range(n_warm):
+    lsqr.capture(1)
+    for _ in range(args.warmup):
         lsqr.replay()
     torch.cuda.synchronize()
-    log(f"warmup {n_warm * GRAPH_ITERS} LSQR iterations done")
+    batch.status()
+    log(f"warmup {args.warmup} LSQR iterations done")
     lsqr.start(y)
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = max(1, args.steps)
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(n_rep):
+    evs[0].record(stream)
+    for k in range(steps):
         lsqr.replay()
-    ev1.record(stream)
+        evs[k + 1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
-    ms_per_step = max(wall * 1e3, ev0.elapsed_time(ev1)) / steps
+    batch.status()
+    per_it = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+    ms_per_step = max(wall * 1e3, evs[0].elapsed_time(evs[-1])) / steps
     phibar = np.abs(lsqr.scalars().cpu().numpy()[3])
-    log(f"timed {steps} LSQR iterations ({n_rep} graph replays): {ms_per_step:.3f} ms/iteration; "
-        f"relative residual after {steps}: {np.median(phibar / np.linalg.norm(y.cpu().numpy().reshape(-1, B), axis=0)):.3e}")
+    log(f"timed {steps} LSQR iterations: {ms_per_step:.3f} ms/iteration (median {np.median(per_it):.3f}, "
+        f"min {per_it.min():.3f}, max {per_it.max():.3f}); relative residual after {steps}: "
+        f"{np.median(phibar / np.linalg.norm(y.cpu().numpy().reshape(-1, B), axis=0)):.3e}")
     lsqr.free()
 
     # kernel durations for the roofline: events around eager applies
-    def step(evs):
-        evs[0].record(stream)
+    reps = max(1, args.roofline_reps)
+    eJ = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps + 1)]
+    eT = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(reps + 1)]
+    for k in range(reps + 1):
+        eJ[k][0].record(stream)
         batch.apply_J(p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS)
-        evs[1].record(stream)
+        eJ[k][1].record(stream)
+    for k in range(reps + 1):
+        eT[k][0].record(stream)
         batch.apply_JT(y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED)
-        evs[2].record(stream)
-
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(4)]
-    for k in range(4):
-        step(events[k])
+        eT[k][1].record(stream)
     torch.cuda.synchronize()
-    tJ = np.array([e[0].elapsed_time(e[1]) for e in events[1:]])
-    tT = np.array([e[1].elapsed_time(e[2]) for e in events[1:]])
-    log(f"eager applies: J {tJ.mean():.3f} ms, J^T {tT.mean():.3f} ms")
+    batch.status()
+    tJ = np.array([e[0].elapsed_time(e[1]) for e in eJ[1:]])
+    tT = np.array([e[0].elapsed_time(e[1]) for e in eT[1:]])
+    log(f"eager applies ({reps} each): J {tJ.mean():.3f} ms (median {np.median(tJ):.3f}), "
+        f"J^T {tT.mean():.3f} ms (median {np.median(tT):.3f})")
 
     # roofline of the dominant kernel: the primal sweep (one launch per apply_J,
     # between a counter reset of S words and the receiver gather of S*R*B
@@ -259,8 +313,15 @@ def main():
     traffic = measured_traffic(kname, args.config, args.precision) if not args.sources else None
     roof = {"bound": "hbm", "achieved": round(gbs_J, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs_J / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "kernel": f"{kname} primal (apply_J)", "bytes_per_launch": bytes_J,
-            "launch_ms": round(float(tJ.mean()), 4),
+            "traffic_kind": "fabric bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a plain copy "
+                            "of known size; they include reads served by the memory-side cache",
+            "kernel": f"{kname} primal (apply_J)",
+            "bytes_per_launch": bytes_J,
+            "bytes_model": "per (source, rhs) 2*vbytes*N, per source N*(ebar*(wbytes+4)+4+wbytes+4) + 8*sum k^2",
+            "bytes_layout": layout_bytes(stats, B, vbytes, vbytes),
+            "bytes_layout_broadcast_once": layout_bytes(stats, B, vbytes, vbytes, broadcast_once=True),
+            "launch_ms": round(float(tJ.mean()), 4), "launch_ms_median": round(float(np.median(tJ)), 4),
+            "launches_timed": reps,
             "transpose_GBs_incl_source_sum": round(gbs_T, 1)}
     # what a plain device copy sustains on this GPU (2 GiB read + 2 GiB
     # written per copy), and the primal kernel's counted bytes per second
@@ -280,13 +341,20 @@ def main():
     roof["frac_of_copy"] = round(gbs_J / copy_gbs, 4)
     if traffic is not None:
         roof["traffic_GBs"] = round(traffic / (tJ.mean() * 1e-3) / 1e9, 1)
-    log(f"device copy {copy_gbs:.0f} GB/s; primal kernel {gbs_J:.0f} GB/s algorithmic = {gbs_J / copy_gbs:.3f} of it")
+        roof["traffic_over_algorithmic"] = round(traffic / bytes_J, 3)
+    log(f"device copy {copy_gbs:.0f} GB/s; primal kernel {gbs_J:.0f} GB/s algorithmic = {gbs_J / PEAK_HBM_GBS:.3f} "
+        f"of peak, {gbs_J / copy_gbs:.3f} of the copy")
 
     sweep = None
     if not args.no_sweep:
         # the same paired application by directional Gauss-Seidel sweeping
-        # (Section 3.6) on the same GPU, converged to the same accuracy
+        # (Section 3.6) on the same GPU, converged, checked against the
+        # SCC/BTF outputs before its rate is reported
         log("directional-sweeping comparison (converged)")
+        batch.apply_J(p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS)
+        batch.apply_JT(y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED)
+        batch.status()
+        d_ref, g_ref = d.clone(), g.clone()
         rcv = torch.as_tensor(wl.rcv, device=dev)
         r_nodes = torch.zeros((S, N, B), device=dev, dtype=dt)
         batch.apply_J_sweep(p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS, max_cycles=1)
@@ -302,12 +370,25 @@ def main():
         torch.cuda.synchronize()
         tsJ, tsT = e0.elapsed_time(e1), e1.elapsed_time(e2)
         del r_nodes
+
+        def rel_pairs(x, ref):
+            """max over (source, rhs) of the relative l2 difference; [S][*][B] or [*][B]"""
+            x, ref = x.double(), ref.double()
+            if x.dim() == 2:
+                x, ref = x[None], ref[None]
+            num = torch.linalg.vector_norm(x - ref, dim=-2)
+            den = torch.linalg.vector_norm(ref, dim=-2).clamp_min(1e-300)
+            return float((num / den).max())
+        errJ, errT = rel_pairs(d, d_ref), rel_pairs(g, g_ref)
+        tol = 1e-11 if prec == fm.FM_FP64 else 1e-4
         sweep = {"value": round(S * B / ((tsJ + tsT) * 1e-3), 3), "unit": "paired applies/s",
                  "J_ms": round(tsJ, 2), "JT_ms": round(tsT, 2),
                  "cycles_J": [int(cj.min()), int(cj.max())], "cycles_JT": [int(ct.min()), int(ct.max())],
-                 "sweeps_per_cycle": 2 ** wl.dim}
+                 "sweeps_per_cycle": 2 ** wl.dim,
+                 "rel_l2_vs_scc_btf_J": errJ, "rel_l2_vs_scc_btf_JT": errT, "agreement_tol": tol,
+                 "agrees": bool(errJ <= tol and errT <= tol)}
         log(f"sweeping: J {tsJ:.1f} ms ({cj.min()}-{cj.max()} cycles), J^T {tsT:.1f} ms "
-            f"({ct.min()}-{ct.max()} cycles)")
+            f"({ct.min()}-{ct.max()} cycles); max rel l2 against SCC/BTF: J {errJ:.2e}, J^T {errT:.2e}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -322,8 +403,10 @@ def main():
         "unit": "paired applies/s",
         "n_gpus": 1,
         "steps": steps,
-        "warmup": n_warm * GRAPH_ITERS,
+        "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4),
+        "ms_per_step_median": round(float(np.median(per_it)), 4),
+        "ms_per_step_min_max": [round(float(per_it.min()), 4), round(float(per_it.max()), 4)],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -332,6 +415,7 @@ def main():
         "config": {"workload": f"{args.config}: {wl.n1}x{wl.n2}x{wl.n3} deformed grid, "
                                f"{S} sources x {B} rhs, {R} receivers",
                    "schedule": batch.tuning(),
+                   "schedule_cached": tune_cached,
                    "schedule_search": ([{"split": t["split"], "threads": t["threads"], "unroll": t["unroll"],
                                          "balance": t.get("balance", 0), "min_lds_bytes": t["min_lds_bytes"],
                                          "ms": round(ms, 3)}
@@ -344,7 +428,7 @@ def main():
                    "J_ms": round(float(tJ.mean()), 4), "JT_ms": round(float(tT.mean()), 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "vs_sweeping": round(value / sweep["value"], 2) if sweep else None,
+        "vs_sweeping": (round(value / sweep["value"], 2) if sweep and sweep["agrees"] else None),
         "sweeping_baseline": sweep,
     }
     print(json.dumps(res), flush=True)

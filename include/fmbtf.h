@@ -206,12 +206,20 @@ int fm_batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t preci
  * count.  ds, j_out, w, jt_out are device buffers laid out per the modes, as
  * for fm_apply_J / fm_apply_JT (j_out and jt_out are overwritten).  Each
  * candidate allocates its own scratch: call it once, before the Krylov loop,
- * not under graph capture.  Errors: FM_EINVAL, FM_ENOMEM, FM_EHIP.
+ * not under graph capture.
+ *   cache_path  NULL or "": always search.  Otherwise a text file of earlier
+ *               results (created if missing, one line appended per search),
+ *               keyed by the device (architecture, compute units), S, B,
+ *               precision, the four modes, a hash of every state's level and
+ *               block structure and the build of this library: on a match
+ *               the stored schedule is returned without running anything,
+ *               *n_out = 0 and candidates[0] / ms[0] hold the stored entry.
+ * Errors: FM_EINVAL, FM_ENOMEM, FM_EHIP.
  */
 int fm_autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* hip_stream,
                 const void* ds, int32_t ds_mode, void* j_out, int32_t out_mode, const void* w, int32_t w_mode,
-                void* jt_out, int32_t jt_mode, int32_t reps, fm_tuning* best, fm_tuning* candidates, float* ms,
-                int32_t max_out, int32_t* n_out);
+                void* jt_out, int32_t jt_mode, int32_t reps, const char* cache_path, fm_tuning* best,
+                fm_tuning* candidates, float* ms, int32_t max_out, int32_t* n_out);
 
 /* Change the stream later applies are enqueued on. */
 int fm_batch_set_stream(fm_batch* b, void* hip_stream);
@@ -225,8 +233,11 @@ int fm_batch_tuning(const fm_batch* b, fm_tuning* out);
  * 1) the workgroups of one source wait on each other at every level; each
  * wait gives up after about 10 s without progress (possible only when the
  * launch cannot keep all its workgroups resident, e.g. beside other work
- * that holds the device), and the launch then runs to its end with invalid
- * outputs.  That case returns FM_EHIP (and clears the flag).
+ * that holds the device), and that launch then runs to its end with invalid
+ * outputs.  That case returns FM_EHIP (and clears the flag).  Each launch
+ * starts with its own waits armed again, so a failed launch does not shorten
+ * the waits of later ones; callers check this status wherever they
+ * synchronise (the Python layer does after every solve and benchmark).
  * Errors: FM_EINVAL, FM_ESTATE, FM_EHIP.
  */
 int fm_batch_status(fm_batch* b);

@@ -67,6 +67,7 @@ class ReceiverTraveltime(torch.autograd.Function):
         g = grad.detach().to(device=dev, dtype=torch.float64).reshape(problem.S, problem.R, 1).contiguous()
         out = torch.empty((problem.N, 1), device=dev, dtype=torch.float64)
         batch.apply_JT(g, FM_W_RECEIVERS, out, FM_JT_SUMMED)
+        batch.status()      # synchronises; raises if a level wait of the launch gave up
         return out.reshape(problem.N).to(device=ctx.s_device, dtype=ctx.s_dtype), None
 
 
@@ -110,6 +111,7 @@ def cgls(batch: Batch, r: torch.Tensor, n_iter: int):
         p = s + beta * p
         gamma = gnew
         norms.append(torch.linalg.vector_norm(res.reshape(-1, B), dim=0))
+    batch.status()
     return x, torch.stack(norms)
 
 

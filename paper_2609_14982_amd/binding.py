@@ -72,6 +72,9 @@ def load():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise ImportError(f"{_LIB_PATH} is not built: run __graft_entry__.build()")
+    # torch brings its own HIP runtime; loading it first makes the library bind
+    # to that same runtime instead of a second copy of it
+    import torch  # noqa: F401
     lib = C.CDLL(_LIB_PATH)
     vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
     sig = {
@@ -85,8 +88,8 @@ def load():
         "fm_state_free": (None, [vp]),
         "fm_batch_create": (C.c_int, [vp, i32, i32, i32, vp, vp, vp]),
         "fm_batch_set_stream": (C.c_int, [vp, vp]),
-        "fm_autotune": (C.c_int, [vp, i32, i32, i32, vp, vp, i32, vp, i32, vp, i32, vp, i32, i32, vp, vp, vp, i32,
-                                  vp]),
+        "fm_autotune": (C.c_int, [vp, i32, i32, i32, vp, vp, i32, vp, i32, vp, i32, vp, i32, i32, C.c_char_p, vp,
+                                  vp, vp, i32, vp]),
         "fm_batch_tuning": (C.c_int, [vp, vp]),
         "fm_batch_status": (C.c_int, [vp]),
         "fm_batch_split_info": (C.c_int, [vp, vp]),
@@ -275,8 +278,25 @@ def _dptr(t, dtype, shape, what):
     return C.c_void_p(t.data_ptr())
 
 
-def autotune(states, B, precision, ds, ds_mode, j_out, out_mode, w, w_mode, jt_out, jt_mode, reps=2, stream=None):
-    """fm_autotune on device tensors: returns (best tuning dict, [(tuning dict, ms per J + J^T pair), ...])."""
+def default_tune_cache() -> str:
+    """Where autotune keeps its results unless told otherwise: $FMBTF_TUNE_CACHE,
+    else ~/.cache/fmbtf/autotune.txt."""
+    path = os.environ.get("FMBTF_TUNE_CACHE")
+    if path is not None:
+        return path
+    d = os.path.join(os.path.expanduser("~"), ".cache", "fmbtf")
+    try:
+        os.makedirs(d, exist_ok=True)
+    except OSError:
+        return ""
+    return os.path.join(d, "autotune.txt")
+
+
+def autotune(states, B, precision, ds, ds_mode, j_out, out_mode, w, w_mode, jt_out, jt_mode, reps=2, stream=None,
+             cache=True):
+    """fm_autotune on device tensors: returns (best tuning dict, [(tuning dict, ms per J + J^T pair), ...]).
+    cache: True (default path), False (always search) or a file path; a cache
+    hit returns the stored schedule and an empty candidate list."""
     import torch
     lib = load()
     states = list(states)
@@ -296,10 +316,11 @@ def autotune(states, B, precision, ds, ds_mode, j_out, out_mode, w, w_mode, jt_o
     cands = (fm_tuning * n_max)()
     ms = (C.c_float * n_max)()
     n = C.c_int32(0)
+    path = default_tune_cache() if cache is True else (cache or "")
     _check(lib.fm_autotune(arr, S, B, int(precision), C.c_void_p(stream.cuda_stream),
                            _dptr(ds, dt, ds_shape, "ds"), int(ds_mode), _dptr(j_out, dt, o_shape, "j_out"),
                            int(out_mode), _dptr(w, dt, w_shape, "w"), int(w_mode), _dptr(jt_out, dt, g_shape, "jt_out"),
-                           int(jt_mode), int(reps), C.byref(best), cands, ms, n_max, C.byref(n)))
+                           int(jt_mode), int(reps), path.encode(), C.byref(best), cands, ms, n_max, C.byref(n)))
     as_dict = lambda t: {k: getattr(t, k) for k, _ in fm_tuning._fields_}
     return as_dict(best), [(as_dict(cands[i]), float(ms[i])) for i in range(n.value)]
 

@@ -34,8 +34,8 @@ int batch_status(fm_batch* b);
 int batch_split_info(fm_batch* b, int32_t* xcd_masks);
 int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* stream, const void* ds,
              int32_t ds_mode, void* j_out, int32_t out_mode, const void* w, int32_t w_mode, void* jt_out,
-             int32_t jt_mode, int32_t reps, fm_tuning* best, fm_tuning* cands, float* ms, int32_t max_out,
-             int32_t* n_out);
+             int32_t jt_mode, int32_t reps, const char* cache_path, fm_tuning* best, fm_tuning* cands, float* ms,
+             int32_t max_out, int32_t* n_out);
 int apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode, int32_t max_cycles,
                   int32_t* cycles_host);
 int apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles, int32_t* cycles_host);
@@ -190,11 +190,11 @@ int fm_batch_status(fm_batch* b) {
 
 int fm_autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* hip_stream,
                 const void* ds, int32_t ds_mode, void* j_out, int32_t out_mode, const void* w, int32_t w_mode,
-                void* jt_out, int32_t jt_mode, int32_t reps, fm_tuning* best, fm_tuning* candidates, float* ms,
-                int32_t max_out, int32_t* n_out) {
+                void* jt_out, int32_t jt_mode, int32_t reps, const char* cache_path, fm_tuning* best,
+                fm_tuning* candidates, float* ms, int32_t max_out, int32_t* n_out) {
     fm::clear_error();
     return fm::autotune(states, S, B, precision, hip_stream, ds, ds_mode, j_out, out_mode, w, w_mode, jt_out, jt_mode,
-                        reps, best, candidates, ms, max_out, n_out);
+                        reps, cache_path, best, candidates, ms, max_out, n_out);
 }
 
 int fm_batch_split_info(fm_batch* b, int32_t* xcd_masks) {

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "batch.h"
@@ -438,6 +439,7 @@ static hipError_t launch_split(const fm_batch* b, bool fwd, const ApplyArgs& a0)
     s.ctr = b->sync;
     s.xmask = b->sync + (size_t)b->S * kCtrStride;
     s.abort_w = b->sync + (size_t)2 * b->S * kCtrStride;
+    s.fail_w = s.abort_w + kCtrStride;
     s.stage = b->stage;
     s.stage_rows = b->stage_rows;
     s.P = b->tun.split;
@@ -747,13 +749,10 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
         }
     }
     size_t vbytes = precision == FM_FP64 ? 8 : 4;
-    size_t scratch = (size_t)S * (size_t)b->N * (size_t)B * vbytes;
     hipError_t e = hipMalloc(&b->d_src, sizeof(SrcDev) * S + sizeof(void*) * S);
-    if (e == hipSuccess) e = hipMalloc(&b->scratch, scratch);
     if (e != hipSuccess) {
-        if (b->d_src) (void)hipFree(b->d_src);
         delete b;
-        set_error("batch allocation (%zu B scratch) failed: %s", scratch, hipGetErrorString(e));
+        set_error("batch allocation failed: %s", hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
     }
     std::vector<const void*> cal(S);
@@ -762,9 +761,7 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     if (e == hipSuccess)
         e = hipMemcpy((char*)b->d_src + sizeof(SrcDev) * S, cal.data(), sizeof(void*) * S, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        (void)hipFree(b->d_src);
-        (void)hipFree(b->scratch);
-        delete b;
+        batch_free(b);
         set_error("batch upload failed: %s", hipGetErrorString(e));
         return FM_EHIP;
     }
@@ -776,6 +773,14 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     if (rc) {
         batch_free(b);
         return rc;
+    }
+    const size_t scratch = (size_t)S * (size_t)b->N * (size_t)B * vbytes;
+    e = hipMalloc(&b->scratch, scratch);
+    if (e != hipSuccess) {
+        b->scratch = nullptr;
+        batch_free(b);
+        set_error("batch allocation (%zu B scratch) failed: %s", scratch, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
     }
     *out = b;
     return FM_OK;
@@ -1093,7 +1098,7 @@ int batch_status(fm_batch* b) {
     if (rc) return rc;
     HIP_TRY(hipStreamSynchronize(b->stream));
     if (b->sync) {
-        unsigned* w = b->sync + (size_t)2 * b->S * kCtrStride;
+        unsigned* w = b->sync + (size_t)2 * b->S * kCtrStride + kCtrStride;   // sticky failure word
         unsigned v = 0;
         HIP_TRY(hipMemcpy(&v, w, sizeof(v), hipMemcpyDeviceToHost));
         if (v) {
@@ -1118,14 +1123,105 @@ int batch_split_info(fm_batch* b, int32_t* xcd_masks) {
     return FM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// schedule cache: one text line per search, "key|tuning fields|ms"; the key
+// names the device (architecture, compute units), the batch (S, B, precision,
+// the four modes), a hash of every state's level and block structure, and the
+// build of this library, so a stale or foreign entry never matches.
+// ---------------------------------------------------------------------------
+static uint64_t fnv1a(uint64_t h, const void* p, size_t n) {
+    const unsigned char* c = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+template <class T>
+static uint64_t fnv1a_vec(uint64_t h, const std::vector<T>& v) {
+    const uint64_t n = v.size();
+    h = fnv1a(h, &n, sizeof(n));
+    return v.empty() ? h : fnv1a(h, v.data(), v.size() * sizeof(T));
+}
+
+static int tune_key(fm_state* const* states, int32_t S, int32_t B, int32_t precision, const int32_t modes[4],
+                    std::string& key) {
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    uint64_t h = 1469598103934665603ull;
+    for (int32_t i = 0; i < S; i++) {
+        const HostState* st = static_cast<const HostState*>(states[i]);
+        if (!st) { set_error("null state %d", i); return FM_EINVAL; }
+        const int64_t dims[5] = {st->dim, st->n[0], st->n[1], st->n[2], st->src};
+        h = fnv1a(h, dims, sizeof(dims));
+        h = fnv1a_vec(h, st->pk.flvl_nsc);
+        h = fnv1a_vec(h, st->pk.rlvl_nsc);
+        h = fnv1a_vec(h, st->pk.fblk_ptr);
+        h = fnv1a_vec(h, st->pk.blk_k);
+        h = fnv1a_vec(h, st->pk.rcv_node);
+    }
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s/%d/S%d/B%d/P%d/m%d%d%d%d/%016llx/%s %s", prop.gcnArchName, cus, S, B, precision,
+             modes[0], modes[1], modes[2], modes[3], (unsigned long long)h, __DATE__, __TIME__);
+    key = buf;
+    for (char& c : key)
+        if (c == '|' || c == '\n') c = '_';
+    return FM_OK;
+}
+
+static bool tune_lookup(const char* path, const std::string& key, fm_tuning* t, float* ms) {
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (fgets(line, sizeof(line), f)) {
+        const char* bar = strchr(line, '|');
+        if (!bar || (size_t)(bar - line) != key.size() || strncmp(line, key.c_str(), key.size()) != 0) continue;
+        fm_tuning x{};
+        float m = 0.0f;
+        if (sscanf(bar + 1, "%d %d %d %d %d %d %d|%f", &x.rhs_per_group, &x.threads, &x.min_lds_bytes, &x.xcd_aware,
+                   &x.unroll, &x.split, &x.balance, &m) == 8) {
+            *t = x;      // the last matching line wins
+            *ms = m;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void tune_store(const char* path, const std::string& key, const fm_tuning& t, float ms) {
+    FILE* f = fopen(path, "a");
+    if (!f) return;      // the cache is an optimisation: an unwritable path only costs the next search
+    fprintf(f, "%s|%d %d %d %d %d %d %d|%.4f\n", key.c_str(), t.rhs_per_group, t.threads, t.min_lds_bytes,
+            t.xcd_aware, t.unroll, t.split, t.balance, (double)ms);
+    fclose(f);
+}
+
 // Schedule search over the built kernels on the caller's own data (the
 // level-chunk autotuning of the batching step).
 int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* stream, const void* ds,
              int32_t ds_mode, void* j_out, int32_t out_mode, const void* w, int32_t w_mode, void* jt_out,
-             int32_t jt_mode, int32_t reps, fm_tuning* best, fm_tuning* cands, float* ms, int32_t max_out,
-             int32_t* n_out) {
+             int32_t jt_mode, int32_t reps, const char* cache_path, fm_tuning* best, fm_tuning* cands, float* ms,
+             int32_t max_out, int32_t* n_out) {
     if (!best) { set_error("null output pointer"); return FM_EINVAL; }
     if (reps < 1) { set_error("reps must be >= 1"); return FM_EINVAL; }
+    if (!states || S < 1) { set_error("need at least one state"); return FM_EINVAL; }
+    std::string key;
+    if (cache_path && cache_path[0]) {
+        const int32_t modes[4] = {ds_mode, out_mode, w_mode, jt_mode};
+        int rc = tune_key(states, S, B, precision, modes, key);
+        if (rc) return rc;
+        float m = 0.0f;
+        if (tune_lookup(cache_path, key, best, &m)) {
+            if (cands && max_out > 0) cands[0] = *best;
+            if (ms && max_out > 0) ms[0] = m;
+            if (n_out) *n_out = 0;      // nothing measured: the schedule came from the cache
+            clear_error();
+            return FM_OK;
+        }
+    }
     std::vector<fm_tuning> list;
     list.push_back(fm_tuning{0, 0, 0, 0, 0, 1, 0});   // rhs groups, library defaults
     const int vw = precision == FM_FP64 ? 2 : 4;

@@ -23,8 +23,10 @@
 // with rows of a multiple of 128 bytes no cache line holds two nodes, so no
 // stale line can sit in a CU's L1; shorter rows take the acquire at every
 // barrier.  Every wait is bounded: after ~10 s without progress the wave sets
-// the batch's abort word and all later barriers of the launch return at once,
-// so a launch always ends (fm_batch_status reports the failure).
+// the launch's abort word, so that all later barriers of that launch return at
+// once and the launch always ends, and the batch's sticky failure word, which
+// fm_batch_status reports.  The abort word is cleared before every launch, so
+// one failed launch never shortens the waits of the next.
 //
 // Nontrivial SCC blocks (Section 4.3) take two phases.  Phase 1 computes the
 // block right-hand sides b_C = q_C + sum_ext w x for the members (members
@@ -39,7 +41,8 @@ namespace fm {
 struct SplitArgs {
     unsigned* ctr;      // [S] arrival counters, one per 128-byte line (32 words apart)
     unsigned* xmask;    // [S] XCDs seen per source, one per 128-byte line
-    unsigned* abort_w;  // one word: set when a barrier wait timed out
+    unsigned* abort_w;  // one word: set when a barrier wait of this launch timed out
+    unsigned* fail_w;   // one word, sticky until fm_batch_status: some launch timed out
     void* stage;        // [S][stage_rows][B] block right-hand sides
     int64_t stage_rows;
     int32_t P;          // workgroups per source
@@ -57,6 +60,7 @@ constexpr uint64_t kBarrierTicks = 1000000000; // 10 s of the 100 MHz realtime c
 struct GroupSync {
     unsigned* ctr;
     unsigned* abort_w;
+    unsigned* fail_w;
     unsigned target;
     bool agent;       // device-scope release/acquire around every barrier
     bool inv_l1;      // acquire at every barrier
@@ -88,6 +92,7 @@ __device__ __forceinline__ void group_barrier(GroupSync& g, int P) {
                 if ((int)(c - g.target) >= 0) break;
                 if (__hip_atomic_load(g.abort_w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) { dead = 1u; break; }
                 if (wall_clock64() - t0 > kBarrierTicks) {
+                    __hip_atomic_fetch_or(g.fail_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_fetch_or(g.abort_w, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     dead = 1u;
                     break;
@@ -578,6 +583,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     GroupSync g;
     g.ctr = s.ctr + (size_t)alpha * kCtrStride;
     g.abort_w = s.abort_w;
+    g.fail_w = s.fail_w;
     g.target = 0;
     g.agent = true;          // until the XCD check at the first barrier
     g.inv_l1 = s.inv_l1 != 0;
@@ -700,11 +706,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     }
 }
 
-// Counters and XCD masks start from zero at every launch (a kernel, not a
-// memset, so that the launch can be captured in a graph).  The abort word is
-// left alone: it stays set until the host has read it.
+// Counters, XCD masks and the launch's abort word start from zero at every
+// launch (a kernel, not a memset, so that the launch can be captured in a
+// graph).  The sticky failure word is left alone: it stays set until the host
+// has read it.
 __global__ void k_split_reset(SplitArgs s, int S) {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S; t += gridDim.x * blockDim.x) {
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t0 == 0) *s.abort_w = 0u;
+    for (int t = t0; t < S; t += gridDim.x * blockDim.x) {
         s.ctr[(size_t)t * kCtrStride] = 0u;
         s.xmask[(size_t)t * kCtrStride] = 0u;
     }

@@ -189,7 +189,7 @@ def test_repeated_applies_reuse_counters(curved):
     batch.free()
 
 
-def test_autotune_picks_a_measured_schedule(curved):
+def test_autotune_picks_a_measured_schedule(curved, tmp_path):
     """The schedule search measures the rhs-group kernel and every node-split
     shape that fits, returns the fastest, and that schedule reproduces the
     oracle."""
@@ -202,12 +202,25 @@ def test_autotune_picks_a_measured_schedule(curved):
     d = torch.empty((1, R, B), device=dev, dtype=torch.float64)
     g = torch.empty((wl.N, B), device=dev, dtype=torch.float64)
     best, table = fm.autotune(states, B, fm.FM_FP64, p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS,
-                              y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=2)
+                              y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=2, cache=False)
     for t, ms in table:
         print(f"{t} {ms:.3f} ms", flush=True)
     assert any(t["split"] == 1 for t, _ in table)
     assert any(t["split"] > 1 for t, _ in table)
     assert min(ms for _, ms in table) == [ms for t, ms in table if t == best][0]
+    # the on-disk cache: the first call searches and stores, the second
+    # returns the stored schedule without measuring anything
+    cache = str(tmp_path / "tune.txt")
+    b1, t1 = fm.autotune(states, B, fm.FM_FP64, p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS,
+                         y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=1, cache=cache)
+    b2, t2 = fm.autotune(states, B, fm.FM_FP64, p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS,
+                         y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED, reps=1, cache=cache)
+    assert len(t1) > 1 and t2 == [] and b1 == b2
+    # another batch shape is another key: it searches again
+    _, t3 = fm.autotune(states, B, fm.FM_FP64, p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS,
+                        y, fm.FM_W_RECEIVERS, torch.empty((1, wl.N, B), device=dev, dtype=torch.float64),
+                        fm.FM_JT_PER_SOURCE, reps=1, cache=cache)
+    assert len(t3) > 1
     x = gpu_run(fm, torch, states, B, fm.FM_FP64, "J", p.cpu().numpy(), fm.FM_DS_BROADCAST, fm.FM_OUT_RECEIVERS, best)
     assert rel_l2_pairs(x, oracle_J(ops, p.cpu().numpy(), False, out="receivers")) <= TOL64
 
