@@ -274,6 +274,29 @@ int fm_apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t 
 int fm_apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode);
 
 /*
+ * Allocation-free variant of fm_apply_J, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation.  It computes what fm_batch_create + fm_apply_J +
+ * fm_batch_free would over the same states, without a batch: the scratch a
+ * batch allocates (the state table the kernels index and, for receiver
+ * output, the [S][N][B] node values) lives in a fixed device array of 64 MiB
+ * that the library holds on every device it runs on until the process ends.
+ *   states     S states already resident on the current device in this
+ *              precision (an earlier fm_batch_create over them uploaded
+ *              them); otherwise FM_ESTATE
+ *   B, precision, ds, ds_mode, out, out_mode   as for fm_batch_create / fm_apply_J
+ *   hip_stream where the work is enqueued (NULL: the null stream)
+ * Runs the rhs-group schedule (no node split).  Allocates nothing and does not
+ * synchronise.  Calls that overlap on one device share that device's array
+ * and race: issue them on one stream or wait between them.
+ * Errors: FM_EINVAL (shapes, modes, or more than 64 MiB of scratch needed:
+ * sizeof(state table) + S*N*B*(8 or 4) bytes with receiver output),
+ * FM_ESTATE, FM_EHIP.
+ */
+int fm_apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* hip_stream,
+                      const void* ds, int32_t ds_mode, void* out, int32_t out_mode);
+
+/*
  * Comparison baseline, not the method: the same J and J^T computed by
  * directional Gauss-Seidel sweeping (Section 3.6) on the GPU, without the
  * graph analysis.  Every (source, rhs) system is swept over the 2^dim axis

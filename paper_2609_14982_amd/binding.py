@@ -24,7 +24,7 @@ SYMBOLS = (
     "fm_state_stats",
     "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
     "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_batch_status", "fm_batch_split_info",
-    "fm_apply_J",
+    "fm_apply_J", "fm_apply_J_static",
     "fm_apply_JT", "fm_apply_J_sweep", "fm_apply_JT_sweep", "fm_batch_free", "fm_last_error",
     "fm_lsqr_create", "fm_lsqr_start", "fm_lsqr_iterate", "fm_lsqr_capture", "fm_lsqr_replay",
     "fm_lsqr_buffers", "fm_lsqr_free", "fm_autotune",
@@ -94,6 +94,7 @@ def load():
         "fm_batch_status": (C.c_int, [vp]),
         "fm_batch_split_info": (C.c_int, [vp, vp]),
         "fm_apply_J": (C.c_int, [vp, vp, i32, vp, i32]),
+        "fm_apply_J_static": (C.c_int, [vp, i32, i32, i32, vp, vp, i32, vp, i32]),
         "fm_apply_JT": (C.c_int, [vp, vp, i32, vp, i32]),
         "fm_apply_J_sweep": (C.c_int, [vp, vp, i32, vp, i32, i32, vp]),
         "fm_apply_JT_sweep": (C.c_int, [vp, vp, vp, i32, i32, vp]),
@@ -323,6 +324,25 @@ def autotune(states, B, precision, ds, ds_mode, j_out, out_mode, w, w_mode, jt_o
                            int(jt_mode), int(reps), path.encode(), C.byref(best), cands, ms, n_max, C.byref(n)))
     as_dict = lambda t: {k: getattr(t, k) for k, _ in fm_tuning._fields_}
     return as_dict(best), [(as_dict(cands[i]), float(ms[i])) for i in range(n.value)]
+
+
+def apply_J_static(states, B, precision, ds, ds_mode, out, out_mode, stream=None):
+    """fm_apply_J_static: J over resident states without a batch and without any
+    device allocation (the library's fixed scratch array)."""
+    import torch
+    states = list(states)
+    S, N, R = len(states), states[0].N, states[0].R
+    B = int(B)
+    dt = torch.float64 if precision == FM_FP64 else torch.float32
+    arr = (C.c_void_p * S)(*[st.ptr.value for st in states])
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    ds_shape = (S, N, B) if ds_mode == FM_DS_PER_PAIR else (N, B)
+    out_shape = (S, N, B) if out_mode == FM_OUT_NODES else (S, R, B)
+    _check(load().fm_apply_J_static(arr, S, B, int(precision), C.c_void_p(stream.cuda_stream),
+                                    _dptr(ds, dt, ds_shape, "ds"), int(ds_mode), _dptr(out, dt, out_shape, "out"),
+                                    int(out_mode)))
+    return out
 
 
 class Batch:

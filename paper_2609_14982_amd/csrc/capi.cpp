@@ -36,6 +36,8 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
              int32_t ds_mode, void* j_out, int32_t out_mode, const void* w, int32_t w_mode, void* jt_out,
              int32_t jt_mode, int32_t reps, const char* cache_path, fm_tuning* best, fm_tuning* cands, float* ms,
              int32_t max_out, int32_t* n_out);
+int apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* stream, const void* ds,
+                   int32_t ds_mode, void* out, int32_t out_mode);
 int apply_J_sweep(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode, int32_t max_cycles,
                   int32_t* cycles_host);
 int apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int32_t max_cycles, int32_t* cycles_host);
@@ -205,6 +207,12 @@ int fm_batch_split_info(fm_batch* b, int32_t* xcd_masks) {
 int fm_apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out_mode) {
     fm::clear_error();
     return fm::apply_J(b, ds, ds_mode, out, out_mode);
+}
+
+int fm_apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* hip_stream,
+                      const void* ds, int32_t ds_mode, void* out, int32_t out_mode) {
+    fm::clear_error();
+    return fm::apply_J_static(states, S, B, precision, hip_stream, ds, ds_mode, out, out_mode);
 }
 
 int fm_apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_mode) {

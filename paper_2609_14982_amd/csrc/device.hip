@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1280,6 +1281,149 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
     if (best_ms < 0.0f) { set_error("no schedule could be created for these states"); return FM_EINVAL; }
     clear_error();
     return FM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free primal apply (fm_apply_J_static)
+//
+// The scratch a batch would allocate - the state table the kernels index by
+// source and, for receiver output, the [S][N][B] node values - lives in one
+// file-scope device array instead.  Each device holds its own copy of the
+// array from module load until the process ends; host code only ever uses
+// the address hipGetSymbolAddress returns for the current device (the
+// array's name is a host-side stand-in, not a device address).  Every call on
+// a device shares that device's array, so calls that overlap on one device
+// race.  The rhs-group kernel runs (no cross-workgroup counters, so nothing
+// has to start at zero); the table is written by a kernel from its launch
+// arguments, so the call also needs no staging copy.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_static_mu;
+static void* g_static_ptr[kMaxDevices] = {};
+
+// The current device's address of the array, looked up once per device.
+static int static_scratch(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("device %d is beyond the %d devices the allocation-free path supports", dev, kMaxDevices);
+        return FM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("hipGetSymbolAddress of the static scratch failed: %s", hipGetErrorString(e));
+            return FM_EHIP;
+        }
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return FM_OK;
+}
+
+constexpr int kTableChunk = 12;   // SrcDev entries per table-writing launch (kernel arguments stay < 4 KB)
+struct TableChunk {
+    int32_t first, count;
+    SrcDev e[kTableChunk];
+};
+
+__global__ void k_put_table(SrcDev* dst, TableChunk c) {
+    const int i = (int)threadIdx.x;
+    if (i < c.count) dst[c.first + i] = c.e[i];
+}
+
+int apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precision, void* stream, const void* ds,
+                   int32_t ds_mode, void* out, int32_t out_mode) {
+    if (!states || S < 1) { set_error("need at least one state"); return FM_EINVAL; }
+    if (B < 1) { set_error("B must be >= 1"); return FM_EINVAL; }
+    if (precision != FM_FP64 && precision != FM_FP32) { set_error("precision must be 64 or 32"); return FM_EINVAL; }
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HostState* s0 = static_cast<HostState*>(states[0]);
+    if (!s0) { set_error("null state"); return FM_EINVAL; }
+    const int32_t R = (int32_t)s0->pk.rcv_ptr.size() - 1;
+    int32_t maxk = 0;
+    for (int32_t i = 0; i < S; i++) {
+        HostState* si = static_cast<HostState*>(states[i]);
+        if (!si) { set_error("null state %d", i); return FM_EINVAL; }
+        if (!si->same_grid(*s0)) { set_error("state %d has another grid shape", i); return FM_EINVAL; }
+        if ((int32_t)si->pk.rcv_ptr.size() - 1 != R) { set_error("state %d has another receiver count", i); return FM_EINVAL; }
+        if (!si->dev || si->dev->device != dev || (precision == FM_FP32 && !si->dev->blob32)) {
+            set_error("state %d is not resident on device %d in FP%d: create a batch over it once first "
+                      "(that call uploads the state and allocates)", i, dev, precision);
+            return FM_ESTATE;
+        }
+        maxk = std::max(maxk, si->pk.max_blk_k);
+    }
+    // the library's default rhs-group schedule
+    fm_tuning t{};
+    t.threads = 1024;
+    t.unroll = 2;
+    t.rhs_per_group = 1;
+    while (t.rhs_per_group < 4 && B % (t.rhs_per_group * 2) == 0) t.rhs_per_group *= 2;
+    t.xcd_aware = 1;
+    t.min_lds_bytes = 96 * 1024;
+    t.split = 1;
+    const size_t need = (size_t)maxk * t.rhs_per_group * sizeof(double);
+    if (need > kLdsMax) {
+        set_error("largest SCC block (%d nodes) needs %zu B of LDS", maxk, need);
+        return FM_EINVAL;
+    }
+    const size_t vbytes = precision == FM_FP64 ? 8 : 4;
+    const size_t table = ((sizeof(SrcDev) * (size_t)S) + 255) & ~size_t(255);
+    const size_t xbytes = out_mode == FM_OUT_RECEIVERS ? (size_t)S * (size_t)s0->N * (size_t)B * vbytes : 0;
+    if (table + xbytes > kStaticScratchBytes) {
+        set_error("this call needs %zu B of scratch (state table %zu B + node values %zu B); the allocation-free "
+                  "path holds at most %zu B", table + xbytes, table, xbytes, kStaticScratchBytes);
+        return FM_EINVAL;
+    }
+    void* base = nullptr;
+    int rc = static_scratch(dev, &base);
+    if (rc) return rc;
+    // a host-side batch object whose device pointers borrow the static array
+    fm_batch b;
+    for (int32_t i = 0; i < S; i++) b.states.push_back(static_cast<HostState*>(states[i]));
+    b.S = S;
+    b.B = B;
+    b.prec = precision;
+    b.R = R;
+    b.tun = t;
+    b.stream = (hipStream_t)stream;
+    b.N = s0->N;
+    b.st1 = s0->stride[1];
+    b.st2 = s0->stride[2];
+    b.device = dev;
+    b.lds_bytes = std::max(need, (size_t)t.min_lds_bytes);
+    b.items = S * (B / t.rhs_per_group);
+    b.per_xcd = (b.items + 7) / 8;
+    b.grid = 8 * b.per_xcd;
+    b.d_src = (SrcDev*)base;
+    b.scratch = xbytes ? (char*)base + table : nullptr;
+    for (int32_t i0 = 0; i0 < S; i0 += kTableChunk) {
+        TableChunk c{};
+        c.first = i0;
+        c.count = std::min(kTableChunk, S - i0);
+        for (int k = 0; k < c.count; k++) {
+            const DeviceState* d = b.states[i0 + k]->dev;
+            c.e[k] = d->d;
+            if (precision == FM_FP32) {
+                c.e[k].fwts = d->fwts32;
+                c.e[k].rwts = d->rwts32;
+                c.e[k].cal_nat = d->cal32;
+            }
+        }
+        hipLaunchKernelGGL(k_put_table, dim3(1), dim3(64), 0, b.stream, b.d_src, c);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) { set_error("state table launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    }
+    b.d_src = (SrcDev*)base;
+    rc = apply_J(&b, ds, ds_mode, out, out_mode);
+    b.d_src = nullptr;   // borrowed: nothing of b is freed
+    b.scratch = nullptr;
+    return rc;
 }
 
 int batch_set_stream(fm_batch* b, void* stream) {
