@@ -62,7 +62,8 @@ struct fm_batch {
     fm_tuning tun{};
     hipStream_t stream = nullptr;
     fm::SrcDev* d_src = nullptr;     // [S]
-    void* scratch = nullptr;         // [S][N][B] of the batch precision
+    void* scratch = nullptr;         // [S][N][xB] of the batch precision
+    int32_t xB = 0;                  // values per scratch row (B, or B padded to whole 128-byte lines)
     int64_t N = 0;
     int64_t st1 = 1, st2 = 1;
     int device = -1;
@@ -111,6 +112,8 @@ struct ApplyArgs {
     int64_t st1, st2;       // node strides of logical axes 1 and 2
     int32_t R;              // receivers per source (receiver layouts)
     int32_t in_mode, out_mode;
+    int32_t xB;             // values per row of work ([S][N][xB], xB >= B; rows padded to 128 bytes
+                            // when work is the batch's own scratch of a node-split batch)
     const void* in;         // J: ds ; J^T: w
     void* out;              // J: nodes output (or unused) ; J^T: per-source output
     void* work;             // J: X (out or scratch) ; J^T: lambda scratch

@@ -241,10 +241,10 @@ __global__ void k_gather_receivers(ApplyArgs a) {
         const int64_t rr = (t / a.B) % a.R;
         const int64_t alpha = t / ((int64_t)a.B * a.R);
         const SrcDev& sd = a.src[alpha];
-        const V* x = (const V*)a.work + alpha * a.N * a.B + b;
+        const V* x = (const V*)a.work + alpha * a.N * a.xB + b;
         V acc = (V)0;
         for (int32_t e = sd.rcv_ptr[rr]; e < sd.rcv_ptr[rr + 1]; ++e)
-            acc += (V)sd.rcv_wt[e] * x[(int64_t)sd.rcv_node[e] * a.B];
+            acc += (V)sd.rcv_wt[e] * x[(int64_t)sd.rcv_node[e] * a.xB];
         ((V*)a.out)[t] = acc;
     }
 }
@@ -259,6 +259,7 @@ __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
     constexpr int VW = 16 / (int)sizeof(V);
     constexpr int SU = 16;
     const int64_t NB = a.N * a.B;
+    const int64_t NXB = a.N * a.xB;          // one source's rows in work (xB >= B values each)
     const V* __restrict__ work = (const V*)a.work;
     V* __restrict__ out = (V*)a.out;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -266,6 +267,7 @@ __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
         for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NB / VW; t += stride) {
             const int64_t e0 = t * VW;
             const int64_t node = e0 / a.B;
+            const int64_t w0 = node * a.xB + (e0 - node * a.B);
             V acc[VW];
 #pragma unroll
             for (int v = 0; v < VW; ++v) acc[v] = (V)0;
@@ -275,7 +277,7 @@ __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
 #pragma unroll
                 for (int u = 0; u < SU; ++u) {
                     if (a0 + u < a.S) {
-                        x[u] = ld_stream<V, VW>(work + (int64_t)(a0 + u) * NB + e0);
+                        x[u] = ld_stream<V, VW>(work + (int64_t)(a0 + u) * NXB + w0);
                         c[u] = gld((const V*)gld(cal + (a0 + u)) + node);
                     }
                 }
@@ -295,7 +297,8 @@ __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
         for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NB; t += stride) {
             const int64_t node = t / a.B;
             V acc = (V)0;
-            for (int alpha = 0; alpha < a.S; ++alpha) acc += ((const V*)cal[alpha])[node] * work[alpha * NB + t];
+            const int64_t w0 = node * a.xB + (t - node * a.B);
+            for (int alpha = 0; alpha < a.S; ++alpha) acc += ((const V*)cal[alpha])[node] * work[alpha * NXB + w0];
             out[t] = acc;
         }
     }
@@ -443,6 +446,7 @@ static hipError_t launch_split(const fm_batch* b, bool fwd, const ApplyArgs& a0)
     s.fail_w = s.abort_w + kCtrStride;
     s.stage = b->stage;
     s.stage_rows = b->stage_rows;
+    s.stage_B = (int32_t)(((b->B * sizeof(double) + 127) / 128) * 128 / sizeof(double));
     s.P = b->tun.split;
     s.lds_rows = b->split_lds_rows;
     s.rcv_lds = b->split_rcv_lds;
@@ -450,7 +454,7 @@ static hipError_t launch_split(const fm_batch* b, bool fwd, const ApplyArgs& a0)
     s.wg_map = b->wg_map;
     s.src_P = b->wg_map ? b->wg_map + b->split_grid : nullptr;
     const size_t vbytes = b->prec == FM_FP64 ? 8 : 4;
-    s.inv_l1 = ((size_t)b->B * vbytes) % 128 != 0 || ((uintptr_t)a.work & 127u) != 0;
+    s.inv_l1 = ((size_t)a.xB * vbytes) % 128 != 0 || ((uintptr_t)a.work & 127u) != 0;
     hipLaunchKernelGGL(k_split_reset, dim3(1), dim3(256), 0, b->stream, s, b->S);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -483,7 +487,8 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
         return FM_EINVAL;
     }
     // the kernel addresses one source's [N][B] arrays with 32-bit byte offsets
-    const bool fits32 = (uint64_t)b->N * (uint64_t)b->B * (fp64 ? 8u : 4u) < (1ull << 32) &&
+    const uint64_t xrow = (((uint64_t)b->B * (fp64 ? 8u : 4u) + 127u) / 128u) * 128u;   // padded node-value row
+    const bool fits32 = (uint64_t)b->N * xrow < (1ull << 32) &&
                         (uint64_t)b->N * 4u * (fp64 ? 8u : 4u) < (1ull << 32);
     if (!built || !fits32) {
         if (t.split == 0) { t.split = 1; return FM_OK; }
@@ -653,7 +658,8 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     }
     b->stage_rows = rows;
     if (b->split_lds_rows < 1) { set_error("LDS too small for one staged row"); return FM_EINVAL; }
-    const size_t stage = (size_t)b->S * rows * b->B * sizeof(double);
+    const size_t stage_B = ((b->B * sizeof(double) + 127) / 128) * 128 / sizeof(double);   // whole lines per row
+    const size_t stage = (size_t)b->S * rows * stage_B * sizeof(double);
     const size_t sync = ((size_t)2 * b->S * kCtrStride + 64) * sizeof(unsigned);
     hipError_t e = hipMalloc(&b->stage, stage);
     if (e == hipSuccess) e = hipMalloc((void**)&b->sync, sync);
@@ -775,7 +781,14 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
         batch_free(b);
         return rc;
     }
-    const size_t scratch = (size_t)S * (size_t)b->N * (size_t)B * vbytes;
+    // the node split reads neighbour rows of the scratch through the L1
+    // without invalidating it at every level barrier, which needs every
+    // node's row to be whole 128-byte lines: rows shorter than that are
+    // padded (FP32 with 16 rhs, FP64 with 8)
+    b->xB = B;
+    if (b->tun.split > 1 && ((size_t)B * vbytes) % 128 != 0)
+        b->xB = (int32_t)((((size_t)B * vbytes + 127) / 128) * 128 / vbytes);
+    const size_t scratch = (size_t)S * (size_t)b->N * (size_t)b->xB * vbytes;
     e = hipMalloc(&b->scratch, scratch);
     if (e != hipSuccess) {
         b->scratch = nullptr;
@@ -817,6 +830,7 @@ ApplyArgs batch_args(const fm_batch* b) {
     a.per_xcd = b->per_xcd;
     a.xcd_aware = b->tun.xcd_aware;
     a.N = b->N;
+    a.xB = b->B;
     a.st1 = b->st1;
     a.st2 = b->st2;
     a.R = b->R;
@@ -849,6 +863,7 @@ int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out
     a.out_mode = out_mode;
     a.out = out;
     a.work = out_mode == FM_OUT_NODES ? out : b->scratch;
+    a.xB = out_mode == FM_OUT_NODES ? b->B : b->xB;
     hipError_t e = b->tun.split > 1       ? launch_split(b, true, a)
                    : b->prec == FM_FP64 ? launch_sweep<double>(true, b->tun, a, b->grid, b->lds_bytes, b->stream)
                                         : launch_sweep<float>(true, b->tun, a, b->grid, b->lds_bytes, b->stream);
@@ -878,6 +893,7 @@ int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_
     a.out_mode = out_mode;
     a.out = out;
     a.work = b->scratch;
+    a.xB = b->xB;
     hipError_t e = b->tun.split > 1       ? launch_split(b, false, a)
                    : b->prec == FM_FP64 ? launch_sweep<double>(false, b->tun, a, b->grid, b->lds_bytes, b->stream)
                                         : launch_sweep<float>(false, b->tun, a, b->grid, b->lds_bytes, b->stream);
@@ -1279,6 +1295,7 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
     if (n_out) *n_out = n;
     if (rc != FM_OK) return rc;
     if (best_ms < 0.0f) { set_error("no schedule could be created for these states"); return FM_EINVAL; }
+    if (!key.empty()) tune_store(cache_path, key, *best, best_ms);
     clear_error();
     return FM_OK;
 }
@@ -1402,6 +1419,7 @@ int apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precis
     b.grid = 8 * b.per_xcd;
     b.d_src = (SrcDev*)base;
     b.scratch = xbytes ? (char*)base + table : nullptr;
+    b.xB = B;
     for (int32_t i0 = 0; i0 < S; i0 += kTableChunk) {
         TableChunk c{};
         c.first = i0;

@@ -21,9 +21,12 @@
 // invalidate) so that the result is right either way.  A node's values are
 // written once per launch and read only after the barrier that follows, and
 // with rows of a multiple of 128 bytes no cache line holds two nodes, so no
-// stale line can sit in a CU's L1; shorter rows take the acquire at every
-// barrier.  Every wait is bounded: after ~10 s without progress the wave sets
-// the launch's abort word, so that all later barriers of that launch return at
+// stale line can sit in a CU's L1.  The batch's own node-value scratch and the
+// block staging rows are therefore padded to whole lines (FP32 with 16 rhs,
+// FP64 with 8); only a caller's output array with shorter rows (J to all
+// nodes) takes the cache-invalidating acquire at every barrier.  Every wait
+// is bounded: after ~10 s without progress the wave sets the launch's abort
+// word, so that all later barriers of that launch return at
 // once and the launch always ends, and the batch's sticky failure word, which
 // fm_batch_status reports.  The abort word is cleared before every launch, so
 // one failed launch never shortens the waits of the next.
@@ -43,8 +46,10 @@ struct SplitArgs {
     unsigned* xmask;    // [S] XCDs seen per source, one per 128-byte line
     unsigned* abort_w;  // one word: set when a barrier wait of this launch timed out
     unsigned* fail_w;   // one word, sticky until fm_batch_status: some launch timed out
-    void* stage;        // [S][stage_rows][B] block right-hand sides
+    void* stage;        // [S][stage_rows][stage_B] block right-hand sides (FP64)
     int64_t stage_rows;
+    int32_t stage_B;    // doubles per staged row: B rounded up to whole 128-byte lines, so
+                        // no line holds two rows (read by other workgroups after a barrier)
     int32_t P;          // workgroups per source
     int32_t lds_rows;   // rows of b_C per LDS chunk (vector block path)
     int32_t inv_l1;     // rows are not a multiple of 128 bytes
@@ -144,7 +149,7 @@ __device__ __forceinline__ uint64_t ld_meta(const uint64_t* p) {
 // instructions.
 template <typename V, int VW>
 struct Node32 {
-    uint32_t row;    // byte offset of this lane's values in a [N][B] array
+    uint32_t row;    // byte offset of this lane's values in the node-value array X (rows of xrowb bytes)
     uint32_t mask;   // neighbour mask (0 for an empty slot)
     uint32_t ovf;
     bool ok;
@@ -185,16 +190,16 @@ struct RcvLds {
 
 template <int DIR, typename V, int VW>
 __device__ __forceinline__ void fetch32(Node32<V, VW>& p, uint64_t m, int pos, const char* __restrict__ wtc,
-                                        const char* __restrict__ inc, uint32_t rowb, uint32_t lane_off,
+                                        const char* __restrict__ inc, uint32_t rowb, uint32_t xrowb, uint32_t lane_off,
                                         const Ctx& cx, const SrcDev& sd, const LevelDesc& d, const V* in,
                                         const RcvLds& rl) {
     const uint32_t node = (uint32_t)(m & kNodeMask);
-    p.row = node * rowb + lane_off;
+    p.row = node * xrowb + lane_off;
     p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
     p.mask = (uint32_t)(m >> kMaskShift);
     p.rec = ldb_stream<V, 4>(wtc, (uint32_t)pos * (uint32_t)(4 * sizeof(V)));
     if (DIR == kFwd || !cx.rcv_in) {
-        p.inp = ldb_stream<V, VW>(inc, p.row);
+        p.inp = ldb_stream<V, VW>(inc, node * rowb + lane_off);
     } else {
 #pragma unroll
         for (int v = 0; v < VW; ++v) p.inp.v[v] = (V)0;
@@ -274,9 +279,9 @@ template <int DIR, typename V, int LPN, int NT>
 __device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
                                                 const char* __restrict__ wtc, const char* __restrict__ inc,
                                                 const V* __restrict__ in, const V* __restrict__ ovf_base,
-                                                const char* __restrict__ Xc, const Strides32 sx, uint32_t lane_off,
-                                                double* __restrict__ stage, const Ctx& cx, int P, int part,
-                                                int slot0, const RcvLds& rl) {
+                                                const char* __restrict__ Xc, const Strides32 sx, uint32_t xrowb,
+                                                uint32_t lane_off, double* __restrict__ stage, int SB, const Ctx& cx,
+                                                int P, int part, int slot0, const RcvLds& rl) {
     constexpr int VW = 16 / (int)sizeof(V);
     constexpr int SLOTS = NT / LPN;
     constexpr uint32_t ROWB = LPN * VW * sizeof(V);
@@ -289,13 +294,14 @@ __device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDes
         share(k, P, part, lo, hi);
         for (int mi = lo + slot0; mi < hi; mi += SLOTS) {
             Node32<V, VW> p;
-            fetch32<DIR, V, VW>(p, ld_meta(meta + bp + mi), bp + mi, wtc, inc, ROWB, lane_off, cx, sd, d, in, rl);
+            fetch32<DIR, V, VW>(p, ld_meta(meta + bp + mi), bp + mi, wtc, inc, ROWB, xrowb, lane_off, cx, sd, d, in,
+                                rl);
             Pack<V, VW> xv[3];
             nbrs32<V, VW>(p, Xc, sx, xv);
             if (DIR == kRev && cx.rcv_in && rl.on) rcv_add<V, VW>(p, bp + mi, d, rl, cx.B, cx.rhs0);
             Pack<double, VW> o;
             acc32<DIR, V, VW, double>(p, xv, ovf_base, Xc, sx, o.v);
-            st<double, VW>(stage + (moff + mi) * cx.B + cx.rhs0, o);
+            st<double, VW>(stage + (moff + mi) * SB + cx.rhs0, o);
         }
     }
 }
@@ -323,8 +329,8 @@ __device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDes
 template <int DIR, typename V, int B, int NT>
 __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const LevelDesc& d,
                                                        const uint64_t* __restrict__ meta, const V* __restrict__ wts,
-                                                       const double* __restrict__ stage, V* __restrict__ X,
-                                                       V* __restrict__ outp, int P, int part) {
+                                                       const double* __restrict__ stage, int SB, V* __restrict__ X,
+                                                       int XB, V* __restrict__ outp, int P, int part) {
     typedef double d4 __attribute__((ext_vector_type(4)));
     constexpr int WAVES = NT / 64;
     constexpr int TW = 4;                       // 16-row tiles per wave
@@ -344,7 +350,7 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
         share(k, P, part, lo, hi);
         for (int r0 = lo; r0 < hi; r0 += ROWS) {
             for (int ct = 0; ct < B; ct += 16) {
-                const double* __restrict__ bsrc = stage + moff * B + ct + lr;
+                const double* __restrict__ bsrc = stage + moff * SB + ct + lr;
                 int rowc[TW];
 #pragma unroll
                 for (int t = 0; t < TW; ++t) rowc[t] = min(r0 + (wave * TW + t) * 16 + lr, hi - 1);
@@ -357,7 +363,7 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
                     for (int g = 0; g < G; ++g) {
                         const int col = j + 4 * g + lk;
                         const int cc = min(col, k - 1);
-                        bv[g] = bsrc[(int64_t)cc * B];
+                        bv[g] = bsrc[(int64_t)cc * SB];
 #pragma unroll
                         for (int t = 0; t < TW; ++t) av[g][t] = Mx[(size_t)cc * k + rowc[t]];
                     }
@@ -377,7 +383,7 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
                         if (i < hi) {
                             const uint64_t mw = gld(meta + bp + i);
                             const int64_t node = (int64_t)(mw & kNodeMask);
-                            X[node * B + ct + lr] = (V)acc[t][r];
+                            X[node * XB + ct + lr] = (V)acc[t][r];
                             if (DIR == kRev && outp) outp[node * B + ct + lr] = gld(wts + (size_t)(bp + i) * 4) * (V)acc[t][r];
                         }
                     }
@@ -389,8 +395,8 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
 
 template <int DIR, typename V, int B, int NT>
 __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
-                                                  const V* __restrict__ wts, const double* __restrict__ stage,
-                                                  V* __restrict__ X, V* __restrict__ outp, int P, int part,
+                                                  const V* __restrict__ wts, const double* __restrict__ stage, int SB,
+                                                  V* __restrict__ X, int XB, V* __restrict__ outp, int P, int part,
                                                   int lds_rows, double* lds) {
     constexpr int G = 16;
     constexpr int CH = 8;    // staged values per thread and round
@@ -401,7 +407,7 @@ __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelD
         const int64_t moff = gld(sd.blk_moff + (blk));
         const __attribute__((address_space(1))) double* __restrict__ Mx =
             gptr(DIR == kFwd ? sd.inv + gld(sd.blk_inv + (blk)) : sd.invt + gld(sd.blk_inv + (blk)));
-        const double* __restrict__ bsrc = stage + moff * B;
+        const double* __restrict__ bsrc = stage + moff * SB;
         int lo, hi;
         share(k, P, part, lo, hi);
         // every thread of the workgroup passes the same barriers: the row
@@ -415,14 +421,14 @@ __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelD
             for (int j0 = 0; j0 < k; j0 += lds_rows) {
                 const int jn = min(lds_rows, k - j0);
                 const int nv = jn * B;
-                const double* __restrict__ bs = bsrc + (int64_t)j0 * B;
+                const double* __restrict__ bs = bsrc + (int64_t)j0 * SB;
                 __syncthreads();
                 for (int t0 = 0; t0 < nv; t0 += NT * CH) {
                     double v[CH];
 #pragma unroll
                     for (int c = 0; c < CH; ++c) {
                         const int t = t0 + c * NT + (int)threadIdx.x;
-                        v[c] = t < nv ? bs[t] : 0.0;
+                        v[c] = t < nv ? bs[(t / B) * SB + (t % B)] : 0.0;
                     }
 #pragma unroll
                     for (int c = 0; c < CH; ++c) {
@@ -457,7 +463,7 @@ __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelD
                 const uint64_t mw = gld(meta + bp + i);
                 const int64_t node = (int64_t)(mw & kNodeMask);
                 const V c = gld(wts + (size_t)(bp + i) * 4);
-                V* dst = X + node * B;
+                V* dst = X + node * XB;
 #pragma unroll
                 for (int rr = 0; rr < B; ++rr) dst[rr] = (V)acc[rr];
                 if (DIR == kRev && outp) {
@@ -542,7 +548,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     cx.N = a.N;
     cx.rcv_in = RCV;
     const V* __restrict__ in;
-    V* __restrict__ X = (V*)a.work + (size_t)alpha * NB;
+    // node values: rows of a.xB >= B values (padded to whole 128-byte lines
+    // when the array is the batch's own scratch, so no line holds two nodes)
+    V* __restrict__ X = (V*)a.work + (size_t)alpha * a.N * a.xB;
     V* __restrict__ outp = nullptr;
     if (DIR == kFwd) {
         in = (const V*)a.in + (a.in_mode == FM_DS_PER_PAIR ? (size_t)alpha * NB : 0);
@@ -550,18 +558,21 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         in = (const V*)a.in + (cx.rcv_in ? (size_t)alpha * a.R * B : (size_t)alpha * NB);
         if (a.out_mode == FM_JT_PER_SOURCE) outp = (V*)a.out + (size_t)alpha * NB;
     }
-    double* __restrict__ stage = (double*)s.stage + (size_t)alpha * s.stage_rows * B;
+    double* __restrict__ stage = (double*)s.stage + (size_t)alpha * s.stage_rows * s.stage_B;
     // byte-offset views of the same arrays (each spans < 4 GiB, checked on the host)
-    constexpr uint32_t ROWB = B * sizeof(V);
+    constexpr uint32_t ROWB = B * sizeof(V);                 // input and per-source output rows
+    // node-value rows (a compile-time ROWB when B values already fill whole lines)
+    const uint32_t XROWB = ROWB % 128 == 0 ? ROWB : (uint32_t)a.xB * sizeof(V);
+    const int xsh = ROWB % 128 == 0 || a.xB == B ? 0 : 1;   // XROWB = ROWB << xsh
     const uint32_t lane_off = (uint32_t)(cx.rhs0 * sizeof(V));
     const char* __restrict__ Xc = reinterpret_cast<const char*>(X);
     char* __restrict__ Xw = reinterpret_cast<char*>(X);
     const char* __restrict__ inc = reinterpret_cast<const char*>(in);
     const char* __restrict__ wtc = reinterpret_cast<const char*>(wts);
     Strides32 sx;
-    sx.a0 = (int32_t)ROWB;
-    sx.a1 = (int32_t)(a.st1 * ROWB);
-    sx.a2 = (int32_t)(a.st2 * ROWB);
+    sx.a0 = (int32_t)XROWB;
+    sx.a1 = (int32_t)(a.st1 * XROWB);
+    sx.a2 = (int32_t)(a.st2 * XROWB);
     // transpose from receiver data: copy this source's receiver entries (in
     // the order of the reverse levels), each input value times the entry's
     // weight, and their positions to LDS
@@ -622,7 +633,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         for (int q = 0; q < U; ++q) {
             ops[q].ok = mw[q] != ~0ull;
             if (ops[q].ok)
-                fetch32<DIR, V, VW>(ops[q], mw[q], c.d.p0 + c.base + slot0 + q * SLOTS, wtc, inc, ROWB, lane_off, cx,
+                fetch32<DIR, V, VW>(ops[q], mw[q], c.d.p0 + c.base + slot0 + q * SLOTS, wtc, inc, ROWB, XROWB, lane_off, cx,
                                     sd, c.d, in, rl);
         }
     };
@@ -669,7 +680,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                         Pack<V, VW> os;
 #pragma unroll
                         for (int v = 0; v < VW; ++v) os.v[v] = oscale[q] * o[q].v[v];
-                        st<V, VW>(reinterpret_cast<V*>(reinterpret_cast<char*>(outp) + orow[q]), os);
+                        const uint32_t irow = ((orow[q] - lane_off) >> xsh) + lane_off;
+                        st<V, VW>(reinterpret_cast<V*>(reinterpret_cast<char*>(outp) + irow), os);
                     }
                 }
             }
@@ -678,8 +690,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             // a level with blocks fetches the next level's first batch after
             // its block products (that state is not kept live across them)
             if (blocks)
-                split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, lane_off, stage, cx, P,
-                                                 part, slot0, rl);
+                split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, XROWB, lane_off, stage,
+                                                 s.stage_B, cx, P, part, slot0, rl);
             group_barrier(g, P);
             if (first) {
                 first = false;
@@ -689,10 +701,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             }
             if (blocks) {
                 if constexpr (B % 16 == 0)
-                    split_block_solve_mfma<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part);
+                    split_block_solve_mfma<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, s.stage_B, X, a.xB, outp, P, part);
                 else
-                    split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, X, outp, P, part, s.lds_rows,
-                                                     lds + s.stage_off);
+                    split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, s.stage_B, X, a.xB, outp, P, part,
+                                                     s.lds_rows, lds + s.stage_off);
                 if (more) fetch_batch(cN, mN);
                 group_barrier(g, P);
             }
