@@ -344,6 +344,37 @@ int fm_lsqr_buffers(const fm_lsqr* L, void** x, void** u, void** v, double** sca
 void fm_lsqr_free(fm_lsqr* L);
 
 /*
+ * CGLS over the paired actions: the inner solve of a Gauss-Newton step
+ * (Algorithm 1, Phase III, with CGLS in place of LSMR and no regularisation),
+ * min ||J x - d||_2 for each of the B columns independently, J and J^T applied
+ * once per iteration at the same frozen state.  Layouts as for LSQR: x and the
+ * search direction are model blocks [N][B] (FM_DS_BROADCAST), d and the
+ * residual r are stacked receiver data [S][R][B], J^T sums over the sources.
+ * Per column: x_0 = 0, r_0 = d, s_0 = J^T d, p_0 = s_0, gamma_0 = ||s_0||^2;
+ * then q = J p, alpha = gamma / ||q||^2, x += alpha p, r -= alpha q,
+ * s = J^T r, gamma' = ||s||^2, p = s + (gamma'/gamma) p.  A column whose
+ * denominators reach zero stops moving.  Same rules as LSQR: everything is on
+ * the device, create allocates, the other calls only enqueue kernels on the
+ * batch stream, and fm_cgls_capture records n iterations as one HIP graph.
+ *   fm_cgls_create   max_iter: rows of the residual history (>= 0)
+ *   fm_cgls_buffers  device pointers of x [N][B], r [S][R][B], the scalars
+ *                    [6][B] (gamma, ||q||^2, alpha, gamma', beta, ||r||^2)
+ *                    and the history [max_iter + 1][B] of ||r||^2: row 0 at
+ *                    start, row k after the k-th iteration enqueued since
+ *                    start (iterations past max_iter are not recorded; a
+ *                    captured graph rewrites the rows it recorded)
+ * Errors: FM_EINVAL, FM_ENOMEM, FM_EHIP, FM_ESTATE.
+ */
+typedef struct fm_cgls fm_cgls;
+int fm_cgls_create(fm_batch* b, int32_t max_iter, fm_cgls** out);
+int fm_cgls_start(fm_cgls* C, const void* d);
+int fm_cgls_iterate(fm_cgls* C, int32_t n);
+int fm_cgls_capture(fm_cgls* C, int32_t n);
+int fm_cgls_replay(fm_cgls* C);
+int fm_cgls_buffers(const fm_cgls* C, void** x, void** r, double** scalars, double** history);
+void fm_cgls_free(fm_cgls* C);
+
+/*
  * Cell-velocity model map M_alpha (Section 4.4, eq. (source-jacobian)): the
  * model is one velocity per cell of the logical grid (hexahedra between
  * nodes, quadrilaterals in 2-D; cell id ci + (n1-1) (cj + (n2-1) ck), 2-D

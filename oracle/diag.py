@@ -136,3 +136,56 @@ def downstream_closure(N: int, j: np.ndarray, i: np.ndarray, seeds: np.ndarray) 
         mark[nxt] = True
         frontier = nxt
     return mark
+
+
+# ---------------------------------------------------------------------------
+# Robustness of the cyclic blocks (Section 5.2.2): the SCCs are a structural
+# feature of the frozen full-metric transport, not an artefact of retained
+# precision or negligible coefficients, if (a) small random perturbations of
+# the stored traveltime leave the SCC partition unchanged over a broad range,
+# and (b) removing progressively larger weak dependencies eliminates all
+# nontrivial SCCs only at cutoffs far above roundoff-level weights.
+# ---------------------------------------------------------------------------
+
+def perturbed_traveltime(T: np.ndarray, src: int, eps: float, seed: int) -> np.ndarray:
+    """T (1 + eps xi) with seeded standard normal xi; the source keeps T = 0."""
+    xi = np.random.default_rng(seed).standard_normal(T.shape)
+    Tp = T * (1.0 + eps * xi)
+    Tp[src] = 0.0
+    return Tp
+
+
+def same_partition(a, b) -> bool:
+    """Whether two lists of nontrivial SCCs (sorted node arrays) are the same sets."""
+    if len(a) != len(b):
+        return False
+    ka = sorted(a, key=lambda c: int(c[0]))
+    kb = sorted(b, key=lambda c: int(c[0]))
+    return all(np.array_equal(x, y) for x, y in zip(ka, kb))
+
+
+def weak_edge_cutoff(W: sp.csr_matrix, tau: float) -> sp.csr_matrix:
+    """W with every dependency of weight below tau removed."""
+    Wt = W.tocsr(copy=True)
+    Wt.data[Wt.data < tau] = 0.0
+    Wt.eliminate_zeros()
+    return Wt
+
+
+def scc_survival_cutoff(W: sp.csr_matrix) -> float:
+    """The largest tau such that keeping only the dependencies of weight
+    >= tau still leaves a nontrivial SCC (0 if W has none): every cutoff above
+    it removes all cyclic blocks.  Raising the cutoff only removes edges, so
+    the test is monotone: bisection over the distinct edge weights."""
+    w = np.unique(W.tocsr().data)
+    w = w[w > 0]
+    if not scc_summary(W):
+        return 0.0
+    lo, hi = 0, w.size      # keeping weights >= w[lo] leaves an SCC; >= w[hi] (or nothing) leaves none
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if scc_summary(weak_edge_cutoff(W, w[mid])):
+            lo = mid
+        else:
+            hi = mid
+    return float(w[lo])

@@ -18,6 +18,7 @@ from .binding import (  # noqa: F401
     FM_W_NODES,
     FM_W_RECEIVERS,
     Batch,
+    Cgls,
     apply_J_static,
     autotune,
     FmError,

@@ -14,14 +14,15 @@ uniform scaling direction ds = s, where both give T).
 
 gauss_newton_step computes the Gauss-Newton increment of the data misfit
 0.5 ||P T(s) - d||^2 by CGLS on J (Algorithm 1, with CGLS in
-place of LSMR and no regularisation).
+place of LSMR and no regularisation); the CGLS iterations run in the
+library's kernels, captured as one HIP graph.
 """
 from __future__ import annotations
 
 import numpy as np
 import torch
 
-from .binding import (FM_DS_BROADCAST, FM_FP64, FM_JT_SUMMED, FM_OUT_RECEIVERS, FM_W_RECEIVERS, Batch,
+from .binding import (FM_DS_BROADCAST, FM_FP64, FM_JT_SUMMED, FM_OUT_RECEIVERS, FM_W_RECEIVERS, Batch, Cgls,
                       build_frozen_states)
 
 
@@ -43,6 +44,7 @@ class TransportProblem:
         """Nonlinear solve at s and Phase I setup: returns (T [S][N], batch)."""
         s = np.ascontiguousarray(s, dtype=np.float64)
         T = np.ascontiguousarray(self.solver(s), dtype=np.float64)
+        self.last_T = T     # the state of the latest linearisation (for checks against an oracle)
         states = build_frozen_states(self.dim, self.n1, self.n2, self.n3, self.G, T, s, self.src,
                                      self.rcv, nthreads=self.nthreads)
         return T, Batch(states, B, FM_FP64, stream=stream)
@@ -89,30 +91,36 @@ def apply_JT_summed(batch: Batch, y: torch.Tensor) -> torch.Tensor:
     return out
 
 
-def cgls(batch: Batch, r: torch.Tensor, n_iter: int):
-    """CGLS for min ||J x - r|| per column: r [S][R][B] -> (x [N][B], residual norms per iteration)."""
-    B = batch.B
-    x = torch.zeros((batch.N, B), device=r.device, dtype=r.dtype)
-    res = r.clone()
-    s = apply_JT_summed(batch, res)
-    p = s.clone()
-    gamma = (s * s).sum(dim=0)
-    norms = [torch.linalg.vector_norm(res.reshape(-1, B), dim=0)]
-    for _ in range(n_iter):
-        q = apply_J_receivers(batch, p)
-        qq = (q * q).reshape(-1, B).sum(dim=0)
-        alpha = torch.where(qq > 0, gamma / torch.where(qq > 0, qq, torch.ones_like(qq)), torch.zeros_like(qq))
-        x += alpha * p
-        res -= alpha * q
-        s = apply_JT_summed(batch, res)
-        gnew = (s * s).sum(dim=0)
-        beta = torch.where(gamma > 0, gnew / torch.where(gamma > 0, gamma, torch.ones_like(gamma)),
-                           torch.zeros_like(gamma))
-        p = s + beta * p
-        gamma = gnew
-        norms.append(torch.linalg.vector_norm(res.reshape(-1, B), dim=0))
-    batch.status()
-    return x, torch.stack(norms)
+def cgls(batch: Batch, r: torch.Tensor, n_iter: int, graph: bool = True):
+    """CGLS for min ||J x - r|| per column: r [S][R][B] -> (x [N][B], residual
+    norms [n_iter + 1][B]).  Every step runs in the library (fm_cgls): with
+    graph=True the n_iter iterations are captured once as a HIP graph and
+    replayed, so the loop has no host round trip."""
+    solver = Cgls(batch, max_iter=n_iter)
+    home = batch._stream
+    # a graph is captured from a stream of its own (the null stream cannot be
+    # captured); it starts after the caller's pending work on that stream
+    side = torch.cuda.Stream() if graph and home.cuda_stream == 0 else None
+    try:
+        if side is not None:
+            side.wait_stream(home)
+            batch.set_stream(side)
+        solver.start(r.contiguous())
+        if n_iter > 0:
+            if graph:
+                solver.capture(n_iter)
+                solver.replay()
+            else:
+                solver.iterate(n_iter)
+        batch.status()
+        x = solver.x()
+        norms = torch.sqrt(solver.history()[:n_iter + 1])
+    finally:
+        if side is not None:
+            home.wait_stream(side)
+            batch.set_stream(home)
+        solver.free()
+    return x, norms
 
 
 def gauss_newton_step(problem: TransportProblem, s: np.ndarray, d_obs: np.ndarray, n_iter: int = 30):

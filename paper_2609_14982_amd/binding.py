@@ -7,7 +7,9 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_PKG, "libfmbtf.so")
+# FMBTF_LIB selects another build of the same library (the sanitizer build of
+# the host code, for CPU checks)
+_LIB_PATH = os.environ.get("FMBTF_LIB") or os.path.join(_PKG, "libfmbtf.so")
 
 FM_OK, FM_EINVAL, FM_ESINGULAR, FM_ENOMEM, FM_EHIP, FM_ESTATE = 0, -1, -2, -3, -4, -5
 FM_FP64, FM_FP32 = 64, 32
@@ -28,6 +30,8 @@ SYMBOLS = (
     "fm_apply_JT", "fm_apply_J_sweep", "fm_apply_JT_sweep", "fm_batch_free", "fm_last_error",
     "fm_lsqr_create", "fm_lsqr_start", "fm_lsqr_iterate", "fm_lsqr_capture", "fm_lsqr_replay",
     "fm_lsqr_buffers", "fm_lsqr_free", "fm_autotune",
+    "fm_cgls_create", "fm_cgls_start", "fm_cgls_iterate", "fm_cgls_capture", "fm_cgls_replay",
+    "fm_cgls_buffers", "fm_cgls_free",
     "fm_model_map_create", "fm_model_map_sizes", "fm_model_map_slowness", "fm_model_map_set_stream",
     "fm_model_map_apply", "fm_model_map_apply_T", "fm_model_map_free",
 )
@@ -106,6 +110,13 @@ def load():
         "fm_lsqr_replay": (C.c_int, [vp]),
         "fm_lsqr_buffers": (C.c_int, [vp, vp, vp, vp, vp]),
         "fm_lsqr_free": (None, [vp]),
+        "fm_cgls_create": (C.c_int, [vp, i32, vp]),
+        "fm_cgls_start": (C.c_int, [vp, vp]),
+        "fm_cgls_iterate": (C.c_int, [vp, i32]),
+        "fm_cgls_capture": (C.c_int, [vp, i32]),
+        "fm_cgls_replay": (C.c_int, [vp]),
+        "fm_cgls_buffers": (C.c_int, [vp, vp, vp, vp, vp]),
+        "fm_cgls_free": (None, [vp]),
         "fm_last_error": (C.c_char_p, []),
         "fm_model_map_create": (C.c_int, [i32, i64, i64, i64, vp, vp, vp]),
         "fm_model_map_sizes": (C.c_int, [vp, vp, vp]),
@@ -535,6 +546,63 @@ class Lsqr:
     def free(self):
         if getattr(self, "_ptr", None) is not None and self._ptr.value:
             load().fm_lsqr_free(self._ptr)
+            self._ptr = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Cgls:
+    """fm_cgls*: CGLS over the paired actions of a batch (device-resident)."""
+
+    def __init__(self, batch: Batch, max_iter: int = 100):
+        self.batch = batch
+        self.max_iter = int(max_iter)
+        out = C.c_void_p()
+        _check(load().fm_cgls_create(batch._ptr, self.max_iter, C.byref(out)))
+        self._ptr = out
+        ptrs = [C.c_void_p() for _ in range(4)]
+        _check(load().fm_cgls_buffers(self._ptr, *[C.byref(p) for p in ptrs]))
+        self._x, self._r, self._scal, self._hist = (p.value for p in ptrs)
+
+    def start(self, d):
+        b = self.batch
+        _check(load().fm_cgls_start(self._ptr, _dptr(d, b.dtype, (b.S, b.R, b.B), "d")))
+
+    def iterate(self, n):
+        _check(load().fm_cgls_iterate(self._ptr, int(n)))
+
+    def capture(self, n):
+        _check(load().fm_cgls_capture(self._ptr, int(n)))
+
+    def replay(self):
+        _check(load().fm_cgls_replay(self._ptr))
+
+    def x(self):
+        """A device copy of the current solution [N][B]."""
+        return _device_copy(self._x, (self.batch.N, self.batch.B), self.batch.dtype)
+
+    def residual(self):
+        """A device copy of the current data residual r = d - J x [S][R][B]."""
+        b = self.batch
+        return _device_copy(self._r, (b.S, b.R, b.B), b.dtype)
+
+    def scalars(self):
+        """Per-column scalars [6][B]: gamma, ||q||^2, alpha, gamma', beta, ||r||^2."""
+        import torch
+        return _device_copy(self._scal, (6, self.batch.B), torch.float64)
+
+    def history(self):
+        """||r||^2 per column after start and after each iteration: [max_iter + 1][B]."""
+        import torch
+        return _device_copy(self._hist, (self.max_iter + 1, self.batch.B), torch.float64)
+
+    def free(self):
+        if getattr(self, "_ptr", None) is not None and self._ptr.value:
+            load().fm_cgls_free(self._ptr)
             self._ptr = C.c_void_p(None)
 
     def __del__(self):

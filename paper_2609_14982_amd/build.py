@@ -32,6 +32,33 @@ def _run(cmd, verbose):
     subprocess.check_call(cmd)
 
 
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-fno-sanitize-recover=undefined",
+                  "-g"]
+LIB_SANITIZE = os.path.join(PKG, "_build_sanitize", "libfmbtf_sanitize.so")
+
+
+def build_sanitize(verbose: bool = False) -> str:
+    """The host setup and C ABI (setup.cpp, capi.cpp) built with the address
+    and undefined-behaviour sanitizers, linked with the kernels of an
+    ordinary build, for host-side checks on the CPU: load it with the
+    sanitizer runtimes preloaded and FMBTF_LIB pointing at it."""
+    if not all(os.path.exists(os.path.join(BUILD, o)) for o in ("device.o", "krylov.o", "model_map.o")):
+        build(verbose)
+    out_dir = os.path.dirname(LIB_SANITIZE)
+    os.makedirs(out_dir, exist_ok=True)
+    objs = []
+    for src in ("setup.cpp", "capi.cpp"):
+        obj = os.path.join(out_dir, src.replace(".cpp", ".o"))
+        _run(["g++", *HOST_FLAGS, *SANITIZE_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o",
+              obj], verbose)
+        objs.append(obj)
+    objs += [os.path.join(BUILD, o) for o in ("device.o", "krylov.o", "model_map.o")]
+    gcc_lib = subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB_SANITIZE, *objs, "-pthread",
+          "-L", os.path.dirname(gcc_lib), "-lasan", "-lubsan"], verbose)
+    return LIB_SANITIZE
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []

@@ -48,6 +48,13 @@ int lsqr_capture(fm_lsqr* L, int32_t n);
 int lsqr_replay(fm_lsqr* L);
 int lsqr_buffers(const fm_lsqr* L, void** x, void** u, void** v, double** scal);
 void lsqr_free(fm_lsqr* L);
+int cgls_create(fm_batch* b, int32_t max_iter, fm_cgls** out);
+int cgls_start_any(fm_cgls* C, const void* d);
+int cgls_iterate_any(fm_cgls* C, int32_t n);
+int cgls_capture(fm_cgls* C, int32_t n);
+int cgls_replay(fm_cgls* C);
+int cgls_buffers(const fm_cgls* C, void** x, void** r, double** scal, double** hist);
+void cgls_free(fm_cgls* C);
 
 }  // namespace fm
 
@@ -261,6 +268,38 @@ int fm_lsqr_buffers(const fm_lsqr* L, void** x, void** u, void** v, double** sca
     fm::clear_error();
     return fm::lsqr_buffers(L, x, u, v, scalars);
 }
+
+int fm_cgls_create(fm_batch* b, int32_t max_iter, fm_cgls** out) {
+    fm::clear_error();
+    return fm::cgls_create(b, max_iter, out);
+}
+
+int fm_cgls_start(fm_cgls* C, const void* d) {
+    fm::clear_error();
+    return fm::cgls_start_any(C, d);
+}
+
+int fm_cgls_iterate(fm_cgls* C, int32_t n) {
+    fm::clear_error();
+    return fm::cgls_iterate_any(C, n);
+}
+
+int fm_cgls_capture(fm_cgls* C, int32_t n) {
+    fm::clear_error();
+    return fm::cgls_capture(C, n);
+}
+
+int fm_cgls_replay(fm_cgls* C) {
+    fm::clear_error();
+    return fm::cgls_replay(C);
+}
+
+int fm_cgls_buffers(const fm_cgls* C, void** x, void** r, double** scalars, double** history) {
+    fm::clear_error();
+    return fm::cgls_buffers(C, x, r, scalars, history);
+}
+
+void fm_cgls_free(fm_cgls* C) { fm::cgls_free(C); }
 
 void fm_lsqr_free(fm_lsqr* L) { fm::lsqr_free(L); }
 

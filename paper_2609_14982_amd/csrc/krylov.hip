@@ -19,6 +19,14 @@
 //   rho = sqrt(rhobar^2 + beta^2), c = rhobar/rho, s = beta/rho,
 //   theta = s alpha, rhobar = -c alpha, phi = c phibar, phibar = s phibar,
 //   x += (phi/rho) w,  w = v - (theta/rho) w.
+//
+// CGLS (Hestenes and Stiefel's conjugate gradients on the normal equations,
+// in the least-squares form that never forms J^T J) is the inner solver of the
+// Gauss-Newton step through the autograd wrapper; per column b:
+//   x_0 = 0, r_0 = d, s_0 = J^T r_0, p_0 = s_0, gamma_0 = ||s_0||^2; then
+//   q = J p, alpha = gamma / ||q||^2, x += alpha p, r -= alpha q,
+//   s = J^T r, gamma' = ||s||^2, beta = gamma' / gamma, p = s + beta p.
+// Same device-resident scalars, same capture rules as LSQR.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -33,6 +41,8 @@ constexpr int kRedThreads = 256;
 
 // per-column scalars, [kScalars][B] doubles on the device
 enum : int { sAlpha = 0, sBeta, sRhobar, sPhibar, sRho, sPhi, sTheta, sInvNorm, kScalars };
+// CGLS per-column scalars, [kCgScalars][B]
+enum : int { cGamma = 0, cQQ, cAlpha, cGnew, cBeta, cRR, kCgScalars };
 
 // partial[blk][b] = sum over this block's rows of x[row][b]^2
 template <typename V>
@@ -141,6 +151,56 @@ __global__ void k_copy(V* __restrict__ y, const V* __restrict__ x, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) y[i] = x[i];
 }
 
+// scal[slot][b] = sum_blk partial[blk][b] (a squared column norm)
+__global__ void k_colsum_finalize(const double* __restrict__ partial, int nblk, int B, double* scal, int slot) {
+    const int b = threadIdx.x;
+    if (b >= B) return;
+    double s = 0.0;
+    for (int q = 0; q < nblk; ++q) s += partial[(int64_t)q * B + b];
+    scal[slot * B + b] = s;
+}
+
+// CGLS step length and direction scalars, per column; a zero denominator
+// (converged column) gives a zero step, so the column stays where it is
+__global__ void k_cgls_alpha(double* scal, int B) {
+    const int b = threadIdx.x;
+    if (b >= B) return;
+    const double qq = scal[cQQ * B + b];
+    scal[cAlpha * B + b] = qq > 0.0 ? scal[cGamma * B + b] / qq : 0.0;
+}
+
+__global__ void k_cgls_beta(double* scal, int B) {
+    const int b = threadIdx.x;
+    if (b >= B) return;
+    const double g = scal[cGamma * B + b], gn = scal[cGnew * B + b];
+    scal[cBeta * B + b] = g > 0.0 ? gn / g : 0.0;
+    scal[cGamma * B + b] = gn;
+}
+
+// x += alpha p (model rows) and r -= alpha q (data rows), one launch each
+template <typename V>
+__global__ void k_axpy_col(V* __restrict__ y, const V* __restrict__ x, int64_t rows, int B,
+                           const double* __restrict__ scal, int slot, double sign) {
+    const int64_t n = rows * B;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (V)((double)y[i] + sign * scal[slot * B + (int)(i % B)] * (double)x[i]);
+}
+
+// hist[row][b] = scal[slot][b]
+__global__ void k_copy_row(double* __restrict__ hist, int row, const double* __restrict__ scal, int slot, int B) {
+    const int b = threadIdx.x;
+    if (b < B) hist[(int64_t)row * B + b] = scal[slot * B + b];
+}
+
+// p = s + beta p
+template <typename V>
+__global__ void k_xpby_col(V* __restrict__ p, const V* __restrict__ s, int64_t rows, int B,
+                           const double* __restrict__ scal, int slot) {
+    const int64_t n = rows * B;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (V)((double)s[i] + scal[slot * B + (int)(i % B)] * (double)p[i]);
+}
+
 }  // namespace fm
 
 struct fm_lsqr {
@@ -156,6 +216,22 @@ struct fm_lsqr {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t graph_iters = 0;
+};
+
+struct fm_cgls {
+    fm_batch* b = nullptr;
+    void* x = nullptr;       // [N][B]
+    void* p = nullptr;       // [N][B]
+    void* s = nullptr;       // [N][B] J^T r
+    void* r = nullptr;       // [S][R][B]
+    void* q = nullptr;       // [S][R][B] J p
+    double* scal = nullptr;  // [kCgScalars][B]
+    double* partial = nullptr;
+    double* hist = nullptr;  // [max_iter + 1][B] ||r||^2 after start and after each iteration
+    int32_t max_iter = 0;
+    int32_t it = 0;          // iterations enqueued since start (a graph records its own positions)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace fm {
@@ -303,5 +379,148 @@ int lsqr_buffers(const fm_lsqr* L, void** x, void** u, void** v, double** scal) 
 }
 
 void lsqr_free(fm_lsqr* L) { lsqr_release(L); }
+
+// ---------------------------------------------------------------------------
+// CGLS
+// ---------------------------------------------------------------------------
+template <typename V>
+static void colsq(fm_batch* b, double* partial, double* scal, const void* x, int64_t rows, int slot) {
+    hipLaunchKernelGGL(k_colsq_partial<V>, dim3(kRedBlocks), dim3(kRedThreads), 0, b->stream, (const V*)x, rows,
+                       b->B, partial);
+    hipLaunchKernelGGL(k_colsum_finalize, dim3(1), dim3(std::max(64, b->B)), 0, b->stream, (const double*)partial,
+                       kRedBlocks, b->B, scal, slot);
+}
+
+template <typename V>
+static int cgls_start(fm_cgls* C, const void* d) {
+    fm_batch* b = C->b;
+    const int64_t nd = (int64_t)b->S * b->R, nm = b->N;
+    hipLaunchKernelGGL(k_copy<V>, dim3(grid_for(nd * b->B)), dim3(256), 0, b->stream, (V*)C->r, (const V*)d, nd * b->B);
+    int rc = apply_JT(b, C->r, FM_W_RECEIVERS, C->s, FM_JT_SUMMED);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_copy<V>, dim3(grid_for(nm * b->B)), dim3(256), 0, b->stream, (V*)C->p, (const V*)C->s, nm * b->B);
+    hipLaunchKernelGGL(k_fill<V>, dim3(grid_for(nm * b->B)), dim3(256), 0, b->stream, (V*)C->x, nm * b->B, (V)0);
+    colsq<V>(b, C->partial, C->scal, C->s, nm, cGamma);
+    colsq<V>(b, C->partial, C->scal, C->r, nd, cRR);
+    C->it = 0;
+    hipLaunchKernelGGL(k_copy_row, dim3(1), dim3(std::max(64, b->B)), 0, b->stream, C->hist, 0,
+                       (const double*)C->scal, (int)cRR, b->B);
+    if (hipGetLastError() != hipSuccess) { set_error("CGLS kernel launch failed"); return FM_EHIP; }
+    return FM_OK;
+}
+
+template <typename V>
+static int cgls_iterate(fm_cgls* C, int n) {
+    fm_batch* b = C->b;
+    const int64_t nd = (int64_t)b->S * b->R, nm = b->N;
+    for (int it = 0; it < n; ++it) {
+        int rc = apply_J(b, C->p, FM_DS_BROADCAST, C->q, FM_OUT_RECEIVERS);
+        if (rc) return rc;
+        colsq<V>(b, C->partial, C->scal, C->q, nd, cQQ);
+        hipLaunchKernelGGL(k_cgls_alpha, dim3(1), dim3(std::max(64, b->B)), 0, b->stream, C->scal, b->B);
+        hipLaunchKernelGGL(k_axpy_col<V>, dim3(grid_for(nm * b->B)), dim3(256), 0, b->stream, (V*)C->x,
+                           (const V*)C->p, nm, b->B, (const double*)C->scal, (int)cAlpha, 1.0);
+        hipLaunchKernelGGL(k_axpy_col<V>, dim3(grid_for(nd * b->B)), dim3(256), 0, b->stream, (V*)C->r,
+                           (const V*)C->q, nd, b->B, (const double*)C->scal, (int)cAlpha, -1.0);
+        rc = apply_JT(b, C->r, FM_W_RECEIVERS, C->s, FM_JT_SUMMED);
+        if (rc) return rc;
+        colsq<V>(b, C->partial, C->scal, C->s, nm, cGnew);
+        hipLaunchKernelGGL(k_cgls_beta, dim3(1), dim3(std::max(64, b->B)), 0, b->stream, C->scal, b->B);
+        hipLaunchKernelGGL(k_xpby_col<V>, dim3(grid_for(nm * b->B)), dim3(256), 0, b->stream, (V*)C->p,
+                           (const V*)C->s, nm, b->B, (const double*)C->scal, (int)cBeta);
+        colsq<V>(b, C->partial, C->scal, C->r, nd, cRR);
+        if (++C->it <= C->max_iter)
+            hipLaunchKernelGGL(k_copy_row, dim3(1), dim3(std::max(64, b->B)), 0, b->stream, C->hist, C->it,
+                               (const double*)C->scal, (int)cRR, b->B);
+        if (hipGetLastError() != hipSuccess) { set_error("CGLS kernel launch failed"); return FM_EHIP; }
+    }
+    return FM_OK;
+}
+
+static void cgls_release(fm_cgls* C) {
+    if (!C) return;
+    if (C->exec) (void)hipGraphExecDestroy(C->exec);
+    if (C->graph) (void)hipGraphDestroy(C->graph);
+    void* bufs[] = {C->x, C->p, C->s, C->r, C->q, C->scal, C->partial, C->hist};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    delete C;
+}
+
+int cgls_create(fm_batch* b, int32_t max_iter, fm_cgls** out) {
+    if (!b || !out) { set_error("null argument"); return FM_EINVAL; }
+    if (max_iter < 0) { set_error("max_iter must be >= 0"); return FM_EINVAL; }
+    *out = nullptr;
+    if (b->R == 0) { set_error("the states have no receivers"); return FM_EINVAL; }
+    if (b->B > 256) { set_error("CGLS supports at most 256 right-hand sides"); return FM_EINVAL; }
+    fm_cgls* C = new fm_cgls();
+    C->b = b;
+    C->max_iter = max_iter;
+    const size_t vb = b->prec == FM_FP64 ? 8 : 4;
+    const size_t nd = (size_t)b->S * b->R * b->B * vb, nm = (size_t)b->N * b->B * vb;
+    hipError_t e = hipSuccess;
+    void** targets[] = {&C->x, &C->p, &C->s, &C->r, &C->q};
+    size_t sizes[] = {nm, nm, nm, nd, nd};
+    for (int i = 0; i < 5 && e == hipSuccess; i++) e = hipMalloc(targets[i], sizes[i]);
+    if (e == hipSuccess) e = hipMalloc((void**)&C->scal, sizeof(double) * kCgScalars * b->B);
+    if (e == hipSuccess) e = hipMalloc((void**)&C->partial, sizeof(double) * kRedBlocks * b->B);
+    if (e == hipSuccess) e = hipMalloc((void**)&C->hist, sizeof(double) * ((size_t)max_iter + 1) * b->B);
+    if (e != hipSuccess) {
+        cgls_release(C);
+        set_error("CGLS allocation failed: %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    *out = C;
+    return FM_OK;
+}
+
+int cgls_start_any(fm_cgls* C, const void* d) {
+    if (!C || !d) { set_error("null argument"); return FM_EINVAL; }
+    return C->b->prec == FM_FP64 ? cgls_start<double>(C, d) : cgls_start<float>(C, d);
+}
+
+int cgls_iterate_any(fm_cgls* C, int32_t n) {
+    if (!C || n < 0) { set_error("bad arguments"); return FM_EINVAL; }
+    return C->b->prec == FM_FP64 ? cgls_iterate<double>(C, n) : cgls_iterate<float>(C, n);
+}
+
+int cgls_capture(fm_cgls* C, int32_t n) {
+    if (!C || n < 1) { set_error("bad arguments"); return FM_EINVAL; }
+    if (C->exec) { (void)hipGraphExecDestroy(C->exec); C->exec = nullptr; }
+    if (C->graph) { (void)hipGraphDestroy(C->graph); C->graph = nullptr; }
+    hipStream_t s = C->b->stream;
+    if (s == nullptr) { set_error("graph capture needs a non-null batch stream"); return FM_EINVAL; }
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = cgls_iterate_any(C, n);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) { set_error("hipStreamEndCapture failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    e = hipGraphInstantiate(&C->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        set_error("hipGraphInstantiate failed: %s", hipGetErrorString(e));
+        return FM_EHIP;
+    }
+    C->graph = g;
+    return FM_OK;
+}
+
+int cgls_replay(fm_cgls* C) {
+    if (!C || !C->exec) { set_error("no captured graph"); return FM_ESTATE; }
+    HIP_TRY(hipGraphLaunch(C->exec, C->b->stream));
+    return FM_OK;
+}
+
+int cgls_buffers(const fm_cgls* C, void** x, void** r, double** scal, double** hist) {
+    if (!C) { set_error("null argument"); return FM_EINVAL; }
+    if (x) *x = C->x;
+    if (r) *r = C->r;
+    if (scal) *scal = C->scal;
+    if (hist) *hist = C->hist;
+    return FM_OK;
+}
+
+void cgls_free(fm_cgls* C) { cgls_release(C); }
 
 }  // namespace fm

@@ -151,61 +151,114 @@ class AugmentedOperator:
                 + self.lam * self.sdiag * y[b:])
 
 
-def lsmr(op, b, n_iter):
-    """n_iter LSMR iterations for min ||op x - b|| from x = 0 (Fong and
-    Saunders' recurrences, no damping; stops early only on a zero beta or
-    alpha).  Returns (x, ||b - op x||)."""
+def lsmr(op, b, n_iter, atol=0.0, btol=0.0, check_every=8):
+    """LSMR for min ||op x - b|| from x = 0 (the recurrences of Fong and
+    Saunders, 2011, with zero damping - the regularisation is inside the
+    augmented operator), at most n_iter iterations.
+
+    Stopping (their tests, with the norm estimates of the same recurrences):
+    ||op^T r|| <= atol ||op|| ||r||  (a least-squares solution to the Krylov
+    optimality tolerance atol; Section 5.3 uses 1e-4), or
+    ||r|| <= btol ||b|| + atol ||op|| ||x||  (a compatible system).  Every
+    scalar stays on the device: a converged column freezes x on the device,
+    and the host reads the stop flag only every check_every iterations, so
+    the loop has no per-iteration synchronisation.
+    Returns (x, ||b - op x||, iterations used, info dict)."""
+    dev, dt = b.device, b.dtype
+    zero = torch.zeros((), dtype=dt, device=dev)
+    one = torch.ones((), dtype=dt, device=dev)
+
+    def safe_div(a, c):
+        return torch.where(c != 0, a / torch.where(c != 0, c, one), zero)
+
     beta = torch.linalg.vector_norm(b)
-    x = torch.zeros(op.shape[1], dtype=b.dtype, device=b.device)
-    if float(beta) == 0.0:
-        return x, 0.0
-    u = b / beta
+    normb = beta
+    x = torch.zeros(op.shape[1], dtype=dt, device=dev)
+    u = safe_div(one, beta) * b
     v = op.rmatvec(u)
     alpha = torch.linalg.vector_norm(v)
-    if float(alpha) == 0.0:
-        return x, float(beta)
-    v = v / alpha
+    v = safe_div(one, alpha) * v
+    # bidiagonalisation and the two rotations
     zetabar = alpha * beta
     alphabar = alpha
-    rho = torch.ones((), dtype=b.dtype, device=b.device)
-    rhobar = torch.ones_like(rho)
-    cbar = torch.ones_like(rho)
-    sbar = torch.zeros_like(rho)
+    rho, rhobar, cbar, sbar = one.clone(), one.clone(), one.clone(), zero.clone()
     h = v.clone()
     hbar = torch.zeros_like(v)
-    for _ in range(n_iter):
-        # bidiagonalisation: beta u = A v - alpha u, alpha v = A^T u - beta v
+    # estimates of ||r|| (betadd, betad, rhodold, tautildeold, thetatilde, zeta)
+    betadd, betad, rhodold = beta.clone(), zero.clone(), one.clone()
+    tautildeold, thetatilde, zeta = zero.clone(), zero.clone(), zero.clone()
+    normA2 = alpha * alpha
+    # an exact zero residual (beta = 0) or gradient (alpha = 0) at the start
+    active = (beta > 0) & (alpha > 0)
+    itn = torch.zeros((), dtype=torch.int64, device=dev)
+    normr = beta.clone()
+    normAr = alpha * beta
+    for k in range(n_iter):
+        if k % check_every == 0 and not bool(active):
+            break
+        # beta u = op v - alpha u ; alpha v = op^T u - beta v
         u = op.matvec(v) - alpha * u
         beta = torch.linalg.vector_norm(u)
-        stop = float(beta) == 0.0
-        if not stop:
-            u = u / beta
-            v = op.rmatvec(u) - beta * v
-            alpha = torch.linalg.vector_norm(v)
-            stop = float(alpha) == 0.0
-            if not stop:
-                v = v / alpha
+        u = safe_div(one, beta) * u
+        v = op.rmatvec(u) - beta * v
+        alpha = torch.linalg.vector_norm(v)
+        v = safe_div(one, alpha) * v
         # rotation P_k
         rhoold = rho
         rho = torch.sqrt(alphabar * alphabar + beta * beta)
-        c, s = alphabar / rho, beta / rho
+        c, s = safe_div(alphabar, rho), safe_div(beta, rho)
         thetanew = s * alpha
         alphabar = c * alpha
         # rotation Pbar_k
         rhobarold = rhobar
+        zetaold = zeta
         thetabar = sbar * rho
         rhotemp = cbar * rho
         rhobar = torch.sqrt(rhotemp * rhotemp + thetanew * thetanew)
-        cbar, sbar = rhotemp / rhobar, thetanew / rhobar
+        cbar, sbar = safe_div(rhotemp, rhobar), safe_div(thetanew, rhobar)
         zeta = cbar * zetabar
         zetabar = -sbar * zetabar
-        # h, hbar, x
-        hbar = h - (thetabar * rho / (rhoold * rhobarold)) * hbar
-        x = x + (zeta / (rho * rhobar)) * hbar
-        h = v - (thetanew / rho) * h
-        if stop:
-            break
-    return x, float(torch.linalg.vector_norm(b - op.matvec(x)))
+        # h, hbar, x (x only while the column is active)
+        hbar = h - safe_div(thetabar * rho, rhoold * rhobarold) * hbar
+        x = torch.where(active, x + safe_div(zeta, rho * rhobar) * hbar, x)
+        h = v - safe_div(thetanew, rho) * h
+        # ||r|| estimate (zero damping: the damping rotation is the identity)
+        betahat = c * betadd
+        betadd = -s * betadd
+        thetatildeold = thetatilde
+        rhotildeold = torch.sqrt(rhodold * rhodold + thetabar * thetabar)
+        ctildeold, stildeold = safe_div(rhodold, rhotildeold), safe_div(thetabar, rhotildeold)
+        thetatilde = stildeold * rhobar
+        rhodold = ctildeold * rhobar
+        betad = -stildeold * betad + ctildeold * betahat
+        tautildeold = safe_div(zetaold - thetatildeold * tautildeold, rhotildeold)
+        taud = safe_div(zeta - thetatilde * tautildeold, rhodold)
+        nr = torch.sqrt((betad - taud) ** 2 + betadd * betadd)
+        # ||A|| estimate, ||A^T r||, ||x||
+        normA2 = normA2 + beta * beta
+        normA = torch.sqrt(normA2)
+        normA2 = normA2 + alpha * alpha
+        nAr = torch.abs(zetabar)
+        normx = torch.linalg.vector_norm(x)
+        normr = torch.where(active, nr, normr)
+        normAr = torch.where(active, nAr, normAr)
+        itn = itn + active.to(torch.int64)
+        test1 = safe_div(nr, normb)
+        den = normA * nr
+        test2 = torch.where(den != 0, nAr / torch.where(den != 0, den, one), torch.full_like(den, float("inf")))
+        t1 = test1 / (1 + safe_div(normA * normx, normb))
+        rtol = btol + atol * safe_div(normA * normx, normb)
+        # the two tests, and their machine-precision limits
+        done = (test2 <= atol) | (test1 <= rtol) | (1 + test2 <= 1) | (1 + t1 <= 1)
+        active = active & ~done
+    info = {"iterations": int(itn), "normr_est": float(normr), "normAr_est": float(normAr),
+            "converged": not bool(active)}
+    return x, float(torch.linalg.vector_norm(b - op.matvec(x))), info["iterations"], info
+
+
+def wrms(wd, r):
+    """Weighted RMS data residual sqrt(mean((W_d r)^2)) (Section 5.4)."""
+    return float(np.sqrt(np.mean((np.asarray(wd) * np.asarray(r)) ** 2)))
 
 
 def data_weights(d_obs, sigma_abs, sigma_rel):
@@ -214,28 +267,51 @@ def data_weights(d_obs, sigma_abs, sigma_rel):
     return 1.0 / np.sqrt(sigma_abs ** 2 + (sigma_rel * d_obs) ** 2)
 
 
-def gauss_newton(prob: CellTomography, v0, d_obs, lam, gamma, sigma_abs, sigma_rel, n_outer=3, n_lsmr=20,
-                 c1=1e-4, max_halvings=8):
-    """Algorithm 1 for n_outer outer iterations.  Returns (v, history) with one
-    record per outer iteration: weighted misfit before the step, step length,
-    the augmented LSMR residual."""
+def gauss_newton(prob: CellTomography, v0, d_obs, lam, gamma, sigma_abs, sigma_rel, k_max=10, n_lsmr=100,
+                 lsmr_atol=1e-4, lsmr_btol=1e-4, outer_rtol=0.01, c1=1e-4, max_halvings=8):
+    """Algorithm 1: at most k_max + 1 outer iterations.  Phase II stops when
+    the relative reduction of the weighted RMS residual between successive
+    outer iterations falls below outer_rtol (Section 5.4 uses 1 %); LSMR stops
+    at the Krylov optimality tolerance lsmr_atol (Section 5.3: 1e-4) or after
+    n_lsmr iterations; Armijo halves the step from t = 1 while the nonlinear
+    weighted misfit does not fall by c1 t |slope|.  Returns (v, history): one
+    record per outer iteration (weighted misfit and WRMS at v_k, step length,
+    LSMR iterations and residual, the stop reason on the last)."""
     wd = data_weights(np.asarray(d_obs, dtype=np.float64), sigma_abs, sigma_rel)
     v = np.ascontiguousarray(v0, dtype=np.float64)
     hist = []
+    dev = torch.device("cuda")
     pred, T, s, mmap = prob.forward(v)
-    phi = 0.5 * float(np.sum((wd * (pred - d_obs)) ** 2))
-    for _ in range(n_outer):
+    prev_wrms = None
+    for k in range(k_max + 1):
+        # Phase II: residual and the outer stopping test
         r = pred - d_obs
+        phi = 0.5 * float(np.sum((wd * r) ** 2))
+        w = wrms(wd, r)
+        rec = {"k": k, "misfit": phi, "wrms": w}
+        hist.append(rec)
+        if prev_wrms is not None and (prev_wrms - w) < outer_rtol * prev_wrms:
+            rec["stop"] = "relative WRMS reduction below %g" % outer_rtol
+            break
+        if k == k_max:
+            rec["stop"] = "k_max"
+            break
+        prev_wrms = w
+        # Phase I (at v_k) and III: frozen states, LSMR on the augmented system
         batch = prob.linearize(v, T, s)
         K = AugmentedOperator(prob, batch, mmap, wd, v, lam, gamma)
-        dev = torch.device("cuda")
         rhs = torch.zeros(K.shape[0], dtype=torch.float64, device=dev)
         rhs[:K.n_data] = torch.from_numpy(-(wd * r).reshape(-1)).to(dev)
-        dv, res = lsmr(K, rhs, n_lsmr)
+        dv, res, its, info = lsmr(K, rhs, n_lsmr, atol=lsmr_atol, btol=lsmr_btol)
         # directional derivative of the weighted misfit: (J^T W_d^2 r) . dv
         gradv = K.JT(torch.from_numpy((wd * wd * r).reshape(-1)).to(dev))
         slope = float(torch.dot(gradv, dv))
+        batch.status()
         dv = dv.cpu().numpy()
+        batch.free()
+        rec.update({"lsmr_iterations": its, "lsmr_converged": info["converged"], "lsmr_residual": res,
+                    "lsmr_rhs": float(torch.linalg.vector_norm(rhs)), "slope": slope})
+        # Phase IV: Armijo on the nonlinear weighted misfit
         t, accepted = 1.0, None
         for _h in range(max_halvings + 1):
             vt = v + t * dv
@@ -243,17 +319,15 @@ def gauss_newton(prob: CellTomography, v0, d_obs, lam, gamma, sigma_abs, sigma_r
                 pt, Tt, st, mt = prob.forward(vt)
                 phit = 0.5 * float(np.sum((wd * (pt - d_obs)) ** 2))
                 if phit <= phi + c1 * t * slope:
-                    accepted = (vt, pt, Tt, st, mt, phit)
+                    accepted = (vt, pt, Tt, st, mt)
                     break
                 mt.free()
             t *= 0.5
-        batch.free()
-        hist.append({"misfit": phi, "step": t if accepted else 0.0, "lsmr_residual": res,
-                     "lsmr_rhs": float(torch.linalg.vector_norm(rhs)), "slope": slope})
+        rec["step"] = t if accepted else 0.0
         if accepted is None:
+            rec["stop"] = "no step satisfies the Armijo condition"
             break
         mmap.free()
-        v, pred, T, s, mmap, phi = accepted
+        v, pred, T, s, mmap = accepted
     mmap.free()
-    hist.append({"misfit": phi})
     return v, hist

@@ -48,3 +48,78 @@ def test_data_weights():
     d = np.array([0.0, 1.0, 2.0])
     w = gn.data_weights(d, 3e-4, 3e-3)
     assert np.allclose(w, 1.0 / np.sqrt(9e-8 + (3e-3 * d) ** 2), rtol=1e-15)
+
+
+class _DenseOp:
+    """A matrix as the operator interface gn.lsmr takes (torch, CPU)."""
+
+    def __init__(self, A):
+        self.A = torch.from_numpy(A)
+        self.shape = A.shape
+
+    def matvec(self, x):
+        return self.A @ x
+
+    def rmatvec(self, y):
+        return self.A.T @ y
+
+
+def _matrix(shape, cond, seed):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((shape[0], shape[0])))
+    V, _ = np.linalg.qr(rng.standard_normal((shape[1], shape[1])))
+    sv = np.geomspace(1.0, 1.0 / cond, min(shape))
+    return U[:, :len(sv)] @ np.diag(sv) @ V[:len(sv), :], rng.standard_normal(shape[0])
+
+
+def test_lsmr_matches_the_published_algorithm():
+    """gn.lsmr (the recurrences of Fong and Saunders, written independently)
+    against scipy's LSMR on a well-conditioned least-squares problem: the
+    same stopping iteration at atol = btol = 1e-4, the same solution and the
+    same residual-norm estimate; with zero tolerances both run exactly the
+    requested count."""
+    import scipy.sparse.linalg as spla
+    A, b = _matrix((400, 200), 10.0, 11)
+    ref = spla.lsmr(A, b, atol=1e-4, btol=1e-4, conlim=1e300, maxiter=1000)
+    x, res, its, info = gn.lsmr(_DenseOp(A), torch.from_numpy(b), 1000, atol=1e-4, btol=1e-4, check_every=3)
+    assert info["converged"] and its == ref[2] and ref[1] == 2, (its, ref[2], ref[1])
+    assert np.linalg.norm(x.numpy() - ref[0]) <= 1e-10 * np.linalg.norm(ref[0])
+    assert abs(info["normr_est"] - ref[3]) <= 1e-10 * ref[3]
+    assert abs(info["normAr_est"] - ref[4]) <= 1e-8 * ref[4]
+    x, res, its, info = gn.lsmr(_DenseOp(A), torch.from_numpy(b), 7)
+    ref = spla.lsmr(A, b, atol=0.0, btol=0.0, conlim=1e300, maxiter=7)
+    assert its == 7 and np.linalg.norm(x.numpy() - ref[0]) <= 1e-12 * np.linalg.norm(ref[0])
+    assert abs(res - np.linalg.norm(b - A @ x.numpy())) <= 1e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("shape,cond,tol", [((400, 200), 100.0, 1e-4), ((500, 120), 1e3, 1e-4),
+                                            ((300, 300), 100.0, 1e-6)])
+def test_lsmr_stopping_tests_hold(shape, cond, tol):
+    """On harder problems the iterates of two implementations part by
+    rounding (the bidiagonalisation loses orthogonality), but the stop comes
+    within an iteration or two of scipy's, and where it stops the true
+    residual satisfies the optimality test (||A^T r|| <= atol ||A||_F ||r||)
+    or the compatibility test it reports."""
+    import scipy.sparse.linalg as spla
+    A, b = _matrix(shape, cond, 7 + shape[0])
+    ref = spla.lsmr(A, b, atol=tol, btol=tol, conlim=1e300, maxiter=2000)
+    x, res, its, info = gn.lsmr(_DenseOp(A), torch.from_numpy(b), 2000, atol=tol, btol=tol)
+    assert info["converged"] and abs(its - ref[2]) <= 2, (its, ref[2])
+    r = b - A @ x.numpy()
+    nA = np.linalg.norm(A)
+    opt = np.linalg.norm(A.T @ r) <= 2 * tol * nA * np.linalg.norm(r)
+    compat = np.linalg.norm(r) <= 2 * (tol * np.linalg.norm(b) + tol * nA * np.linalg.norm(x.numpy()))
+    assert opt or compat
+
+
+def test_lsmr_zero_rhs_and_compatible_system():
+    A = np.random.default_rng(5).standard_normal((20, 20)) + 8 * np.eye(20)
+    x, res, its, info = gn.lsmr(_DenseOp(A), torch.zeros(20, dtype=torch.float64), 50, atol=1e-4, btol=1e-4)
+    assert its == 0 and res == 0.0 and torch.count_nonzero(x) == 0
+    xs = np.random.default_rng(6).standard_normal(20)
+    x, res, its, info = gn.lsmr(_DenseOp(A), torch.from_numpy(A @ xs), 100, atol=1e-10, btol=1e-10)
+    assert info["converged"] and res <= 1e-9 * np.linalg.norm(A @ xs)
+
+
+def test_wrms():
+    assert gn.wrms(np.array([2.0, 2.0]), np.array([1.0, -1.0])) == 2.0

@@ -165,3 +165,54 @@ def test_reversal_criterion_on_violating_faces():
         assert np.all(lhs[vio] < -diag_term[vio])
         n_checked += int(vio.sum())
     assert n_checked > 0
+
+
+def _case_c_operator(T=None):
+    from oracle.assembly import assemble
+    wl = W.curved_state(41, 41, 25, A=500.0, eps_T=0.05)
+    T = wl.T[0] if T is None else T
+    return wl, assemble(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, T, wl.s, int(wl.src[0]))
+
+
+def test_case_c_sccs_survive_traveltime_perturbation():
+    """Section 5.2.2: small random perturbations of the stored traveltime
+    leave case C's SCC structure (6 blocks, 82 cyclic nodes, Table 2)
+    unchanged over a broad range - here every relative size from 1e-14 to
+    1e-6, eight decades, for two seeds."""
+    wl, op = _case_c_operator()
+    base = diag.scc_summary(op.W)
+    assert len(base) == 6 and sum(len(c) for c in base) == 82
+    for seed in (0, 1):
+        for eps in (1e-14, 1e-12, 1e-10, 1e-8, 1e-6):
+            Tp = diag.perturbed_traveltime(wl.T[0], int(wl.src[0]), eps, seed)
+            _, opp = _case_c_operator(Tp)
+            assert diag.same_partition(diag.scc_summary(opp.W), base), (seed, eps)
+
+
+def test_case_c_sccs_survive_weak_edge_cutoff():
+    """Section 5.2.2: removing ever weaker-to-stronger dependencies does not
+    eliminate all nontrivial SCCs until the cutoff is far above roundoff:
+    cutoffs up to 1e-4 leave the partition unchanged, and the largest cutoff
+    at which a cyclic block survives is above 1e-3 (it is 1.5e-2 here); just
+    above it none is left."""
+    wl, op = _case_c_operator()
+    base = diag.scc_summary(op.W)
+    for tau in (1e-15, 1e-12, 1e-9, 1e-6, 1e-4):
+        assert diag.same_partition(diag.scc_summary(diag.weak_edge_cutoff(op.W, tau)), base), tau
+    tau = diag.scc_survival_cutoff(op.W)
+    assert tau > 1e-3
+    assert diag.scc_summary(diag.weak_edge_cutoff(op.W, tau))
+    assert not diag.scc_summary(diag.weak_edge_cutoff(op.W, np.nextafter(tau, 1.0)))
+
+
+def test_survival_cutoff_closed_form():
+    """On a hand-made graph the survival cutoff is the weakest edge of the
+    strongest cycle: cycles 0->1->0 (weights 0.5, 0.2) and 2->3->4->2
+    (weights 0.3, 0.4, 0.1) give max(min(0.5, 0.2), min(0.3, 0.4, 0.1)) = 0.2;
+    an acyclic graph gives 0."""
+    # W[i, j] = w_ij is the weight of edge j -> i
+    ij = {(1, 0): 0.5, (0, 1): 0.2, (3, 2): 0.3, (4, 3): 0.4, (2, 4): 0.1, (4, 0): 0.9}
+    W = sp.csr_matrix((list(ij.values()), ([i for i, _ in ij], [j for _, j in ij])), shape=(5, 5))
+    assert diag.scc_survival_cutoff(W) == 0.2
+    dag = sp.csr_matrix(([0.3, 0.7], ([1, 2], [0, 1])), shape=(3, 3))
+    assert diag.scc_survival_cutoff(dag) == 0.0

@@ -23,6 +23,7 @@ from .grids import (  # noqa: F401
     perturbed_model,
     smooth_noise,
     small_3d,
+    smooth_3d,
     traveltime_solver,
     data_noise,
     CONFIG_NAMES,

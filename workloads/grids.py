@@ -370,6 +370,30 @@ def config(name: str, with_T: bool = True, nthreads: int | None = None) -> Workl
     return wl
 
 
+def smooth_3d(n1: int, n2: int, n3: int, topo_amp: float = 0.0, name: str = "smooth3d",
+              with_T: bool = True) -> Workload:
+    """A smooth 3-D member for refinement studies, the same physical problem
+    at every size: 4 x 4 x 2 km, surface h = topo_amp sin(2 pi x / 4) cos(2 pi y / 4)
+    km, v = 1.8 + 0.6 z km/s, one source at the centre of the surface lattice
+    and 5 x 5 surface receivers (the lattices scale with the grid)."""
+    xi = np.linspace(0.0, 1.0, n1)
+    et = np.linspace(0.0, 1.0, n2)
+    ze = np.linspace(0.0, 1.0, n3)
+    XX, YY = np.meshgrid(4.0 * xi, 4.0 * et, indexing="xy")
+    h = topo_amp * np.sin(2.0 * np.pi * XX / 4.0) * np.cos(2.0 * np.pi * YY / 4.0)
+    Z = h[None, :, :] + ze[:, None, None] * (2.0 - h[None, :, :])
+    X = np.stack([np.broadcast_to(XX[None], Z.shape), np.broadcast_to(YY[None], Z.shape), Z], axis=-1)
+    s = 1.0 / (1.8 + 0.6 * Z)
+    si, sj = _lattice(n1, 1), _lattice(n2, 1)
+    src = np.array([i + n1 * j for j in sj for i in si], dtype=np.int64)
+    ri, rj = _lattice(n1, 5), _lattice(n2, 5)
+    rcv = np.array([i + n1 * j for j in rj for i in ri], dtype=np.int64)
+    wl = _mk(name, 3, n1, n2, n3, X, s, src, rcv, 1, 0, meta={"topo_amp": topo_amp})
+    if with_T:
+        eikonal(wl)
+    return wl
+
+
 def small_3d(n1: int, n2: int, n3: int, seed: int, S: int, B: int, name: str = "small3d",
              with_T: bool = True) -> Workload:
     """A reduced member of the 3-D family (same recipe, fewer nodes)."""
