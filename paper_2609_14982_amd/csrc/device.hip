@@ -254,7 +254,9 @@ __global__ void k_gather_receivers(ApplyArgs a) {
 // consecutive values of one node (one 16-byte access per source) and keeps
 // the accesses of SU sources in flight; lambda is read once, so its loads
 // are non-temporal, and every load names the global address space.
-template <typename V>
+// PAD: work rows hold a.xB > B values (padded scratch); otherwise xB = B and
+// the addressing is the plain [S][N][B] one.
+template <typename V, bool PAD>
 __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
     constexpr int VW = 16 / (int)sizeof(V);
     constexpr int SU = 16;
@@ -267,7 +269,7 @@ __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
         for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NB / VW; t += stride) {
             const int64_t e0 = t * VW;
             const int64_t node = e0 / a.B;
-            const int64_t w0 = node * a.xB + (e0 - node * a.B);
+            const int64_t w0 = PAD ? node * a.xB + (e0 - node * a.B) : e0;
             V acc[VW];
 #pragma unroll
             for (int v = 0; v < VW; ++v) acc[v] = (V)0;
@@ -297,7 +299,7 @@ __global__ void k_sum_sources(ApplyArgs a, const void* const* cal) {
         for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < NB; t += stride) {
             const int64_t node = t / a.B;
             V acc = (V)0;
-            const int64_t w0 = node * a.xB + (t - node * a.B);
+            const int64_t w0 = PAD ? node * a.xB + (t - node * a.B) : t;
             for (int alpha = 0; alpha < a.S; ++alpha) acc += ((const V*)cal[alpha])[node] * work[alpha * NXB + w0];
             out[t] = acc;
         }
@@ -902,8 +904,14 @@ int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_
         int64_t total = b->N * b->B;
         int grid = (int)std::min<int64_t>((total + 255) / 256, 16384);
         const void* const* cal = (const void* const*)((char*)b->d_src + sizeof(SrcDev) * b->S);
-        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_sum_sources<double>, dim3(grid), dim3(256), 0, b->stream, a, cal);
-        else hipLaunchKernelGGL(k_sum_sources<float>, dim3(grid), dim3(256), 0, b->stream, a, cal);
+        const bool pad = a.xB != a.B;
+        if (b->prec == FM_FP64) {
+            if (pad) hipLaunchKernelGGL((k_sum_sources<double, true>), dim3(grid), dim3(256), 0, b->stream, a, cal);
+            else hipLaunchKernelGGL((k_sum_sources<double, false>), dim3(grid), dim3(256), 0, b->stream, a, cal);
+        } else {
+            if (pad) hipLaunchKernelGGL((k_sum_sources<float, true>), dim3(grid), dim3(256), 0, b->stream, a, cal);
+            else hipLaunchKernelGGL((k_sum_sources<float, false>), dim3(grid), dim3(256), 0, b->stream, a, cal);
+        }
         e = hipGetLastError();
         if (e != hipSuccess) { set_error("source-sum launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
     }
@@ -1092,8 +1100,8 @@ int apply_JT_sweep(fm_batch* b, const void* w, void* out, int32_t out_mode, int3
     if (out_mode == FM_JT_SUMMED) {
         int64_t total = b->N * b->B;
         int grid = (int)std::min<int64_t>((total + 255) / 256, 16384);
-        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_sum_sources<double>, dim3(grid), dim3(256), 0, b->stream, g.a, cal);
-        else hipLaunchKernelGGL(k_sum_sources<float>, dim3(grid), dim3(256), 0, b->stream, g.a, cal);
+        if (b->prec == FM_FP64) hipLaunchKernelGGL((k_sum_sources<double, false>), dim3(grid), dim3(256), 0, b->stream, g.a, cal);
+        else hipLaunchKernelGGL((k_sum_sources<float, false>), dim3(grid), dim3(256), 0, b->stream, g.a, cal);
     } else {
         int64_t total = (int64_t)b->S * b->N * b->B;
         int grid = (int)std::min<int64_t>((total + 255) / 256, 16384);

@@ -558,7 +558,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         in = (const V*)a.in + (cx.rcv_in ? (size_t)alpha * a.R * B : (size_t)alpha * NB);
         if (a.out_mode == FM_JT_PER_SOURCE) outp = (V*)a.out + (size_t)alpha * NB;
     }
-    double* __restrict__ stage = (double*)s.stage + (size_t)alpha * s.stage_rows * s.stage_B;
+    // staged rows: a compile-time B when B doubles already fill whole lines
+    const int SB = (B * 8) % 128 == 0 ? B : s.stage_B;
+    double* __restrict__ stage = (double*)s.stage + (size_t)alpha * s.stage_rows * SB;
     // byte-offset views of the same arrays (each spans < 4 GiB, checked on the host)
     constexpr uint32_t ROWB = B * sizeof(V);                 // input and per-source output rows
     // node-value rows (a compile-time ROWB when B values already fill whole lines)
@@ -691,7 +693,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             // its block products (that state is not kept live across them)
             if (blocks)
                 split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, XROWB, lane_off, stage,
-                                                 s.stage_B, cx, P, part, slot0, rl);
+                                                 SB, cx, P, part, slot0, rl);
             group_barrier(g, P);
             if (first) {
                 first = false;
@@ -701,9 +703,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             }
             if (blocks) {
                 if constexpr (B % 16 == 0)
-                    split_block_solve_mfma<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, s.stage_B, X, a.xB, outp, P, part);
+                    split_block_solve_mfma<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, SB, X, a.xB, outp, P, part);
                 else
-                    split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, s.stage_B, X, a.xB, outp, P, part,
+                    split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, SB, X, a.xB, outp, P, part,
                                                      s.lds_rows, lds + s.stage_off);
                 if (more) fetch_batch(cN, mN);
                 group_barrier(g, P);
