@@ -139,8 +139,12 @@ class OracleOperator:
         return self.W.T.tocsr()
 
 
-def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None, rcv_w=None) -> OracleOperator:
+def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None, rcv_w=None, identity_rows=None) -> OracleOperator:
     """Assemble W and c (Section 3.1 eq. (discrete-row), Section 3.2).
+
+    identity_rows: further nodes whose rows are identity rows besides src
+    (the source-seed rows of an off-grid point source, oracle.source); their
+    calibration is then replaced by the seed derivative there.
 
     parity: pinned by the manufactured tangent test (first-order convergence to
     eq. (test-dT), Table 1), the flat-grid causal-order case, the 1-D closed
@@ -176,6 +180,8 @@ def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None, rcv_w=None) -> OracleOpera
         dsum = dsum + cs
     active = dsum > 0.0
     active[src] = False
+    if identity_rows is not None:
+        active[np.asarray(identity_rows, dtype=np.int64)] = False
     rows, cols, vals = [], [], []
     wslots = []
     for cs, js in zip(slot_c, slot_j):

@@ -15,6 +15,7 @@ from .grids import (  # noqa: F401
     config,
     curved_state,
     eikonal,
+    eikonal_point,
     flat_radial,
     interpolating_receivers,
     manufactured,

@@ -218,6 +218,13 @@ static double local_update(const grid_t *g, int64_t p, const double *T, const ui
     return best;
 }
 
+/* Off-grid point source at logical coordinates xi (dim values): the seed
+ * region is every node within max-norm distance rho of xi, initialised with
+ * the straight-ray time (s_src + s_p)/2 |x_p - x_src|, where s_src and x_src
+ * are multilinear interpolations over the corners of xi's cell; the rest is
+ * the same fast marching as for an on-grid source. */
+static int solve_one_pt(const grid_t *g, const double *X, const double *xi, double rho, double *T);
+
 static int solve_one(const grid_t *g, const double *X, int64_t src, int init_radius, double *T) {
     int64_t N = g->n[0] * g->n[1] * g->n[2];
     uint8_t *known = (uint8_t *)calloc((size_t)N, 1);
@@ -309,6 +316,123 @@ int fmgen_eikonal(int dim, int64_t n1, int64_t n2, int64_t n3, const double *G, 
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1) reduction(min : rc)
     for (int32_t a = 0; a < nsrc; a++) {
         int r = solve_one(&g, X, src[a], init_radius, T + (size_t)a * (size_t)N);
+        if (r < rc) rc = r;
+    }
+    return rc;
+}
+
+static int solve_one_pt(const grid_t *g, const double *X, const double *xi, double rho, double *T) {
+    int64_t N = g->n[0] * g->n[1] * g->n[2];
+    int dim = g->dim;
+    uint8_t *known = (uint8_t *)calloc((size_t)N, 1);
+    uint8_t *frozen = (uint8_t *)calloc((size_t)N, 1);
+    heap_t h;
+    h.key = T;
+    h.heap = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    h.pos = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    h.n = 0;
+    if (!known || !frozen || !h.heap || !h.pos) {
+        free(known); free(frozen); free(h.heap); free(h.pos);
+        return -2;
+    }
+    for (int64_t p = 0; p < N; p++) { T[p] = INFINITY; h.pos[p] = -1; }
+    /* the source cell and its multilinear weights */
+    int64_t base[3] = {0, 0, 0};
+    double t[3] = {0, 0, 0};
+    for (int d = 0; d < dim; d++) {
+        double f = floor(xi[d]);
+        int64_t b = (int64_t)f;
+        if (b > g->n[d] - 2) b = g->n[d] - 2;
+        if (b < 0) b = 0;
+        base[d] = b;
+        t[d] = xi[d] - (double)b;
+    }
+    double s_src = 0.0, x_src[3] = {0, 0, 0};
+    for (int corner = 0; corner < (1 << dim); corner++) {
+        double w = 1.0;
+        int64_t p = 0;
+        for (int d = 0; d < dim; d++) {
+            int up = (corner >> d) & 1;
+            int64_t c = base[d] + (g->n[d] > 1 ? up : 0);
+            w *= up ? t[d] : 1.0 - t[d];
+            p += c * g->stride[d];
+        }
+        s_src += w * g->s[p];
+        for (int d = 0; d < dim; d++) x_src[d] += w * X[(size_t)dim * p + d];
+    }
+    int64_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int d = 0; d < dim; d++) {
+        lo[d] = (int64_t)ceil(xi[d] - rho);
+        hi[d] = (int64_t)floor(xi[d] + rho);
+        if (lo[d] < 0) lo[d] = 0;
+        if (hi[d] > g->n[d] - 1) hi[d] = g->n[d] - 1;
+    }
+    int nseed = 0;
+    for (int64_t k = lo[2]; k <= hi[2]; k++)
+        for (int64_t j = lo[1]; j <= hi[1]; j++)
+            for (int64_t i = lo[0]; i <= hi[0]; i++) {
+                int64_t p = i + g->stride[1] * j + g->stride[2] * k;
+                const double *xp = X + (size_t)dim * p;
+                double r2 = 0.0;
+                for (int d = 0; d < dim; d++) r2 += (xp[d] - x_src[d]) * (xp[d] - x_src[d]);
+                T[p] = 0.5 * (s_src + g->s[p]) * sqrt(r2);
+                frozen[p] = 1;
+                heap_push_or_decrease(&h, (int32_t)p);
+                nseed++;
+            }
+    if (nseed == 0) {
+        free(known); free(frozen); free(h.heap); free(h.pos);
+        return -3;
+    }
+    while (h.n > 0) {
+        int32_t p = heap_pop(&h);
+        known[p] = 1;
+        int64_t c[3];
+        node_coords(g, p, c);
+        for (int d = 0; d < dim; d++) {
+            for (int side = -1; side <= 1; side += 2) {
+                int64_t cc = c[d] + side;
+                if (cc < 0 || cc >= g->n[d]) continue;
+                int64_t q = p + side * g->stride[d];
+                if (known[q] || frozen[q]) continue;
+                double tn = local_update(g, q, T, known);
+                if (tn < T[q]) {
+                    T[q] = tn;
+                    heap_push_or_decrease(&h, (int32_t)q);
+                }
+            }
+        }
+    }
+    free(known); free(frozen); free(h.heap); free(h.pos);
+    return 0;
+}
+
+/*
+ * Off-grid point sources: xi is [nsrc][dim] logical source coordinates, rho
+ * the seed radius (max-norm, logical units); otherwise as fmgen_eikonal.
+ */
+int fmgen_eikonal_pt(int dim, int64_t n1, int64_t n2, int64_t n3, const double *G, const double *X,
+                     const double *s, int32_t nsrc, const double *xi, double rho, int32_t nthreads, double *T) {
+    if (dim != 2 && dim != 3) return -1;
+    grid_t g;
+    g.dim = dim;
+    g.n[0] = n1;
+    if (dim == 3) { g.n[1] = n2; g.n[2] = n3; }
+    else { g.n[1] = n3; g.n[2] = 1; }
+    g.stride[0] = 1;
+    g.stride[1] = g.n[0];
+    g.stride[2] = g.n[0] * g.n[1];
+    g.G = G;
+    g.s = s;
+    int64_t N = g.n[0] * g.n[1] * g.n[2];
+    if (N <= 0 || N >= ((int64_t)1 << 31) || !(rho >= 0.0)) return -1;
+    for (int32_t a = 0; a < nsrc; a++)
+        for (int d = 0; d < dim; d++)
+            if (!(xi[(size_t)a * dim + d] >= 0.0) || !(xi[(size_t)a * dim + d] <= (double)(g.n[d] - 1))) return -1;
+    int rc = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads > 0 ? nthreads : 1) reduction(min : rc)
+    for (int32_t a = 0; a < nsrc; a++) {
+        int r = solve_one_pt(&g, X, xi + (size_t)a * dim, rho, T + (size_t)a * (size_t)N);
         if (r < rc) rc = r;
     }
     return rc;

@@ -46,6 +46,11 @@ def _load():
             ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
             ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+        lib.fmgen_eikonal_pt.restype = ctypes.c_int
+        lib.fmgen_eikonal_pt.argtypes = [
+            ctypes.c_int, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+            ctypes.c_void_p, ctypes.c_double, ctypes.c_int32, ctypes.c_void_p]
         _lib = lib
     return _lib
 
@@ -159,6 +164,27 @@ def eikonal(wl: Workload, init_radius: int = 2, nthreads: int | None = None) -> 
                            T.ctypes.data)
     if rc != 0:
         raise RuntimeError(f"fmgen_eikonal failed with code {rc}")
+    wl.T = T
+    return T
+
+
+def eikonal_point(wl: Workload, xi: np.ndarray, rho: float, nthreads: int | None = None) -> np.ndarray:
+    """First-arrival traveltimes [S][N] for off-grid point sources at logical
+    coordinates xi [S][dim], seed region of max-norm radius rho (straight-ray
+    times there, fast marching elsewhere); sets wl.T."""
+    lib = _load()
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
+    xi = np.ascontiguousarray(xi, dtype=np.float64).reshape(-1, wl.dim)
+    S = xi.shape[0]
+    T = np.empty((S, wl.N), dtype=np.float64)
+    G = np.ascontiguousarray(wl.G, dtype=np.float64)
+    X = np.ascontiguousarray(wl.X, dtype=np.float64)
+    s = np.ascontiguousarray(wl.s, dtype=np.float64)
+    rc = lib.fmgen_eikonal_pt(wl.dim, wl.n1, wl.n2, wl.n3, G.ctypes.data, X.ctypes.data, s.ctypes.data, S,
+                              xi.ctypes.data, float(rho), nthreads, T.ctypes.data)
+    if rc != 0:
+        raise RuntimeError(f"fmgen_eikonal_pt failed with code {rc}")
     wl.T = T
     return T
 
