@@ -87,6 +87,8 @@ typedef struct fm_stats {
     double f_vio, f_cyc, f_unr;   /* eq. (graph-fractions) */
     double setup_seconds;   /* host time of the build */
     int64_t state_bytes;    /* bytes of the packed per-source state (one precision) */
+    int32_t n_seed;         /* seed-region nodes of an off-grid source (0 for a source on a node) */
+    int32_t n_direct;       /* receivers an off-grid source reaches through its direct term D */
 } fm_stats;
 
 /* Launch schedule of a batch; zero fields take the library default. */
@@ -159,6 +161,45 @@ int fm_build_frozen_state_w(const fm_grid* g, const double* T, const double* s, 
 int fm_build_frozen_states_w(const fm_grid* g, int32_t S, const double* T, const double* s,
                              const int64_t* src_nodes, const int64_t* rcv_nodes, const double* rcv_weights,
                              int32_t n_rcv, int32_t k_per_rcv, int32_t nthreads, fm_state** out);
+
+/*
+ * An off-grid point source (Section 3.1's source-seed rows, Section 3.2's
+ * right-hand side from the differentiated source treatment, and the direct
+ * term D_alpha of eq. (source-jacobian) / eq. (source-transpose)).  The
+ * library's reading, since the paper gives no formula for them:
+ *   - the source sits at logical coordinates xi_src (dim values, axis 0
+ *     first, each in [0, n_d - 1]); the 2^dim corners k of its cell carry
+ *     multilinear weights phi_k, so s_src = sum phi_k s_k and
+ *     x_src = sum phi_k X_k;
+ *   - the seed region is every node p with max_d |i_d(p) - xi_d| <= seed_radius;
+ *     T there must be the straight-ray time (s_src + s_p)/2 |X_p - x_src|
+ *     (the caller's first-arrival solver seeds it so); its rows of A are
+ *     identity rows with right-hand side
+ *     |X_p - x_src|/2 (sum_k phi_k ds_k + ds_p);
+ *   - a receiver whose position (its weights applied to its nodes' logical
+ *     coordinates) lies in the seed region is direct: it has no row in P,
+ *     and its row of D is |x_r - x_src|/2 (sum_k phi_k ds_k + sum_e w_e ds_e)
+ *     with x_r interpolated by the receiver's weights;
+ *   - J = P A^{-1} C + D, J^T = C^T A^{-T} P^T + D^T; J to nodes is A^{-1} C
+ *     (seed rows included), J^T from nodal weights C^T A^{-T} (no D).
+ *   X            host [N][dim] physical node coordinates (finite)
+ *   xi_src       host [dim] (per state; [S][dim] for the batch builder)
+ *   seed_radius  >= 0, logical units; the region must hold at least one node
+ * Other arguments as fm_build_frozen_state_w (rcv_weights may be NULL).  Every
+ * apply (J, J^T, both modes, both precisions, the allocation-free primal) takes
+ * such states, mixed with on-grid ones in one batch; the directional-sweeping
+ * baseline refuses them (FM_EINVAL).
+ * Errors: as fm_build_frozen_state_w; FM_EINVAL for X NULL or not finite,
+ * xi_src outside the grid, seed_radius negative or not finite, or an empty
+ * seed region.
+ */
+int fm_build_frozen_state_pt(const fm_grid* g, const double* X, const double* T, const double* s,
+                             const double* xi_src, double seed_radius, const int64_t* rcv_nodes,
+                             const double* rcv_weights, int32_t n_rcv, int32_t k_per_rcv, fm_state** out);
+int fm_build_frozen_states_pt(const fm_grid* g, const double* X, int32_t S, const double* T, const double* s,
+                              const double* xi_src, double seed_radius, const int64_t* rcv_nodes,
+                              const double* rcv_weights, int32_t n_rcv, int32_t k_per_rcv, int32_t nthreads,
+                              fm_state** out);
 
 /* Structural statistics of a state (Section 5.2, eq. (graph-fractions)). */
 int fm_state_stats(const fm_state* st, fm_stats* out);

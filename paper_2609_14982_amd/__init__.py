@@ -27,6 +27,7 @@ from .binding import (  # noqa: F401
     State,
     build_frozen_state,
     build_frozen_states,
+    build_frozen_states_pt,
     exported_symbols,
     lib_path,
     load,

@@ -23,7 +23,7 @@ _ERRNAMES = {FM_EINVAL: "FM_EINVAL", FM_ESINGULAR: "FM_ESINGULAR", FM_ENOMEM: "F
 
 SYMBOLS = (
     "fm_build_frozen_state", "fm_build_frozen_states", "fm_build_frozen_state_w", "fm_build_frozen_states_w",
-    "fm_state_stats",
+    "fm_build_frozen_state_pt", "fm_build_frozen_states_pt", "fm_state_stats",
     "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
     "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_batch_status", "fm_batch_split_info",
     "fm_apply_J", "fm_apply_J_static",
@@ -53,7 +53,8 @@ class fm_stats(C.Structure):
                 ("levels_rev", C.c_int32), ("n_scc", C.c_int32), ("largest_scc", C.c_int32),
                 ("n_cyc", C.c_int64), ("sum_k2", C.c_int64), ("n_vio", C.c_int64),
                 ("n_unr", C.c_int64), ("f_vio", C.c_double), ("f_cyc", C.c_double),
-                ("f_unr", C.c_double), ("setup_seconds", C.c_double), ("state_bytes", C.c_int64)]
+                ("f_unr", C.c_double), ("setup_seconds", C.c_double), ("state_bytes", C.c_int64),
+                ("n_seed", C.c_int32), ("n_direct", C.c_int32)]
 
 
 class fm_tuning(C.Structure):
@@ -86,6 +87,8 @@ def load():
         "fm_build_frozen_states": (C.c_int, [vp, i32, vp, vp, vp, vp, i32, i32, vp]),
         "fm_build_frozen_state_w": (C.c_int, [vp, vp, vp, i64, vp, vp, i32, i32, vp]),
         "fm_build_frozen_states_w": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, i32, i32, i32, vp]),
+        "fm_build_frozen_state_pt": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, vp, vp, i32, i32, vp]),
+        "fm_build_frozen_states_pt": (C.c_int, [vp, vp, i32, vp, vp, vp, C.c_double, vp, vp, i32, i32, i32, vp]),
         "fm_state_stats": (C.c_int, [vp, vp]),
         "fm_state_export_operator": (C.c_int, [vp, vp, vp, vp, vp]),
         "fm_state_export_graph": (C.c_int, [vp, vp, vp, vp]),
@@ -275,6 +278,54 @@ def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nth
                                       rcv.ctypes.data if rcv.size else None, int(rcv.shape[1]),
                                       int(nthreads), outs))
     return [State(outs[a], N, dim, (n1, n2, n3), int(rcv.shape[1])) for a in range(S)]
+
+
+def _receivers_pt(rcv_nodes, rcv_weights, S):
+    """Receiver arrays [S][R][K] (nodes, weights or None) from [R], [R][K] or
+    [S][R][K] inputs, shared across sources when given without S."""
+    if rcv_nodes is None:
+        return np.zeros((S, 0, 1), dtype=np.int64), None
+    rcv = np.asarray(rcv_nodes, dtype=np.int64)
+    if rcv_weights is None:
+        if rcv.ndim == 1:
+            rcv = np.broadcast_to(rcv[None], (S, rcv.shape[0]))
+        if rcv.ndim != 2 or rcv.shape[0] != S:
+            raise ValueError("receivers without weights are [R] (shared) or [S][R]")
+        return np.ascontiguousarray(rcv.reshape(S, -1, 1)), None
+    w = np.asarray(rcv_weights, dtype=np.float64)
+    if w.shape != rcv.shape or rcv.ndim not in (2, 3):
+        raise ValueError("interpolating receivers need rcv_nodes and rcv_weights of one shape, [R][K] or [S][R][K]")
+    if rcv.ndim == 2:
+        rcv = np.broadcast_to(rcv[None], (S,) + rcv.shape)
+        w = np.broadcast_to(w[None], (S,) + w.shape)
+    return np.ascontiguousarray(rcv), np.ascontiguousarray(w)
+
+
+def build_frozen_states_pt(dim, n1, n2, n3, G, X, T, s, xi_src, seed_radius, rcv_nodes=None, rcv_weights=None,
+                           nthreads=None):
+    """fm_build_frozen_states_pt: off-grid point sources at logical
+    coordinates xi_src [S][dim] with seed regions of max-norm radius
+    seed_radius; X [N][dim] physical node coordinates, T [S][N] (straight-ray
+    times over each seed region).  Receivers: [R] node selections or [R][K]
+    nodes with rcv_weights [R][K] (shared by every source), or [S][R][K]."""
+    lib = load()
+    G, T, s, X = _f64(G), _f64(T), _f64(s), _f64(X)
+    xi = np.ascontiguousarray(np.asarray(xi_src, dtype=np.float64).reshape(-1, dim))
+    S = int(xi.shape[0])
+    if T.size != S * int(n1) * int(n2) * int(n3):
+        raise ValueError("T must be [S][N] with one row per source")
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
+    g = _grid(dim, n1, n2, n3, G)
+    outs = (C.c_void_p * S)()
+    N = int(n1) * int(n2) * int(n3)
+    rcv, w = _receivers_pt(rcv_nodes, rcv_weights, S)
+    R, K = int(rcv.shape[1]), int(rcv.shape[2])
+    _check(lib.fm_build_frozen_states_pt(C.byref(g), X.ctypes.data, S, T.ctypes.data, s.ctypes.data, xi.ctypes.data,
+                                         float(seed_radius), rcv.ctypes.data if rcv.size else None,
+                                         w.ctypes.data if w is not None and w.size else None, R, K, int(nthreads),
+                                         outs))
+    return [State(outs[a], N, dim, (n1, n2, n3), R) for a in range(S)]
 
 
 def _dptr(t, dtype, shape, what):

@@ -9,6 +9,37 @@
 
 namespace fm {
 
+// An off-grid point source (Section 3.1 source-seed rows, the direct term of
+// eq. (source-jacobian)); a state whose source sits on a node has none.
+struct PtDev {
+    const int32_t* seed_node;   // [n_seed] identity rows the forward walk skips
+    const int32_t* seed_ptr;    // [n_seed + 1] their right-hand-side entries
+    const int32_t* seed_col;    //   node of each entry
+    const double* seed_w;       //   weight of each entry
+    const int32_t* d_ptr;       // [R + 1] entries of D per receiver (none: not direct)
+    const int32_t* d_col;
+    const double* d_w;
+    const int32_t* sc_tgt;      // [n_tgt] targets of the transposes of both, ascending
+    const int32_t* sc_ptr;      // [n_tgt + 1]
+    const int32_t* sc_idx;      //   seed node (kind 0) or receiver (kind 1)
+    const uint8_t* sc_kind;
+    const double* sc_w;
+    int32_t n_seed, n_tgt;
+};
+
+// The same transposes of every off-grid source of a batch, grouped by target
+// node over the batch (J^T summed over sources): target tgt[t] receives
+// sum_i w[i] v_i over i in [ptr[t], ptr[t+1]), sources ascending.
+struct UnionDev {
+    const int32_t* tgt;
+    const int32_t* ptr;
+    const int32_t* alpha;
+    const int32_t* idx;
+    const uint8_t* kind;
+    const double* w;
+    int32_t n;
+};
+
 struct SrcDev {
     const uint64_t* fmeta;
     const void* fwts;
@@ -37,6 +68,7 @@ struct SrcDev {
     const int32_t* rcv_pos;     // [E] reverse position of each sorted entry
     const int32_t* rcv_idx;     // [E] receiver of each sorted entry
     const double* rcv_ew;       // [E] weight of each sorted entry
+    const PtDev* pt;            // off-grid source tables, or nullptr
     int32_t L_f, L_r, n_rcv, n_ent;
 };
 
@@ -79,6 +111,10 @@ struct fm_batch {
     void* stage = nullptr;           // [S][stage_rows][B] FP64 block right-hand sides
     unsigned* sync = nullptr;        // counters [S*32], XCD masks [S*32], abort word
     int32_t* wg_map = nullptr;       // balanced split: [grid] source << 8 | part (-1 idle), then [S] P per source
+    // off-grid sources: the most seed rows and transpose targets of one source
+    int32_t max_seed = 0, max_tgt = 0;
+    void* union_blob = nullptr;      // UnionDev arrays (J^T summed)
+    fm::UnionDev uni{};
 };
 
 namespace fm {

@@ -125,6 +125,66 @@ int fm_build_frozen_states_w(const fm_grid* g, int32_t S, const double* T, const
     return FM_OK;
 }
 
+int fm_build_frozen_state_pt(const fm_grid* g, const double* X, const double* T, const double* s,
+                             const double* xi_src, double seed_radius, const int64_t* rcv_nodes,
+                             const double* rcv_weights, int32_t n_rcv, int32_t k_per_rcv, fm_state** out) {
+    fm::clear_error();
+    if (!out) { fm::set_error("null output pointer"); return FM_EINVAL; }
+    *out = nullptr;
+    if (!g || !xi_src) { fm::set_error("null argument"); return FM_EINVAL; }
+    if (g->dim != 2 && g->dim != 3) { fm::set_error("dim must be 2 or 3, got %d", g->dim); return FM_EINVAL; }
+    fm::PointSource ps{};
+    ps.X = X;
+    for (int d = 0; d < g->dim; d++) ps.xi[d] = xi_src[d];
+    ps.rho = seed_radius;
+    return fm::build_state(g, T, s, -1, rcv_nodes, rcv_weights, n_rcv, k_per_rcv, out, &ps);
+}
+
+int fm_build_frozen_states_pt(const fm_grid* g, const double* X, int32_t S, const double* T, const double* s,
+                              const double* xi_src, double seed_radius, const int64_t* rcv_nodes,
+                              const double* rcv_weights, int32_t n_rcv, int32_t k_per_rcv, int32_t nthreads,
+                              fm_state** out) {
+    fm::clear_error();
+    if (!g || !T || !s || !xi_src || !out || S < 1) { fm::set_error("bad arguments"); return FM_EINVAL; }
+    if (g->dim != 2 && g->dim != 3) { fm::set_error("dim must be 2 or 3, got %d", g->dim); return FM_EINVAL; }
+    if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) { fm::set_error("grid sizes must be >= 1"); return FM_EINVAL; }
+    if (k_per_rcv < 1) { fm::set_error("entries per receiver must be >= 1"); return FM_EINVAL; }
+    const int64_t N = g->n1 * g->n2 * g->n3;
+    const size_t per_src = (size_t)(n_rcv > 0 ? n_rcv : 0) * (size_t)k_per_rcv;
+    std::vector<fm_state*> res(S, nullptr);
+    std::vector<int> rcs(S, FM_OK);
+    std::vector<std::string> msgs(S);
+    std::atomic<int32_t> next{0};
+    int nt = std::max(1, std::min<int32_t>(nthreads > 0 ? nthreads : 1, S));
+    auto worker = [&]() {
+        for (;;) {
+            int32_t a = next.fetch_add(1);
+            if (a >= S) break;
+            fm_state* st = nullptr;
+            int rc = fm_build_frozen_state_pt(g, X, T + (size_t)a * N, s, xi_src + (size_t)a * g->dim, seed_radius,
+                                              n_rcv > 0 ? rcv_nodes + (size_t)a * per_src : nullptr,
+                                              n_rcv > 0 && rcv_weights ? rcv_weights + (size_t)a * per_src : nullptr,
+                                              n_rcv, k_per_rcv, &st);
+            rcs[a] = rc;
+            res[a] = st;
+            if (rc != FM_OK) msgs[a] = fm_last_error();
+        }
+    };
+    std::vector<std::thread> th;
+    for (int i = 1; i < nt; i++) th.emplace_back(worker);
+    worker();
+    for (auto& t : th) t.join();
+    for (int32_t a = 0; a < S; a++) {
+        if (rcs[a] != FM_OK) {
+            for (auto* p : res) fm_state_free(p);
+            fm::set_error("source %d: %s", a, msgs[a].c_str());
+            return rcs[a];
+        }
+    }
+    std::copy(res.begin(), res.end(), out);
+    return FM_OK;
+}
+
 int fm_state_stats(const fm_state* st, fm_stats* out) {
     fm::clear_error();
     if (!st || !out) { fm::set_error("null argument"); return FM_EINVAL; }

@@ -101,6 +101,21 @@ int upload_state(HostState* st) {
     size_t o_rp = ar.add<int32_t>(pk.rcv_pos.size());
     size_t o_ri = ar.add<int32_t>(pk.rcv_idx.size());
     size_t o_rew = ar.add<double>(pk.rcv_ew.size());
+    // an off-grid source's tables and the PtDev that points at them
+    const bool has_pt = !pk.seed_node.empty();
+    size_t o_sn = ar.add<int32_t>(pk.seed_node.size());
+    size_t o_sp = ar.add<int32_t>(pk.seed_ptr.size());
+    size_t o_sc = ar.add<int32_t>(pk.seed_col.size());
+    size_t o_sw = ar.add<double>(pk.seed_w.size());
+    size_t o_dp = ar.add<int32_t>(pk.d_ptr.size());
+    size_t o_dc = ar.add<int32_t>(pk.d_col.size());
+    size_t o_dw = ar.add<double>(pk.d_w.size());
+    size_t o_tt = ar.add<int32_t>(pk.sc_tgt.size());
+    size_t o_tp = ar.add<int32_t>(pk.sc_ptr.size());
+    size_t o_ti = ar.add<int32_t>(pk.sc_idx.size());
+    size_t o_tk = ar.add<uint8_t>(pk.sc_kind.size());
+    size_t o_tw = ar.add<double>(pk.sc_w.size());
+    size_t o_pt = ar.add<PtDev>(has_pt ? 1 : 0);
     size_t total = ar.add<char>(0) + 256;
     DeviceState* ds = new DeviceState();
     hipError_t e = hipMalloc(&ds->blob, total);
@@ -138,6 +153,36 @@ int upload_state(HostState* st) {
     rc = rc ? rc : put(b, o_rp, pk.rcv_pos);
     rc = rc ? rc : put(b, o_ri, pk.rcv_idx);
     rc = rc ? rc : put(b, o_rew, pk.rcv_ew);
+    if (has_pt) {
+        rc = rc ? rc : put(b, o_sn, pk.seed_node);
+        rc = rc ? rc : put(b, o_sp, pk.seed_ptr);
+        rc = rc ? rc : put(b, o_sc, pk.seed_col);
+        rc = rc ? rc : put(b, o_sw, pk.seed_w);
+        rc = rc ? rc : put(b, o_dp, pk.d_ptr);
+        rc = rc ? rc : put(b, o_dc, pk.d_col);
+        rc = rc ? rc : put(b, o_dw, pk.d_w);
+        rc = rc ? rc : put(b, o_tt, pk.sc_tgt);
+        rc = rc ? rc : put(b, o_tp, pk.sc_ptr);
+        rc = rc ? rc : put(b, o_ti, pk.sc_idx);
+        rc = rc ? rc : put(b, o_tk, pk.sc_kind);
+        rc = rc ? rc : put(b, o_tw, pk.sc_w);
+        PtDev h{};
+        h.seed_node = (const int32_t*)(b + o_sn);
+        h.seed_ptr = (const int32_t*)(b + o_sp);
+        h.seed_col = (const int32_t*)(b + o_sc);
+        h.seed_w = (const double*)(b + o_sw);
+        h.d_ptr = (const int32_t*)(b + o_dp);
+        h.d_col = (const int32_t*)(b + o_dc);
+        h.d_w = (const double*)(b + o_dw);
+        h.sc_tgt = (const int32_t*)(b + o_tt);
+        h.sc_ptr = (const int32_t*)(b + o_tp);
+        h.sc_idx = (const int32_t*)(b + o_ti);
+        h.sc_kind = (const uint8_t*)(b + o_tk);
+        h.sc_w = (const double*)(b + o_tw);
+        h.n_seed = (int32_t)pk.seed_node.size();
+        h.n_tgt = (int32_t)pk.sc_tgt.size();
+        rc = rc ? rc : put(b, o_pt, std::vector<PtDev>(1, h));
+    }
     if (rc != FM_OK) {
         (void)hipFree(ds->blob);
         delete ds;
@@ -171,6 +216,7 @@ int upload_state(HostState* st) {
     d.rcv_pos = (const int32_t*)(b + o_rp);
     d.rcv_idx = (const int32_t*)(b + o_ri);
     d.rcv_ew = (const double*)(b + o_rew);
+    d.pt = has_pt ? (const PtDev*)(b + o_pt) : nullptr;
     d.L_f = pk.L_f;
     d.L_r = pk.L_r;
     d.n_rcv = (int32_t)pk.rcv_ptr.size() - 1;
@@ -245,7 +291,88 @@ __global__ void k_gather_receivers(ApplyArgs a) {
         V acc = (V)0;
         for (int32_t e = sd.rcv_ptr[rr]; e < sd.rcv_ptr[rr + 1]; ++e)
             acc += (V)sd.rcv_wt[e] * x[(int64_t)sd.rcv_node[e] * a.xB];
+        if (sd.pt) {
+            // a receiver an off-grid source reaches directly: its row of D
+            // applied to ds (it has no entries above)
+            const PtDev* pt = sd.pt;
+            const V* ds = (const V*)a.in + (a.in_mode == FM_DS_PER_PAIR ? alpha * a.N * a.B : 0) + b;
+            for (int32_t i = pt->d_ptr[rr]; i < pt->d_ptr[rr + 1]; ++i)
+                acc += (V)pt->d_w[i] * ds[(int64_t)pt->d_col[i] * a.B];
+        }
         ((V*)a.out)[t] = acc;
+    }
+}
+
+// The seed rows of off-grid sources, before the forward walk (which skips
+// them): X[alpha][p][b] = sum_i seed_w[i] ds[seed_col[i]][b], the derivative
+// of the straight-ray seed time (Section 3.2's right-hand side for
+// source-seed rows).
+template <typename V>
+__global__ void k_seed_rows(ApplyArgs a, int32_t max_seed) {
+    const int64_t total = (int64_t)a.S * max_seed * a.B;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t % a.B;
+        const int32_t e = (int32_t)((t / a.B) % max_seed);
+        const int64_t alpha = t / ((int64_t)a.B * max_seed);
+        const PtDev* pt = a.src[alpha].pt;
+        if (!pt || e >= pt->n_seed) continue;
+        const V* ds = (const V*)a.in + (a.in_mode == FM_DS_PER_PAIR ? alpha * a.N * a.B : 0) + b;
+        double acc = 0.0;
+        for (int32_t i = pt->seed_ptr[e]; i < pt->seed_ptr[e + 1]; ++i)
+            acc += pt->seed_w[i] * (double)ds[(int64_t)pt->seed_col[i] * a.B];
+        ((V*)a.work)[(alpha * a.N + pt->seed_node[e]) * a.xB + b] = (V)acc;
+    }
+}
+
+// J^T per source, after the reverse walk wrote c lambda: each off-grid
+// source adds the transposes of its seed rows (lambda at the seeds) and of
+// D (receiver data, when the input is receiver data) at their targets,
+// one thread per (source, target, rhs), so no two threads share an output.
+template <typename V>
+__global__ void k_seed_scatter(ApplyArgs a, int32_t max_tgt) {
+    const int64_t total = (int64_t)a.S * max_tgt * a.B;
+    const bool rcv = a.in_mode == FM_W_RECEIVERS;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t % a.B;
+        const int32_t e = (int32_t)((t / a.B) % max_tgt);
+        const int64_t alpha = t / ((int64_t)a.B * max_tgt);
+        const PtDev* pt = a.src[alpha].pt;
+        if (!pt || e >= pt->n_tgt) continue;
+        const V* lam = (const V*)a.work + alpha * a.N * a.xB + b;
+        const V* y = (const V*)a.in + alpha * (int64_t)a.R * a.B + b;
+        double acc = 0.0;
+        for (int32_t i = pt->sc_ptr[e]; i < pt->sc_ptr[e + 1]; ++i) {
+            if (pt->sc_kind[i] == 0) acc += pt->sc_w[i] * (double)lam[(int64_t)pt->sc_idx[i] * a.xB];
+            else if (rcv) acc += pt->sc_w[i] * (double)y[(int64_t)pt->sc_idx[i] * a.B];
+        }
+        V* o = (V*)a.out + (alpha * a.N + pt->sc_tgt[e]) * a.B + b;
+        *o = (V)((double)*o + acc);
+    }
+}
+
+// J^T summed over sources, after the source sum: the same transposes of
+// every off-grid source, grouped by target over the batch (sources
+// ascending inside a target), one thread per (target, rhs).
+template <typename V>
+__global__ void k_union_scatter(ApplyArgs a, UnionDev u) {
+    const int64_t total = (int64_t)u.n * a.B;
+    const bool rcv = a.in_mode == FM_W_RECEIVERS;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = t % a.B;
+        const int64_t e = t / a.B;
+        double acc = 0.0;
+        for (int32_t i = u.ptr[e]; i < u.ptr[e + 1]; ++i) {
+            const int64_t alpha = u.alpha[i];
+            if (u.kind[i] == 0)
+                acc += u.w[i] * (double)((const V*)a.work)[(alpha * a.N + u.idx[i]) * a.xB + b];
+            else if (rcv)
+                acc += u.w[i] * (double)((const V*)a.in)[(alpha * a.R + u.idx[i]) * a.B + b];
+        }
+        V* o = (V*)a.out + (int64_t)u.tgt[e] * a.B + b;
+        *o = (V)((double)*o + acc);
     }
 }
 
@@ -681,6 +808,67 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
 
 void batch_free(fm_batch* b);
 
+// Off-grid sources of a batch: the most seed rows and transpose targets of
+// one source (launch sizes), and the union of every source's transpose
+// entries grouped by target node for J^T summed over sources (entries of one
+// target in ascending source order, each source's in its own order).
+static int prepare_point_sources(fm_batch* b) {
+    b->max_seed = b->max_tgt = 0;
+    struct Ent { int32_t tgt, alpha, idx; uint8_t kind; double w; };
+    std::vector<Ent> ents;
+    for (int32_t a = 0; a < b->S; a++) {
+        const Packed& pk = b->states[a]->pk;
+        b->max_seed = std::max(b->max_seed, (int32_t)pk.seed_node.size());
+        b->max_tgt = std::max(b->max_tgt, (int32_t)pk.sc_tgt.size());
+        for (size_t t = 0; t < pk.sc_tgt.size(); t++)
+            for (int32_t i = pk.sc_ptr[t]; i < pk.sc_ptr[t + 1]; i++)
+                ents.push_back({pk.sc_tgt[t], a, pk.sc_idx[i], pk.sc_kind[i], pk.sc_w[i]});
+    }
+    if (ents.empty()) return FM_OK;
+    // entries were appended source by source, each source's by target: a
+    // stable sort by target keeps sources ascending and each one's order
+    std::stable_sort(ents.begin(), ents.end(), [](const Ent& x, const Ent& y) { return x.tgt < y.tgt; });
+    std::vector<int32_t> tgt, ptr(1, 0), alpha, idx;
+    std::vector<uint8_t> kind;
+    std::vector<double> w;
+    for (size_t i = 0; i < ents.size(); i++) {
+        if (i > 0 && ents[i].tgt != ents[i - 1].tgt) ptr.push_back((int32_t)i);
+        if (i == 0 || ents[i].tgt != ents[i - 1].tgt) tgt.push_back(ents[i].tgt);
+        alpha.push_back(ents[i].alpha);
+        idx.push_back(ents[i].idx);
+        kind.push_back(ents[i].kind);
+        w.push_back(ents[i].w);
+    }
+    ptr.push_back((int32_t)ents.size());
+    Arena ar;
+    const size_t o_t = ar.add<int32_t>(tgt.size()), o_p = ar.add<int32_t>(ptr.size());
+    const size_t o_a = ar.add<int32_t>(alpha.size()), o_i = ar.add<int32_t>(idx.size());
+    const size_t o_k = ar.add<uint8_t>(kind.size()), o_w = ar.add<double>(w.size());
+    const size_t total = ar.add<char>(0) + 256;
+    hipError_t e = hipMalloc(&b->union_blob, total);
+    if (e != hipSuccess) {
+        b->union_blob = nullptr;
+        set_error("batch allocation (%zu B source-seed transposes) failed: %s", total, hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    char* base = (char*)b->union_blob;
+    int rc = put(base, o_t, tgt);
+    rc = rc ? rc : put(base, o_p, ptr);
+    rc = rc ? rc : put(base, o_a, alpha);
+    rc = rc ? rc : put(base, o_i, idx);
+    rc = rc ? rc : put(base, o_k, kind);
+    rc = rc ? rc : put(base, o_w, w);
+    if (rc) return rc;
+    b->uni.tgt = (const int32_t*)(base + o_t);
+    b->uni.ptr = (const int32_t*)(base + o_p);
+    b->uni.alpha = (const int32_t*)(base + o_a);
+    b->uni.idx = (const int32_t*)(base + o_i);
+    b->uni.kind = (const uint8_t*)(base + o_k);
+    b->uni.w = (const double*)(base + o_w);
+    b->uni.n = (int32_t)tgt.size();
+    return FM_OK;
+}
+
 int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precision, const fm_tuning* tuning,
                  void* stream, fm_batch** out) {
     if (!out) { set_error("null output pointer"); return FM_EINVAL; }
@@ -798,6 +986,11 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
         set_error("batch allocation (%zu B scratch) failed: %s", scratch, hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
     }
+    rc = prepare_point_sources(b);
+    if (rc) {
+        batch_free(b);
+        return rc;
+    }
     *out = b;
     return FM_OK;
 }
@@ -811,6 +1004,7 @@ void batch_free(fm_batch* b) {
     if (b->cycles_dev) (void)hipFree(b->cycles_dev);
     if (b->d_src) (void)hipFree(b->d_src);
     if (b->scratch) (void)hipFree(b->scratch);
+    if (b->union_blob) (void)hipFree(b->union_blob);
     delete b;
 }
 
@@ -866,6 +1060,14 @@ int apply_J(fm_batch* b, const void* ds, int32_t ds_mode, void* out, int32_t out
     a.out = out;
     a.work = out_mode == FM_OUT_NODES ? out : b->scratch;
     a.xB = out_mode == FM_OUT_NODES ? b->B : b->xB;
+    if (b->max_seed > 0) {
+        const int64_t total = (int64_t)b->S * b->max_seed * b->B;
+        const int grid = (int)std::min<int64_t>((total + 255) / 256, 65535);
+        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_seed_rows<double>, dim3(grid), dim3(256), 0, b->stream, a, b->max_seed);
+        else hipLaunchKernelGGL(k_seed_rows<float>, dim3(grid), dim3(256), 0, b->stream, a, b->max_seed);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) { set_error("seed-row launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    }
     hipError_t e = b->tun.split > 1       ? launch_split(b, true, a)
                    : b->prec == FM_FP64 ? launch_sweep<double>(true, b->tun, a, b->grid, b->lds_bytes, b->stream)
                                         : launch_sweep<float>(true, b->tun, a, b->grid, b->lds_bytes, b->stream);
@@ -900,6 +1102,14 @@ int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_
                    : b->prec == FM_FP64 ? launch_sweep<double>(false, b->tun, a, b->grid, b->lds_bytes, b->stream)
                                         : launch_sweep<float>(false, b->tun, a, b->grid, b->lds_bytes, b->stream);
     if (e != hipSuccess) { set_error("reverse launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    if (out_mode == FM_JT_PER_SOURCE && b->max_tgt > 0) {
+        const int64_t total = (int64_t)b->S * b->max_tgt * b->B;
+        const int grid = (int)std::min<int64_t>((total + 255) / 256, 65535);
+        if (b->prec == FM_FP64) hipLaunchKernelGGL(k_seed_scatter<double>, dim3(grid), dim3(256), 0, b->stream, a, b->max_tgt);
+        else hipLaunchKernelGGL(k_seed_scatter<float>, dim3(grid), dim3(256), 0, b->stream, a, b->max_tgt);
+        e = hipGetLastError();
+        if (e != hipSuccess) { set_error("seed-transpose launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+    }
     if (out_mode == FM_JT_SUMMED) {
         int64_t total = b->N * b->B;
         int grid = (int)std::min<int64_t>((total + 255) / 256, 16384);
@@ -914,6 +1124,14 @@ int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_
         }
         e = hipGetLastError();
         if (e != hipSuccess) { set_error("source-sum launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+        if (b->uni.n > 0) {
+            const int64_t ut = (int64_t)b->uni.n * b->B;
+            const int ug = (int)std::min<int64_t>((ut + 255) / 256, 65535);
+            if (b->prec == FM_FP64) hipLaunchKernelGGL(k_union_scatter<double>, dim3(ug), dim3(256), 0, b->stream, a, b->uni);
+            else hipLaunchKernelGGL(k_union_scatter<float>, dim3(ug), dim3(256), 0, b->stream, a, b->uni);
+            e = hipGetLastError();
+            if (e != hipSuccess) { set_error("seed-transpose launch failed: %s", hipGetErrorString(e)); return FM_EHIP; }
+        }
     }
     return FM_OK;
 }
@@ -972,6 +1190,10 @@ static int upload_natural(HostState* st, int prec) {
 }
 
 static int prepare_baseline(fm_batch* b) {
+    if (b->max_seed > 0) {
+        set_error("the directional-sweeping baseline takes sources on a node only (this batch has off-grid sources)");
+        return FM_EINVAL;
+    }
     if (b->nat_dev) return FM_OK;
     std::vector<NatDev> h(b->S);
     for (int32_t i = 0; i < b->S; i++) {
@@ -1185,6 +1407,8 @@ static int tune_key(fm_state* const* states, int32_t S, int32_t B, int32_t preci
         h = fnv1a_vec(h, st->pk.fblk_ptr);
         h = fnv1a_vec(h, st->pk.blk_k);
         h = fnv1a_vec(h, st->pk.rcv_node);
+        h = fnv1a_vec(h, st->pk.seed_node);
+        h = fnv1a_vec(h, st->pk.d_col);
     }
     char buf[512];
     snprintf(buf, sizeof(buf), "%s/%d/S%d/B%d/P%d/m%d%d%d%d/%016llx/%s %s", prop.gcnArchName, cus, S, B, precision,
@@ -1355,6 +1579,8 @@ struct TableChunk {
     SrcDev e[kTableChunk];
 };
 
+static_assert(sizeof(TableChunk) < 4096, "kernel arguments must stay below 4 KB");
+
 __global__ void k_put_table(SrcDev* dst, TableChunk c) {
     const int i = (int)threadIdx.x;
     if (i < c.count) dst[c.first + i] = c.e[i];
@@ -1428,6 +1654,7 @@ int apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precis
     b.d_src = (SrcDev*)base;
     b.scratch = xbytes ? (char*)base + table : nullptr;
     b.xB = B;
+    for (HostState* si : b.states) b.max_seed = std::max(b.max_seed, (int32_t)si->pk.seed_node.size());
     for (int32_t i0 = 0; i0 < S; i0 += kTableChunk) {
         TableChunk c{};
         c.first = i0;

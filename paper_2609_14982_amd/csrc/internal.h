@@ -73,6 +73,32 @@ struct Packed {
     std::vector<double> rcv_ew;        // [E] weight of each sorted entry
     int32_t max_blk_k = 0;
     int64_t max_level_nodes = 0;
+    // off-grid point source (all empty for an on-grid source).  Seed node
+    // seed_node[e] is an identity row whose right-hand side is
+    // sum_i seed_w[i] ds[seed_col[i]] over i in [seed_ptr[e], seed_ptr[e+1]);
+    // it has no forward position inside a level (the forward walk never
+    // computes it: a pass before the walk writes it).
+    std::vector<int32_t> seed_node, seed_ptr, seed_col;
+    std::vector<double> seed_w;
+    // direct term D_alpha: receiver r adds sum_i d_w[i] ds[d_col[i]] over
+    // i in [d_ptr[r], d_ptr[r+1]) (its P entries are dropped)
+    std::vector<int32_t> d_ptr, d_col;
+    std::vector<double> d_w;
+    // the transposes of both, grouped by target node for J^T: target
+    // sc_tgt[t] receives sum_i sc_w[i] v_i over i in [sc_ptr[t], sc_ptr[t+1]),
+    // v_i = lambda at node sc_idx[i] (sc_kind 0) or y at receiver sc_idx[i] (1)
+    std::vector<int32_t> sc_tgt, sc_ptr, sc_idx;
+    std::vector<uint8_t> sc_kind;
+    std::vector<double> sc_w;
+};
+
+// An off-grid point source: logical coordinates xi, the seed region of
+// max-norm radius rho around it, and the physical node coordinates X the
+// straight-ray seed times are measured in.
+struct PointSource {
+    const double* X;   // [N][dim]
+    double xi[3];
+    double rho;
 };
 
 struct DeviceState;   // defined in the HIP translation unit
@@ -112,7 +138,8 @@ namespace fm {
 // Receiver r is sum_k rcv_w[r*K + k] x[rcv[r*K + k]] (rcv_w NULL: weights 1);
 // entries of weight 0 are dropped.
 int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
-                const int64_t* rcv, const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out);
+                const int64_t* rcv, const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out,
+                const PointSource* ps = nullptr);
 
 // Natural-order records of the full operator (W for fwd, W^T otherwise) in
 // the packed record format, for the directional-sweeping comparison baseline.

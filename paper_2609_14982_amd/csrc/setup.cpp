@@ -162,7 +162,7 @@ void lu_inverse(int k, const double* lu, const int32_t* piv, double* x) {
 }
 
 int validate(const fm_grid* g, const double* T, const double* s, int64_t src, const int64_t* rcv,
-             const double* rcv_w, int32_t n_rcv, int32_t K, Grid& gr) {
+             const double* rcv_w, int32_t n_rcv, int32_t K, Grid& gr, const PointSource* ps) {
     if (!g || !g->G || !T || !s) { set_error("null argument"); return FM_EINVAL; }
     if (g->dim != 2 && g->dim != 3) { set_error("dim must be 2 or 3, got %d", g->dim); return FM_EINVAL; }
     if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) { set_error("grid sizes must be >= 1"); return FM_EINVAL; }
@@ -178,7 +178,18 @@ int validate(const fm_grid* g, const double* T, const double* s, int64_t src, co
     gr.G = g->G;
     gr.ncomp_g = g->dim == 3 ? 6 : 3;
     if (gr.N >= (int64_t)kNodeMask) { set_error("grid too large: %lld nodes", (long long)gr.N); return FM_EINVAL; }
-    if (src < 0 || src >= gr.N) { set_error("source node %lld out of range", (long long)src); return FM_EINVAL; }
+    if (!ps && (src < 0 || src >= gr.N)) { set_error("source node %lld out of range", (long long)src); return FM_EINVAL; }
+    if (ps) {
+        if (!ps->X) { set_error("an off-grid source needs the node coordinates"); return FM_EINVAL; }
+        if (!(ps->rho >= 0.0) || !std::isfinite(ps->rho)) { set_error("seed radius must be finite and >= 0"); return FM_EINVAL; }
+        for (int d = 0; d < gr.dim; d++)
+            if (!(ps->xi[d] >= 0.0) || !(ps->xi[d] <= (double)(gr.n[d] - 1))) {
+                set_error("source coordinate %d (%g) outside the grid [0, %lld]", d, ps->xi[d], (long long)(gr.n[d] - 1));
+                return FM_EINVAL;
+            }
+        for (int64_t i = 0; i < gr.N * gr.dim; i++)
+            if (!std::isfinite(ps->X[i])) { set_error("node coordinates are not finite"); return FM_EINVAL; }
+    }
     if (n_rcv < 0 || (n_rcv > 0 && !rcv)) { set_error("bad receiver list"); return FM_EINVAL; }
     if (K < 1 || K > 64) { set_error("entries per receiver must be 1 to 64, got %d", K); return FM_EINVAL; }
     for (int64_t e = 0; e < (int64_t)n_rcv * K; e++) {
@@ -201,19 +212,44 @@ int validate(const fm_grid* g, const double* T, const double* s, int64_t src, co
         for (int c = 0; c < gr.dim; c++)
             if (!(m[c] > 0.0)) { set_error("G[%lld] has a nonpositive diagonal", (long long)p); return FM_EINVAL; }
     }
-    if (T[src] != 0.0) { set_error("T at the source node must be 0, got %g", T[src]); return FM_EINVAL; }
+    if (!ps && T[src] != 0.0) { set_error("T at the source node must be 0, got %g", T[src]); return FM_EINVAL; }
     return FM_OK;
+}
+
+// The off-grid source's cell: corners (axis 0 fastest in the corner bits)
+// and multilinear weights; a coordinate on a cell face gives weight 1 there.
+void source_cell(const Grid& gr, const double* xi, int64_t corner[8], double wt[8], int& nc) {
+    int64_t base[3] = {0, 0, 0};
+    double t[3] = {0, 0, 0};
+    for (int d = 0; d < gr.dim; d++) {
+        int64_t b = (int64_t)std::floor(xi[d]);
+        b = std::min<int64_t>(std::max<int64_t>(b, 0), std::max<int64_t>(gr.n[d] - 2, 0));
+        base[d] = b;
+        t[d] = xi[d] - (double)b;
+    }
+    nc = 1 << gr.dim;
+    for (int c = 0; c < nc; c++) {
+        double w = 1.0;
+        int64_t p = 0;
+        for (int d = 0; d < gr.dim; d++) {
+            const int up = (c >> d) & 1;
+            w *= up ? t[d] : 1.0 - t[d];
+            p += (base[d] + (gr.n[d] > 1 ? up : 0)) * gr.stride[d];
+        }
+        corner[c] = p;
+        wt[c] = w;
+    }
 }
 
 }  // namespace
 
 int build_state(const fm_grid* g, const double* T, const double* s, int64_t src, const int64_t* rcv,
-                const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out) {
+                const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out, const PointSource* ps) {
     auto t0 = std::chrono::steady_clock::now();
     if (!out) { set_error("null output pointer"); return FM_EINVAL; }
     *out = nullptr;
     Grid gr;
-    int rc = validate(g, T, s, src, rcv, rcv_w, n_rcv, K, gr);
+    int rc = validate(g, T, s, src, rcv, rcv_w, n_rcv, K, gr, ps);
     if (rc != FM_OK) return rc;
     fm_state* st = new (std::nothrow) fm_state();
     if (!st) { set_error("out of host memory"); return FM_ENOMEM; }
@@ -223,6 +259,53 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         for (int a = 0; a < 3; a++) { st->n[a] = gr.n[a]; st->stride[a] = gr.stride[a]; }
         st->N = N;
         st->src = src;
+
+        // ---- 0: an off-grid source's seed region (identity rows) ----
+        // seed rows take the derivative of the straight-ray seed time
+        // T_p = (s_src + s_p)/2 |X_p - x_src| as their right-hand side:
+        // q_p = |X_p - x_src|/2 (sum_k phi_k ds_k + ds_p)
+        std::vector<uint8_t> ident(N, 0);
+        int64_t cell[8];
+        double phi[8];
+        int ncell = 0;
+        double x_src[3] = {0, 0, 0};
+        Packed& pk0 = st->pk;
+        if (ps) {
+            source_cell(gr, ps->xi, cell, phi, ncell);
+            for (int c = 0; c < ncell; c++)
+                for (int d = 0; d < gr.dim; d++) x_src[d] += phi[c] * ps->X[(size_t)gr.dim * cell[c] + d];
+            int64_t lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+            for (int d = 0; d < gr.dim; d++) {
+                lo[d] = std::max<int64_t>(0, (int64_t)std::ceil(ps->xi[d] - ps->rho));
+                hi[d] = std::min<int64_t>(gr.n[d] - 1, (int64_t)std::floor(ps->xi[d] + ps->rho));
+            }
+            pk0.seed_ptr.assign(1, 0);
+            for (int64_t k = lo[2]; k <= hi[2]; k++)
+                for (int64_t j = lo[1]; j <= hi[1]; j++)
+                    for (int64_t i = lo[0]; i <= hi[0]; i++) {
+                        const int64_t p = i + gr.stride[1] * j + gr.stride[2] * k;
+                        ident[p] = 1;
+                        double r2 = 0.0;
+                        for (int d = 0; d < gr.dim; d++) {
+                            const double dx = ps->X[(size_t)gr.dim * p + d] - x_src[d];
+                            r2 += dx * dx;
+                        }
+                        const double half_r = 0.5 * std::sqrt(r2);
+                        pk0.seed_node.push_back((int32_t)p);
+                        for (int c = 0; c < ncell; c++) {
+                            pk0.seed_col.push_back((int32_t)cell[c]);
+                            pk0.seed_w.push_back(half_r * phi[c]);
+                        }
+                        pk0.seed_col.push_back((int32_t)p);
+                        pk0.seed_w.push_back(half_r);
+                        pk0.seed_ptr.push_back((int32_t)pk0.seed_col.size());
+                    }
+            if (pk0.seed_node.empty()) { set_error("the seed region holds no node"); delete st; return FM_EINVAL; }
+            src = pk0.seed_node[0];
+            st->src = src;
+        } else {
+            ident[src] = 1;
+        }
 
         // ---- 1-2: couplings, weights, calibration (Sections 3.1-3.2) ----
         st->pmask.assign(N, 0);
@@ -247,7 +330,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             for (int slot = 0; slot < nslot; slot++) dsum = dsum + c6[slot];
             double acc = 0.0;
             uint8_t mask = 0;
-            if (p != src && dsum > 0.0) {
+            if (!ident[p] && dsum > 0.0) {
                 for (int slot = 0; slot < nslot; slot++) {
                     if (c6[slot] > 0.0) {
                         double w = c6[slot] / dsum;
@@ -264,6 +347,8 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             double ell = T[p] - acc;
             st->cal[p] = ell / s[p];
         }
+        if (ps)
+            for (int32_t p : st->pk.seed_node) st->cal[p] = 0.0;   // their right-hand side is the seed row
         st->smask.assign(N, 0);
         for (int64_t p = 0; p < N; p++) {
             uint8_t m = st->pmask[p];
@@ -465,10 +550,14 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                                   std::vector<int32_t>& blk_ptr, std::vector<int32_t>& blk_id,
                                   std::vector<int32_t>& blk_pos, std::vector<int32_t>& pos_of, int32_t L) {
             const std::vector<int32_t>& clev = fwd ? st->clev_f : st->clev_r;
+            // an off-grid source's seed nodes take no part in the forward walk
+            // (a pass before it writes their values): they get the last
+            // positions, after every level
+            auto skip = [&](int32_t v) { return fwd && ps && ident[v]; };
             std::vector<int64_t> cnt_sc(L + 1, 0), cnt_bl(L + 1, 0), nb(L + 1, 0);
             for (int32_t c = 0; c < ncomp; c++) {
                 int32_t k = st->cptr[c + 1] - st->cptr[c];
-                if (k == 1) cnt_sc[clev[c]]++;
+                if (k == 1) { if (!skip(st->cnodes[st->cptr[c]])) cnt_sc[clev[c]]++; }
                 else { cnt_bl[clev[c]] += k; nb[clev[c]]++; }
             }
             lvl_ptr.assign(L + 1, 0);
@@ -489,13 +578,15 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             blk_id.assign(nblk, 0);
             blk_pos.assign(nblk, 0);
             pos_of.assign(N, 0);
+            int32_t next_tail = lvl_ptr[L];
             // components in id order; singletons of one level then come in
             // ascending component id; sort each level's singletons by node id
             for (int32_t c = 0; c < ncomp; c++) {
                 int32_t k = st->cptr[c + 1] - st->cptr[c];
                 int32_t l = clev[c];
                 if (k == 1) {
-                    pos_of[st->cnodes[st->cptr[c]]] = next_sc[l]++;
+                    const int32_t v = st->cnodes[st->cptr[c]];
+                    pos_of[v] = skip(v) ? next_tail++ : next_sc[l]++;
                 } else {
                     int32_t b = comp_blk[c];
                     blk_id[next_b[l]++] = b;
@@ -571,7 +662,46 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         pk.rcv_node.clear();
         pk.rcv_wt.clear();
         std::vector<int32_t> ent_rcv;
+        // an off-grid source: a receiver inside the seed region takes the
+        // straight-ray time directly, d_r = (s_src + s_r)/2 |x_r - x_src|
+        // (s_r, x_r interpolated by its own weights): no P entries, and the
+        // row |x_r - x_src|/2 (sum_k phi_k ds_k + sum_e w_e ds_e) of D_alpha
+        if (ps) pk.d_ptr.assign((size_t)n_rcv + 1, 0);
         for (int32_t r = 0; r < n_rcv; r++) {
+            if (ps) {
+                double xr_log[3] = {0, 0, 0}, xr[3] = {0, 0, 0};
+                for (int32_t k = 0; k < K; k++) {
+                    const int64_t e = (int64_t)r * K + k;
+                    const double w = rcv_w ? rcv_w[e] : 1.0;
+                    for (int d = 0; d < gr.dim; d++) {
+                        xr_log[d] += w * (double)coord(gr, rcv[e], d);
+                        xr[d] += w * ps->X[(size_t)gr.dim * rcv[e] + d];
+                    }
+                }
+                bool direct = true;
+                for (int d = 0; d < gr.dim; d++)
+                    if (!(std::fabs(xr_log[d] - ps->xi[d]) <= ps->rho)) direct = false;
+                if (direct) {
+                    double r2 = 0.0;
+                    for (int d = 0; d < gr.dim; d++) r2 += (xr[d] - x_src[d]) * (xr[d] - x_src[d]);
+                    const double half_r = 0.5 * std::sqrt(r2);
+                    for (int c = 0; c < ncell; c++) {
+                        pk.d_col.push_back((int32_t)cell[c]);
+                        pk.d_w.push_back(half_r * phi[c]);
+                    }
+                    for (int32_t k = 0; k < K; k++) {
+                        const int64_t e = (int64_t)r * K + k;
+                        const double w = rcv_w ? rcv_w[e] : 1.0;
+                        if (w == 0.0) continue;
+                        pk.d_col.push_back((int32_t)rcv[e]);
+                        pk.d_w.push_back(half_r * w);
+                    }
+                    pk.d_ptr[r + 1] = (int32_t)pk.d_col.size();
+                    pk.rcv_ptr[r + 1] = (int32_t)pk.rcv_node.size();
+                    continue;
+                }
+                pk.d_ptr[r + 1] = (int32_t)pk.d_col.size();
+            }
             for (int32_t k = 0; k < K; k++) {
                 const int64_t e = (int64_t)r * K + k;
                 const double w = rcv_w ? rcv_w[e] : 1.0;
@@ -606,6 +736,35 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             }
         }
 
+        // the transposes of the seed rows and of D, grouped by target node
+        // (ascending; in a target, seed entries in seed order, then direct
+        // entries in receiver order): J^T adds them after the reverse walk
+        if (ps) {
+            struct Ent { int32_t tgt, order; uint8_t kind; int32_t idx; double w; };
+            std::vector<Ent> ents;
+            int32_t ord = 0;
+            for (size_t e = 0; e + 1 < pk.seed_ptr.size(); e++)
+                for (int32_t i = pk.seed_ptr[e]; i < pk.seed_ptr[e + 1]; i++)
+                    ents.push_back({pk.seed_col[i], ord++, 0, pk.seed_node[e], pk.seed_w[i]});
+            for (int32_t r = 0; r < n_rcv; r++)
+                for (int32_t i = pk.d_ptr[r]; i < pk.d_ptr[r + 1]; i++)
+                    ents.push_back({pk.d_col[i], ord++, 1, r, pk.d_w[i]});
+            std::stable_sort(ents.begin(), ents.end(), [](const Ent& a, const Ent& b) {
+                return a.tgt != b.tgt ? a.tgt < b.tgt : a.order < b.order;
+            });
+            pk.sc_ptr.assign(1, 0);
+            for (size_t i = 0; i < ents.size(); i++) {
+                if (i == 0 || ents[i].tgt != ents[i - 1].tgt) {
+                    if (i > 0) pk.sc_ptr.push_back((int32_t)i);
+                    pk.sc_tgt.push_back(ents[i].tgt);
+                }
+                pk.sc_kind.push_back(ents[i].kind);
+                pk.sc_idx.push_back(ents[i].idx);
+                pk.sc_w.push_back(ents[i].w);
+            }
+            if (!ents.empty()) pk.sc_ptr.push_back((int32_t)ents.size());
+        }
+
         // ---- statistics ----
         int64_t n_unr = 0;
         for (int64_t p = 0; p < N; p++) n_unr += unres[st->comp[p]];
@@ -625,6 +784,9 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         S.f_unr = (double)n_unr / (double)N;
         S.state_bytes = (int64_t)(pk.fmeta.size() + pk.rmeta.size()) * 8 +
                         (int64_t)(pk.fwts.size() + pk.rwts.size() + 2 * pk.inv.size() + pk.cal_nat.size()) * 8;
+        S.n_seed = (int32_t)pk.seed_node.size();
+        S.n_direct = 0;
+        for (size_t r = 0; r + 1 < pk.d_ptr.size(); r++) S.n_direct += pk.d_ptr[r + 1] > pk.d_ptr[r];
         S.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     } catch (const std::bad_alloc&) {
         delete st;
