@@ -43,14 +43,18 @@ def algorithmic_bytes(stats_list, B, vbytes, wbytes):
     source its state read once - per node the mean edge count times a weight
     and a 4-byte index, a calibration weight and two 4-byte indices
     (N * (ebar * (wbytes + 4) + 4 + wbytes + 4)) - and the FP64 SCC block
-    matrix of that direction (8 * sum k^2).  Predecessor re-reads count as
+    matrix of that direction (8 * sum k^2 over the blocks kept as dense
+    inverses; a block solved by its Neumann series reads its in-block
+    couplings, a weight and a 4-byte index each, 12 * couplings).
+    Predecessor re-reads and the series' re-reads of the couplings count as
     cache hits.  A broadcast input counts once per (source, rhs), as every
     source reads it."""
     total = 0
     for st in stats_list:
-        N, k2 = st["N"], st["sum_k2"]
+        N = st["N"]
         ebar = st["E"] / N
-        total += 2 * vbytes * N * B + N * (ebar * (wbytes + 4) + 4 + wbytes + 4) + 8 * k2
+        blocks = 8 * st.get("dense_k2", st["sum_k2"]) + 12 * st.get("iter_nnz", 0)
+        total += 2 * vbytes * N * B + N * (ebar * (wbytes + 4) + 4 + wbytes + 4) + blocks
     return int(round(total))
 
 
@@ -62,7 +66,8 @@ def layout_bytes(stats_list, B, vbytes, wbytes, broadcast_once=False):
     for i, st in enumerate(stats_list):
         N, k2 = st["N"], st["sum_k2"]
         nin = 0 if (broadcast_once and i > 0) else 1
-        total += (nin + 1) * vbytes * N * B + (8 + 4 * wbytes) * N + 8 * k2
+        total += (nin + 1) * vbytes * N * B + (8 + 4 * wbytes) * N + 8 * st.get("dense_k2", k2) + \
+            12 * st.get("iter_nnz", 0)
     return total
 
 

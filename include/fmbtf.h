@@ -89,6 +89,10 @@ typedef struct fm_stats {
     int64_t state_bytes;    /* bytes of the packed per-source state (one precision) */
     int32_t n_seed;         /* seed-region nodes of an off-grid source (0 for a source on a node) */
     int32_t n_direct;       /* receivers an off-grid source reaches through its direct term D */
+    int32_t n_iter_blocks;  /* nontrivial SCCs solved iteratively (fm_set_iterative_block_min) */
+    int32_t max_iter;       /* most series terms of such a block (either direction) */
+    int64_t dense_k2;       /* sum of k^2 over the blocks kept as dense inverses */
+    int64_t iter_nnz;       /* in-block couplings stored for the iterative blocks */
 } fm_stats;
 
 /* Launch schedule of a batch; zero fields take the library default. */
@@ -200,6 +204,24 @@ int fm_build_frozen_states_pt(const fm_grid* g, const double* X, int32_t S, cons
                               const double* xi_src, double seed_radius, const int64_t* rcv_nodes,
                               const double* rcv_weights, int32_t n_rcv, int32_t k_per_rcv, int32_t nthreads,
                               fm_state** out);
+
+/*
+ * Solver of large SCC blocks (Section 6 leaves sparse or iterative block
+ * solvers for large components open; Section 4.3's dense local solve is the
+ * default).  Blocks of k >= k_min nodes that the builders create from now on
+ * are solved by the Neumann series of W_CC instead of a stored inverse:
+ * x_C = sum_{j<=m} W_CC^j b_C (transpose: W_CC^T), m chosen at build time as
+ * the least number of terms after which ||W_CC^{m+1}||_inf (||W_CC^{m+1}||_1
+ * for the transpose) is at most 2^-56, so the truncation is below FP64
+ * rounding; that norm being below 1 also proves A_C nonsingular (Theorem 1
+ * gives rho(W_CC) < 1).  A block whose series needs more than 200 terms keeps
+ * the dense inverse.  Such a block stores only its couplings (no k x k
+ * inverse, no O(k^3) factorisation); applying it costs m sparse products and,
+ * in the node split, m - 1 extra barriers between the P workgroups.
+ *   k_min  >= 2: that threshold; 0: the default (1024); < 0: never (all dense)
+ * Process-wide, read when a state is built; returns FM_OK.
+ */
+int fm_set_iterative_block_min(int32_t k_min);
 
 /* Structural statistics of a state (Section 5.2, eq. (graph-fractions)). */
 int fm_state_stats(const fm_state* st, fm_stats* out);

@@ -23,7 +23,7 @@ _ERRNAMES = {FM_EINVAL: "FM_EINVAL", FM_ESINGULAR: "FM_ESINGULAR", FM_ENOMEM: "F
 
 SYMBOLS = (
     "fm_build_frozen_state", "fm_build_frozen_states", "fm_build_frozen_state_w", "fm_build_frozen_states_w",
-    "fm_build_frozen_state_pt", "fm_build_frozen_states_pt", "fm_state_stats",
+    "fm_build_frozen_state_pt", "fm_build_frozen_states_pt", "fm_set_iterative_block_min", "fm_state_stats",
     "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
     "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_batch_status", "fm_batch_split_info",
     "fm_apply_J", "fm_apply_J_static",
@@ -54,7 +54,8 @@ class fm_stats(C.Structure):
                 ("n_cyc", C.c_int64), ("sum_k2", C.c_int64), ("n_vio", C.c_int64),
                 ("n_unr", C.c_int64), ("f_vio", C.c_double), ("f_cyc", C.c_double),
                 ("f_unr", C.c_double), ("setup_seconds", C.c_double), ("state_bytes", C.c_int64),
-                ("n_seed", C.c_int32), ("n_direct", C.c_int32)]
+                ("n_seed", C.c_int32), ("n_direct", C.c_int32), ("n_iter_blocks", C.c_int32),
+                ("max_iter", C.c_int32), ("dense_k2", C.c_int64), ("iter_nnz", C.c_int64)]
 
 
 class fm_tuning(C.Structure):
@@ -89,6 +90,7 @@ def load():
         "fm_build_frozen_states_w": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, i32, i32, i32, vp]),
         "fm_build_frozen_state_pt": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, vp, vp, i32, i32, vp]),
         "fm_build_frozen_states_pt": (C.c_int, [vp, vp, i32, vp, vp, vp, C.c_double, vp, vp, i32, i32, i32, vp]),
+        "fm_set_iterative_block_min": (C.c_int, [i32]),
         "fm_state_stats": (C.c_int, [vp, vp]),
         "fm_state_export_operator": (C.c_int, [vp, vp, vp, vp, vp]),
         "fm_state_export_graph": (C.c_int, [vp, vp, vp, vp]),
@@ -278,6 +280,12 @@ def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nth
                                       rcv.ctypes.data if rcv.size else None, int(rcv.shape[1]),
                                       int(nthreads), outs))
     return [State(outs[a], N, dim, (n1, n2, n3), int(rcv.shape[1])) for a in range(S)]
+
+
+def set_iterative_block_min(k_min):
+    """fm_set_iterative_block_min: states built from now on solve SCC blocks of
+    at least k_min nodes by their Neumann series (0: default, < 0: never)."""
+    _check(load().fm_set_iterative_block_min(int(k_min)))
 
 
 def _receivers_pt(rcv_nodes, rcv_weights, S):

@@ -57,7 +57,15 @@ struct SrcDev {
     const int32_t* blk_fpos;
     const int32_t* blk_rpos;
     const int64_t* blk_inv;
-    const int64_t* blk_moff;    // first staging row of each block (prefix sum of k)
+    const int64_t* blk_moff;    // first staging row of each block (prefix sum of k, 3k iterative)
+    const int32_t* blk_it;      // [2 nblk] series terms, primal and transpose (0: dense inverse)
+    const int64_t* blk_sp;      // [nblk] first row pointer of an iterative block's couplings
+    const int32_t* sp_ptr;      // in-block couplings, primal rows (member order)
+    const int32_t* sp_col;
+    const double* sp_w;
+    const int32_t* spt_ptr;     // the same, transpose rows
+    const int32_t* spt_col;
+    const double* spt_w;
     const double* inv;
     const double* invt;
     const void* cal_nat;

@@ -185,6 +185,13 @@ int fm_build_frozen_states_pt(const fm_grid* g, const double* X, int32_t S, cons
     return FM_OK;
 }
 
+int fm_set_iterative_block_min(int32_t k_min) {
+    fm::clear_error();
+    if (k_min == 1) { fm::set_error("a block has at least 2 nodes: k_min must be >= 2, 0 or negative"); return FM_EINVAL; }
+    fm::set_iterative_min(k_min);
+    return FM_OK;
+}
+
 int fm_state_stats(const fm_state* st, fm_stats* out) {
     fm::clear_error();
     if (!st || !out) { fm::set_error("null argument"); return FM_EINVAL; }

@@ -88,9 +88,17 @@ int upload_state(HostState* st) {
     std::vector<int64_t> moff(pk.blk_k.size());
     {
         int64_t acc = 0;
-        for (size_t i = 0; i < pk.blk_k.size(); i++) { moff[i] = acc; acc += pk.blk_k[i]; }
+        for (size_t i = 0; i < pk.blk_k.size(); i++) { moff[i] = acc; acc += block_stage_rows(pk, (int32_t)i); }
     }
     size_t o_moff = ar.add<int64_t>(moff.size());
+    size_t o_bit = ar.add<int32_t>(pk.blk_it.size());
+    size_t o_bsp = ar.add<int64_t>(pk.blk_sp.size());
+    size_t o_spp = ar.add<int32_t>(pk.sp_ptr.size());
+    size_t o_spc = ar.add<int32_t>(pk.sp_col.size());
+    size_t o_spw = ar.add<double>(pk.sp_w.size());
+    size_t o_stp = ar.add<int32_t>(pk.spt_ptr.size());
+    size_t o_stc = ar.add<int32_t>(pk.spt_col.size());
+    size_t o_stw = ar.add<double>(pk.spt_w.size());
     size_t o_inv = ar.add<double>(pk.inv.size());
     size_t o_invt = ar.add<double>(pk.invt.size());
     size_t o_cal = ar.add<double>(pk.cal_nat.size());
@@ -143,6 +151,14 @@ int upload_state(HostState* st) {
     rc = rc ? rc : put(b, o_brp, pk.blk_rpos);
     rc = rc ? rc : put(b, o_binv, pk.blk_inv);
     rc = rc ? rc : put(b, o_moff, moff);
+    rc = rc ? rc : put(b, o_bit, pk.blk_it);
+    rc = rc ? rc : put(b, o_bsp, pk.blk_sp);
+    rc = rc ? rc : put(b, o_spp, pk.sp_ptr);
+    rc = rc ? rc : put(b, o_spc, pk.sp_col);
+    rc = rc ? rc : put(b, o_spw, pk.sp_w);
+    rc = rc ? rc : put(b, o_stp, pk.spt_ptr);
+    rc = rc ? rc : put(b, o_stc, pk.spt_col);
+    rc = rc ? rc : put(b, o_stw, pk.spt_w);
     rc = rc ? rc : put(b, o_inv, pk.inv);
     rc = rc ? rc : put(b, o_invt, pk.invt);
     rc = rc ? rc : put(b, o_cal, pk.cal_nat);
@@ -206,6 +222,14 @@ int upload_state(HostState* st) {
     d.blk_rpos = (const int32_t*)(b + o_brp);
     d.blk_inv = (const int64_t*)(b + o_binv);
     d.blk_moff = (const int64_t*)(b + o_moff);
+    d.blk_it = (const int32_t*)(b + o_bit);
+    d.blk_sp = (const int64_t*)(b + o_bsp);
+    d.sp_ptr = (const int32_t*)(b + o_spp);
+    d.sp_col = (const int32_t*)(b + o_spc);
+    d.sp_w = (const double*)(b + o_spw);
+    d.spt_ptr = (const int32_t*)(b + o_stp);
+    d.spt_col = (const int32_t*)(b + o_stc);
+    d.spt_w = (const double*)(b + o_stw);
     d.inv = (const double*)(b + o_inv);
     d.invt = (const double*)(b + o_invt);
     d.cal_nat = b + o_cal;
@@ -754,7 +778,7 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     int64_t rows = 1;
     for (HostState* st : b->states) {
         int64_t sum = 0;
-        for (int32_t k : st->pk.blk_k) sum += k;
+        for (int32_t i = 0; i < st->pk.nblk; i++) sum += block_stage_rows(st->pk, i);
         rows = std::max(rows, sum);
     }
     t.split = P;
@@ -879,21 +903,24 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     HostState* s0 = static_cast<HostState*>(states[0]);
     if (!s0) { set_error("null state"); return FM_EINVAL; }
     int32_t R = (int32_t)s0->pk.rcv_ptr.size() - 1;
-    int32_t maxk = 0;
+    int64_t maxk = 0;
     for (int32_t i = 0; i < S; i++) {
         HostState* si = static_cast<HostState*>(states[i]);
         if (!si) { set_error("null state %d", i); return FM_EINVAL; }
         if (!si->same_grid(*s0)) { set_error("state %d has another grid shape", i); return FM_EINVAL; }
         if ((int32_t)si->pk.rcv_ptr.size() - 1 != R) { set_error("state %d has another receiver count", i); return FM_EINVAL; }
-        maxk = std::max(maxk, si->pk.max_blk_k);
+        maxk = std::max<int64_t>(maxk, si->pk.max_blk_rows);
     }
     fm_tuning t{};
     if (tuning) t = *tuning;
     if (t.threads == 0) t.threads = 1024;
     if (t.unroll == 0) t.unroll = 2;
     if (t.rhs_per_group == 0) {
+        // up to 4 rhs per group, fewer when the blocks' staged rows would not
+        // fit the LDS of the rhs-group kernel
         t.rhs_per_group = 1;
-        while (t.rhs_per_group < 16 && B % (t.rhs_per_group * 2) == 0 && t.rhs_per_group * 2 <= 4)
+        while (t.rhs_per_group < 16 && B % (t.rhs_per_group * 2) == 0 && t.rhs_per_group * 2 <= 4 &&
+               (size_t)maxk * t.rhs_per_group * 2 * sizeof(double) <= kLdsMax)
             t.rhs_per_group *= 2;
     }
     t.xcd_aware = t.xcd_aware < 0 ? 0 : 1;
@@ -905,7 +932,8 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     if (t.unroll < 1 || t.unroll > 6) { set_error("unroll must be 1 to 6"); return FM_EINVAL; }
     size_t need = (size_t)maxk * rg * sizeof(double);
     if (need > kLdsMax) {
-        set_error("largest SCC block (%d nodes) needs %zu B of LDS with %d rhs per group; use fewer", maxk, need, rg);
+        set_error("the SCC blocks need %lld staged rows (%zu B of LDS with %d rhs per group) in the rhs-group "
+                  "kernel; use fewer rhs per group", (long long)maxk, need, rg);
         return FM_EINVAL;
     }
     size_t lds = std::max(need, (size_t)std::min<int64_t>(t.min_lds_bytes, (int64_t)kLdsMax));
@@ -1407,6 +1435,7 @@ static int tune_key(fm_state* const* states, int32_t S, int32_t B, int32_t preci
         h = fnv1a_vec(h, st->pk.fblk_ptr);
         h = fnv1a_vec(h, st->pk.blk_k);
         h = fnv1a_vec(h, st->pk.rcv_node);
+        h = fnv1a_vec(h, st->pk.blk_it);
         h = fnv1a_vec(h, st->pk.seed_node);
         h = fnv1a_vec(h, st->pk.d_col);
     }
@@ -1596,7 +1625,7 @@ int apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precis
     HostState* s0 = static_cast<HostState*>(states[0]);
     if (!s0) { set_error("null state"); return FM_EINVAL; }
     const int32_t R = (int32_t)s0->pk.rcv_ptr.size() - 1;
-    int32_t maxk = 0;
+    int64_t maxk = 0;
     for (int32_t i = 0; i < S; i++) {
         HostState* si = static_cast<HostState*>(states[i]);
         if (!si) { set_error("null state %d", i); return FM_EINVAL; }
@@ -1607,20 +1636,22 @@ int apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precis
                       "(that call uploads the state and allocates)", i, dev, precision);
             return FM_ESTATE;
         }
-        maxk = std::max(maxk, si->pk.max_blk_k);
+        maxk = std::max<int64_t>(maxk, si->pk.max_blk_rows);
     }
     // the library's default rhs-group schedule
     fm_tuning t{};
     t.threads = 1024;
     t.unroll = 2;
     t.rhs_per_group = 1;
-    while (t.rhs_per_group < 4 && B % (t.rhs_per_group * 2) == 0) t.rhs_per_group *= 2;
+    while (t.rhs_per_group < 4 && B % (t.rhs_per_group * 2) == 0 &&
+           (size_t)maxk * t.rhs_per_group * 2 * sizeof(double) <= kLdsMax)
+        t.rhs_per_group *= 2;
     t.xcd_aware = 1;
     t.min_lds_bytes = 96 * 1024;
     t.split = 1;
     const size_t need = (size_t)maxk * t.rhs_per_group * sizeof(double);
     if (need > kLdsMax) {
-        set_error("largest SCC block (%d nodes) needs %zu B of LDS", maxk, need);
+        set_error("the SCC blocks need %lld staged rows (%zu B of LDS)", (long long)maxk, need);
         return FM_EINVAL;
     }
     const size_t vbytes = precision == FM_FP64 ? 8 : 4;

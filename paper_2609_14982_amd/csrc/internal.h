@@ -73,6 +73,18 @@ struct Packed {
     std::vector<double> rcv_ew;        // [E] weight of each sorted entry
     int32_t max_blk_k = 0;
     int64_t max_level_nodes = 0;
+    // Large blocks solved iteratively (Neumann series of W_CC, no inverse):
+    // blk_it[2b], blk_it[2b+1] = iterations of the primal and transpose solve
+    // (both 0: a dense block with an inverse at blk_inv[b]; blk_inv[b] = -1
+    // otherwise).  The in-block couplings of such a block, member order:
+    // primal row i in sp_ptr[blk_sp[b] + i .. + i + 1) lists members j with
+    // w_ij > 0 (sp_col, sp_w); transpose row j in spt_* the same way lists
+    // members i with weight w_ij.
+    std::vector<int32_t> blk_it;
+    std::vector<int64_t> blk_sp;
+    std::vector<int32_t> sp_ptr, sp_col, spt_ptr, spt_col;
+    std::vector<double> sp_w, spt_w;
+    int64_t max_blk_rows = 0;          // most FP64 rows one block stages (k, or 3k iterative)
     // off-grid point source (all empty for an on-grid source).  Seed node
     // seed_node[e] is an identity row whose right-hand side is
     // sum_i seed_w[i] ds[seed_col[i]] over i in [seed_ptr[e], seed_ptr[e+1]);
@@ -140,6 +152,19 @@ namespace fm {
 int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 const int64_t* rcv, const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out,
                 const PointSource* ps = nullptr);
+
+// Staging rows of block b: its right-hand sides, plus two iterate buffers
+// when it is solved iteratively.
+inline int64_t block_stage_rows(const Packed& pk, int32_t b) {
+    return (int64_t)pk.blk_k[b] * (pk.blk_it[2 * (size_t)b] ? 3 : 1);
+}
+
+// Blocks of at least this many nodes are solved iteratively when the Neumann
+// series reaches full precision within kNeumannMax terms (<= 0: never).
+constexpr int32_t kIterativeMinDefault = 1024;
+constexpr int32_t kNeumannMax = 200;
+void set_iterative_min(int32_t k_min);
+int32_t iterative_min();
 
 // Natural-order records of the full operator (W for fwd, W^T otherwise) in
 // the packed record format, for the directional-sweeping comparison baseline.

@@ -15,6 +15,7 @@
 // with -ffp-contract=off, so every upwind sign decision is a reproducible FP64
 // decision.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -26,6 +27,11 @@
 #include "internal.h"
 
 namespace fm {
+
+static std::atomic<int32_t> g_iterative_min{kIterativeMinDefault};
+
+void set_iterative_min(int32_t k_min) { g_iterative_min.store(k_min == 0 ? kIterativeMinDefault : k_min); }
+int32_t iterative_min() { return g_iterative_min.load(); }
 
 namespace {
 
@@ -476,6 +482,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         }
 
         // ---- 6: factor every nontrivial block, keep A_C^{-1} ----
+        // (large blocks: the Neumann series of W_CC instead, see below)
         Packed& pk = st->pk;
         std::vector<int32_t> blk_comp;
         for (int32_t c = 0; c < ncomp; c++)
@@ -485,17 +492,104 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         pk.nblk = nblk;
         pk.blk_k.resize(nblk);
         pk.blk_inv.resize(nblk);
-        int64_t inv_total = 0, n_cyc = 0;
+        pk.blk_it.assign((size_t)2 * nblk, 0);
+        pk.blk_sp.assign(nblk, -1);
+        pk.sp_ptr.clear();
+        pk.sp_col.clear();
+        pk.sp_w.clear();
+        pk.spt_ptr.clear();
+        pk.spt_col.clear();
+        pk.spt_w.clear();
+        // A block of k >= the iterative threshold whose series converges is
+        // solved as x = sum_{j<=m} W_CC^j b (Theorem 1: rho(W_CC) < 1), with
+        // m the least number of terms after which ||W_CC^{m+1}||_inf <= 2^-56
+        // relative to x (primal), ||(W_CC^T)^{m+1}||_inf the same (transpose).
+        // W_CC >= 0, so these norms are exactly the largest entries of
+        // W^{m+1} 1 and (W^T)^{m+1} 1, and a norm below 1 also proves A_C
+        // nonsingular.
+        const int32_t it_min = iterative_min();
+        for (int32_t b = 0; b < nblk; b++) {
+            const int32_t c = blk_comp[b];
+            const int32_t k = st->cptr[c + 1] - st->cptr[c];
+            if (it_min <= 0 || k < it_min) continue;
+            const int32_t* mem = st->cnodes.data() + st->cptr[c];
+            // in-block couplings, rows in member order, columns ascending
+            std::vector<int32_t> rp(1, 0), cl;
+            std::vector<double> wv;
+            for (int32_t i = 0; i < k; i++) {
+                const int32_t v = mem[i];
+                const uint8_t pm = st->pmask[v];
+                std::vector<std::pair<int32_t, double>> row;
+                for (int slot = 0; slot < nslot; slot++) {
+                    if (!(pm & (1u << slot))) continue;
+                    const int32_t u = (int32_t)nbr(gr, v, slot);
+                    if (st->comp[u] != c) continue;
+                    row.push_back({(int32_t)(std::lower_bound(mem, mem + k, u) - mem), st->w6[(size_t)v * 6 + slot]});
+                }
+                std::sort(row.begin(), row.end());
+                for (auto& e : row) { cl.push_back(e.first); wv.push_back(e.second); }
+                rp.push_back((int32_t)cl.size());
+            }
+            // the transpose, rows = columns of W_CC, entries in ascending row order
+            std::vector<int32_t> tp(k + 1, 0), tc(cl.size());
+            std::vector<double> tw(cl.size());
+            for (int32_t col : cl) tp[col + 1]++;
+            for (int32_t j = 0; j < k; j++) tp[j + 1] += tp[j];
+            {
+                std::vector<int32_t> fill(tp.begin(), tp.end() - 1);
+                for (int32_t i = 0; i < k; i++)
+                    for (int32_t e = rp[i]; e < rp[i + 1]; e++) {
+                        tc[fill[cl[e]]] = i;
+                        tw[fill[cl[e]]++] = wv[e];
+                    }
+            }
+            auto terms = [&](const std::vector<int32_t>& ptr, const std::vector<int32_t>& col,
+                             const std::vector<double>& w) {
+                std::vector<double> v(k, 1.0), nv(k);
+                for (int32_t j = 1; j <= kNeumannMax + 1; j++) {
+                    double mx = 0.0;
+                    for (int32_t i = 0; i < k; i++) {
+                        double a = 0.0;
+                        for (int32_t e = ptr[i]; e < ptr[i + 1]; e++) a += w[e] * v[col[e]];
+                        nv[i] = a;
+                        mx = std::max(mx, a);
+                    }
+                    v.swap(nv);
+                    if (mx <= 0x1p-56) return std::max(j - 1, 1);
+                }
+                return 0;   // no convergence within the cap: dense
+            };
+            const int32_t mf = terms(rp, cl, wv);
+            const int32_t mr = mf ? terms(tp, tc, tw) : 0;
+            if (!mf || !mr) continue;
+            pk.blk_it[2 * (size_t)b] = mf;
+            pk.blk_it[2 * (size_t)b + 1] = mr;
+            const int32_t base = (int32_t)pk.sp_col.size();
+            pk.blk_sp[b] = (int64_t)pk.sp_ptr.size();
+            for (int32_t i = 0; i <= k; i++) {
+                pk.sp_ptr.push_back(base + rp[i]);
+                pk.spt_ptr.push_back(base + tp[i]);
+            }
+            pk.sp_col.insert(pk.sp_col.end(), cl.begin(), cl.end());
+            pk.sp_w.insert(pk.sp_w.end(), wv.begin(), wv.end());
+            pk.spt_col.insert(pk.spt_col.end(), tc.begin(), tc.end());
+            pk.spt_w.insert(pk.spt_w.end(), tw.begin(), tw.end());
+        }
+        int64_t inv_total = 0, n_cyc = 0, k2_all = 0;
         int32_t largest = 0;
+        pk.max_blk_rows = 0;
         for (int32_t b = 0; b < nblk; b++) {
             int32_t c = blk_comp[b];
             comp_blk[c] = b;
             int32_t k = st->cptr[c + 1] - st->cptr[c];
             pk.blk_k[b] = k;
-            pk.blk_inv[b] = inv_total;
-            inv_total += (int64_t)k * k;
+            const bool iter = pk.blk_it[2 * (size_t)b] != 0;
+            pk.blk_inv[b] = iter ? -1 : inv_total;
+            if (!iter) inv_total += (int64_t)k * k;
+            k2_all += (int64_t)k * k;
             n_cyc += k;
             largest = std::max(largest, k);
+            pk.max_blk_rows = std::max(pk.max_blk_rows, block_stage_rows(pk, b));
         }
         pk.max_blk_k = largest;
         pk.inv.assign((size_t)inv_total, 0.0);
@@ -504,6 +598,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             std::vector<double> a, x;
             std::vector<int32_t> piv, local(0);
             for (int32_t b = 0; b < nblk; b++) {
+                if (pk.blk_it[2 * (size_t)b]) continue;   // iterative: no factors
                 int32_t c = blk_comp[b];
                 int32_t k = pk.blk_k[b];
                 const int32_t* mem = st->cnodes.data() + st->cptr[c];
@@ -776,14 +871,25 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         S.n_scc = nblk;
         S.largest_scc = largest;
         S.n_cyc = n_cyc;
-        S.sum_k2 = inv_total;
+        S.sum_k2 = k2_all;
+        S.dense_k2 = inv_total;
+        S.n_iter_blocks = 0;
+        S.max_iter = 0;
+        S.iter_nnz = (int64_t)pk.sp_col.size();
+        for (int32_t b = 0; b < nblk; b++)
+            if (pk.blk_it[2 * (size_t)b]) {
+                S.n_iter_blocks++;
+                S.max_iter = std::max({S.max_iter, pk.blk_it[2 * (size_t)b], pk.blk_it[2 * (size_t)b + 1]});
+            }
         S.n_vio = n_vio;
         S.n_unr = n_unr;
         S.f_vio = E ? (double)n_vio / (double)E : 0.0;
         S.f_cyc = (double)n_cyc / (double)N;
         S.f_unr = (double)n_unr / (double)N;
         S.state_bytes = (int64_t)(pk.fmeta.size() + pk.rmeta.size()) * 8 +
-                        (int64_t)(pk.fwts.size() + pk.rwts.size() + 2 * pk.inv.size() + pk.cal_nat.size()) * 8;
+                        (int64_t)(pk.fwts.size() + pk.rwts.size() + 2 * pk.inv.size() + pk.cal_nat.size()) * 8 +
+                        (int64_t)(pk.sp_col.size() + pk.spt_col.size()) * 12 +
+                        (int64_t)(pk.sp_ptr.size() + pk.spt_ptr.size()) * 4;
         S.n_seed = (int32_t)pk.seed_node.size();
         S.n_direct = 0;
         for (size_t r = 0; r + 1 < pk.d_ptr.size(); r++) S.n_direct += pk.d_ptr[r + 1] > pk.d_ptr[r];

@@ -341,6 +341,7 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
     const int lr = lane & 15, lk = lane >> 4;
     for (int bi = d.b0; bi < d.b1; ++bi) {
         const int blk = DIR == kFwd ? gld(sd.fblk_id + (bi)) : gld(sd.rblk_id + (bi));
+        if (gld(sd.blk_it + 2 * blk)) continue;   // solved iteratively
         const int k = gld(sd.blk_k + (blk));
         const int bp = DIR == kFwd ? gld(sd.blk_fpos + (blk)) : gld(sd.blk_rpos + (blk));
         const int64_t moff = gld(sd.blk_moff + (blk));
@@ -393,6 +394,76 @@ __device__ __forceinline__ void split_block_solve_mfma(const SrcDev& sd, const L
     }
 }
 
+// Blocks solved iteratively (large SCCs; Section 6 names iterative block
+// solvers for them): with rho(W_CC) < 1 (Theorem 1) the block solution is the
+// Neumann series x = sum_j W_CC^j b, summed as x^0 = b, x^j = b + W_CC x^{j-1}
+// for j = 1..m (transpose: W_CC^T), m fixed at setup so that the tail is
+// below FP64 rounding.  The iterates live in FP64 in the two staging buffers
+// after b (k rows each), the last one goes straight to the node rows.  The
+// P workgroups split the block's rows; all of them pass the m - 1 barriers
+// between iterates, which invalidate the L1 (the two buffers are rewritten
+// every other iterate).  Each row sums its couplings in one fixed order, so
+// every schedule gives the same bits.
+template <int DIR, typename V, int B, int NT>
+__device__ __forceinline__ void split_block_iterate(const SrcDev& sd, const LevelDesc& d,
+                                                    const uint64_t* __restrict__ meta, const V* __restrict__ wts,
+                                                    double* __restrict__ stage, int SB, V* __restrict__ X, int XB,
+                                                    V* __restrict__ outp, int P, int part, GroupSync& g) {
+    constexpr int H = B / 2;   // pairs of right-hand sides per row
+    for (int bi = d.b0; bi < d.b1; ++bi) {
+        const int blk = DIR == kFwd ? gld(sd.fblk_id + (bi)) : gld(sd.rblk_id + (bi));
+        const int m = gld(sd.blk_it + 2 * blk + (DIR == kFwd ? 0 : 1));
+        if (!m) continue;
+        const int k = gld(sd.blk_k + (blk));
+        const int bp = DIR == kFwd ? gld(sd.blk_fpos + (blk)) : gld(sd.blk_rpos + (blk));
+        const int64_t moff = gld(sd.blk_moff + (blk));
+        const int64_t sp = gld(sd.blk_sp + (blk));
+        const int32_t* __restrict__ rp = (DIR == kFwd ? sd.sp_ptr : sd.spt_ptr) + sp;
+        const int32_t* __restrict__ cl = DIR == kFwd ? sd.sp_col : sd.spt_col;
+        const double* __restrict__ wv = DIR == kFwd ? sd.sp_w : sd.spt_w;
+        double* __restrict__ b0 = stage + moff * SB;
+        double* __restrict__ buf[2] = {b0 + (int64_t)k * SB, b0 + (int64_t)2 * k * SB};
+        int lo, hi;
+        share(k, P, part, lo, hi);
+        const int items = (hi - lo) * H;
+        for (int j = 1; j <= m; ++j) {
+            const double* __restrict__ cur = j == 1 ? b0 : buf[(j - 1) & 1];
+            double* __restrict__ nxt = buf[j & 1];
+            for (int t = (int)threadIdx.x; t < items; t += NT) {
+                const int i = lo + t / H;
+                const int c = 2 * (t % H);
+                double a0 = gld(b0 + (int64_t)i * SB + c), a1 = gld(b0 + (int64_t)i * SB + c + 1);
+                const int e1 = gld(rp + i + 1);
+                for (int e = gld(rp + i); e < e1; ++e) {
+                    const int64_t r = (int64_t)gld(cl + e) * SB + c;
+                    const double w = gld(wv + e);
+                    a0 += w * gld(cur + r);
+                    a1 += w * gld(cur + r + 1);
+                }
+                if (j < m) {
+                    nxt[(int64_t)i * SB + c] = a0;
+                    nxt[(int64_t)i * SB + c + 1] = a1;
+                } else {
+                    const int64_t node = (int64_t)(gld(meta + bp + i) & kNodeMask);
+                    X[node * XB + c] = (V)a0;
+                    X[node * XB + c + 1] = (V)a1;
+                    if (DIR == kRev && outp) {
+                        const V cc = gld(wts + (size_t)(bp + i) * 4);
+                        outp[node * B + c] = cc * (V)a0;
+                        outp[node * B + c + 1] = cc * (V)a1;
+                    }
+                }
+            }
+            if (j < m) {
+                const bool keep = g.inv_l1;
+                g.inv_l1 = true;
+                group_barrier(g, P);
+                g.inv_l1 = keep;
+            }
+        }
+    }
+}
+
 template <int DIR, typename V, int B, int NT>
 __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
                                                   const V* __restrict__ wts, const double* __restrict__ stage, int SB,
@@ -402,6 +473,7 @@ __device__ __forceinline__ void split_block_solve(const SrcDev& sd, const LevelD
     constexpr int CH = 8;    // staged values per thread and round
     for (int bi = d.b0; bi < d.b1; ++bi) {
         const int blk = DIR == kFwd ? gld(sd.fblk_id + (bi)) : gld(sd.rblk_id + (bi));
+        if (gld(sd.blk_it + 2 * blk)) continue;   // solved iteratively
         const int k = gld(sd.blk_k + (blk));
         const int bp = DIR == kFwd ? gld(sd.blk_fpos + (blk)) : gld(sd.blk_rpos + (blk));
         const int64_t moff = gld(sd.blk_moff + (blk));
@@ -707,6 +779,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 else
                     split_block_solve<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, SB, X, a.xB, outp, P, part,
                                                      s.lds_rows, lds + s.stage_off);
+                split_block_iterate<DIR, V, B, NT>(sd, cC.d, meta, wts, stage, SB, X, a.xB, outp, P, part, g);
                 if (more) fetch_batch(cN, mN);
                 group_barrier(g, P);
             }

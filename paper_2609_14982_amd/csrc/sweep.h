@@ -161,6 +161,51 @@ __device__ __forceinline__ void block_solve(const SrcDev& sd, int blk, const uin
         for (int v = 0; v < VW; ++v) lds[mi * RG + sub * VW + v] = acc[v];
     }
     __syncthreads();
+    const int m_it = sd.blk_it[2 * blk + (DIR == kFwd ? 0 : 1)];
+    if (m_it) {
+        // a large block solved by its Neumann series (as in the node split):
+        // x^0 = b, x^j = b + W_CC x^{j-1} (transpose: W_CC^T), j = 1..m, the
+        // iterates in two more LDS buffers of k x RG values, the last one
+        // straight to the node rows
+        const int64_t sp = sd.blk_sp[blk];
+        const int32_t* __restrict__ rp = (DIR == kFwd ? sd.sp_ptr : sd.spt_ptr) + sp;
+        const int32_t* __restrict__ cl = DIR == kFwd ? sd.sp_col : sd.spt_col;
+        const double* __restrict__ wv = DIR == kFwd ? sd.sp_w : sd.spt_w;
+        double* buf[2] = {lds + (size_t)k * RG, lds + (size_t)2 * k * RG};
+        const int g0 = cx.rhs0 - sub * VW;
+        for (int j = 1; j <= m_it; ++j) {
+            const double* cur = j == 1 ? lds : buf[(j - 1) & 1];
+            double* nxt = buf[j & 1];
+            for (int i = threadIdx.x; i < k; i += NT) {
+                double acc[RG];
+#pragma unroll
+                for (int rr = 0; rr < RG; ++rr) acc[rr] = lds[i * RG + rr];
+                for (int e = rp[i]; e < rp[i + 1]; ++e) {
+                    const double w = wv[e];
+                    const double* src = cur + (size_t)cl[e] * RG;
+#pragma unroll
+                    for (int rr = 0; rr < RG; ++rr) acc[rr] += w * src[rr];
+                }
+                if (j < m_it) {
+#pragma unroll
+                    for (int rr = 0; rr < RG; ++rr) nxt[i * RG + rr] = acc[rr];
+                } else {
+                    const int64_t node = (int64_t)(meta[bp + i] & kNodeMask);
+                    const V c = wts[(size_t)(bp + i) * 4];
+                    V* dst = X + node * cx.B + g0;
+#pragma unroll
+                    for (int rr = 0; rr < RG; ++rr) dst[rr] = (V)acc[rr];
+                    if (DIR == kRev && outp) {
+                        V* o = outp + node * cx.B + g0;
+#pragma unroll
+                        for (int rr = 0; rr < RG; ++rr) o[rr] = c * (V)acc[rr];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
     // phase 2: thread t owns outputs t, t + NT, ... and all RG right-hand
     // sides of each, so consecutive lanes read consecutive matrix entries:
     // primal x_i = sum_j Minv(i, j) b_j reads the column-major inverse,
