@@ -438,6 +438,44 @@ int fm_cgls_buffers(const fm_cgls* C, void** x, void** r, double** scalars, doub
 void fm_cgls_free(fm_cgls* C);
 
 /*
+ * First-arrival traveltimes on the GPU (the state of Section 2.1: T the
+ * viscosity solution of |grad_x T| = s, T = 0 at the source; Algorithm 1,
+ * Phase I).  The paper only cites its own solver; the library's
+ * discretisation is a monotone semi-Lagrangian update on the
+ * boundary-conforming grid: node i takes the least value of
+ * T(y) + s_i |x_i - y| over the points y of its stencil's simplices (face
+ * neighbours, segments joining neighbours on two different axes, and in 3-D
+ * triangles with one neighbour per axis), T linear over each simplex, x the
+ * physical positions.  Seeds: nodes within max-norm logical distance
+ * seed_radius of the source's logical coordinates keep the straight-ray time
+ * (s_src + s_p)/2 |x_p - x_src| (s_src, x_src multilinear over the source's
+ * cell; a source on a node is integer coordinates, T = 0 there).  The update
+ * is monotone, so every iteration order reaches the same largest fixed point
+ * from T = +inf; the solver runs Jacobi iterations (a node is recomputed only
+ * when a neighbour changed) until one changes nothing.
+ *
+ * fm_eikonal_create: X host [N][dim] physical node coordinates (copied);
+ *   room for up to max_sources sources per solve (device scratch of
+ *   max_sources x N x 10 bytes); work is enqueued on hip_stream (NULL: the
+ *   null stream).
+ * fm_eikonal_solve: s device [N] slowness (finite, > 0), xi_src host [S][dim]
+ *   logical source coordinates in [0, n_d - 1], seed_radius >= 0 logical
+ *   units (the region must hold a node), T device [S][N] output, 8-byte
+ *   aligned; iterations (may be NULL) receives the number of Jacobi
+ *   iterations, the last one changing nothing.  Synchronises the stream.
+ *   Errors: FM_EINVAL for bad arguments, FM_ESTATE when no fixed point is
+ *   reached within max_iter iterations (T then holds the last iterate) or the
+ *   solver lives on another device, FM_EHIP for a failed HIP call.
+ */
+typedef struct fm_eikonal fm_eikonal;
+int fm_eikonal_create(int32_t dim, int64_t n1, int64_t n2, int64_t n3, const double* X, int32_t max_sources,
+                      void* hip_stream, fm_eikonal** out);
+int fm_eikonal_set_stream(fm_eikonal* e, void* hip_stream);
+int fm_eikonal_solve(fm_eikonal* e, const double* s, int32_t S, const double* xi_src, double seed_radius,
+                     int32_t max_iter, double* T, int32_t* iterations);
+void fm_eikonal_free(fm_eikonal* e);
+
+/*
  * Cell-velocity model map M_alpha (Section 4.4, eq. (source-jacobian)): the
  * model is one velocity per cell of the logical grid (hexahedra between
  * nodes, quadrilaterals in 2-D; cell id ci + (n1-1) (cj + (n2-1) ck), 2-D

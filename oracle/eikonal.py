@@ -169,8 +169,26 @@ def solve(dim, n1, n2, n3, X, s, src, radius=2, order="jacobi", max_iter=100000)
     N = n1 * n2 * n3
     X = np.asarray(X, dtype=np.float64).reshape(N, dim)
     s = np.asarray(s, dtype=np.float64)
-    nb = neighbours(dim, n1, n2, n3)
     sn, st = seeds(dim, n1, n2, n3, X, s, src, radius)
+    return solve_seeded(dim, n1, n2, n3, X, s, sn, st, order, max_iter)
+
+
+def solve_point(dim, n1, n2, n3, X, s, xi, rho, order="jacobi", max_iter=100000):
+    """The same for a source at logical coordinates xi with a seed region of
+    max-norm radius rho (the seeds of oracle.source: straight-ray times with
+    s_src, x_src multilinear over xi's cell)."""
+    from .source import seed_traveltime
+    N = n1 * n2 * n3
+    X = np.asarray(X, dtype=np.float64).reshape(N, dim)
+    s = np.asarray(s, dtype=np.float64)
+    sn, st, _, _ = seed_traveltime(dim, n1, n2, n3, X, s, np.asarray(xi, dtype=np.float64), rho)
+    return solve_seeded(dim, n1, n2, n3, X, s, sn, st, order, max_iter)
+
+
+def solve_seeded(dim, n1, n2, n3, X, s, sn, st, order="jacobi", max_iter=100000):
+    """Iterate from T = st on the seed nodes sn and +inf elsewhere."""
+    N = n1 * n2 * n3
+    nb = neighbours(dim, n1, n2, n3)
     T = np.full(N, np.inf)
     T[sn] = st
     free = np.ones(N, bool)

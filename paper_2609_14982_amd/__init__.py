@@ -19,6 +19,7 @@ from .binding import (  # noqa: F401
     FM_W_RECEIVERS,
     Batch,
     Cgls,
+    Eikonal,
     apply_J_static,
     autotune,
     FmError,

@@ -32,6 +32,7 @@ SYMBOLS = (
     "fm_lsqr_buffers", "fm_lsqr_free", "fm_autotune",
     "fm_cgls_create", "fm_cgls_start", "fm_cgls_iterate", "fm_cgls_capture", "fm_cgls_replay",
     "fm_cgls_buffers", "fm_cgls_free",
+    "fm_eikonal_create", "fm_eikonal_set_stream", "fm_eikonal_solve", "fm_eikonal_free",
     "fm_model_map_create", "fm_model_map_sizes", "fm_model_map_slowness", "fm_model_map_set_stream",
     "fm_model_map_apply", "fm_model_map_apply_T", "fm_model_map_free",
 )
@@ -91,6 +92,10 @@ def load():
         "fm_build_frozen_state_pt": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, vp, vp, i32, i32, vp]),
         "fm_build_frozen_states_pt": (C.c_int, [vp, vp, i32, vp, vp, vp, C.c_double, vp, vp, i32, i32, i32, vp]),
         "fm_set_iterative_block_min": (C.c_int, [i32]),
+        "fm_eikonal_create": (C.c_int, [i32, i64, i64, i64, vp, i32, vp, vp]),
+        "fm_eikonal_set_stream": (C.c_int, [vp, vp]),
+        "fm_eikonal_solve": (C.c_int, [vp, vp, i32, vp, C.c_double, i32, vp, vp]),
+        "fm_eikonal_free": (None, [vp]),
         "fm_state_stats": (C.c_int, [vp, vp]),
         "fm_state_export_operator": (C.c_int, [vp, vp, vp, vp, vp]),
         "fm_state_export_graph": (C.c_int, [vp, vp, vp, vp]),
@@ -559,6 +564,48 @@ class ModelMap:
     def free(self):
         if self._ptr and self._ptr.value:
             load().fm_model_map_free(self._ptr)
+            self._ptr = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Eikonal:
+    """fm_eikonal*: first-arrival traveltimes for many sources on the GPU
+    (the monotone semi-Lagrangian update; Section 2.1's state)."""
+
+    def __init__(self, dim, n1, n2, n3, X, max_sources, stream=None):
+        import torch
+        lib = load()
+        X = _f64(X)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self._stream = stream
+        out = C.c_void_p()
+        _check(lib.fm_eikonal_create(int(dim), int(n1), int(n2), int(n3), X.ctypes.data, int(max_sources),
+                                     C.c_void_p(stream.cuda_stream), C.byref(out)))
+        self._ptr = out
+        self.dim, self.N, self.max_sources = int(dim), int(n1) * int(n2) * int(n3), int(max_sources)
+
+    def solve(self, s, xi_src, seed_radius, out, max_iter=100000):
+        """out [S][N] (device FP64) <- traveltimes for slowness s [N] (device
+        FP64) and sources at logical coordinates xi_src [S][dim] (host);
+        returns the number of Jacobi iterations."""
+        import torch
+        xi = np.ascontiguousarray(np.asarray(xi_src, dtype=np.float64).reshape(-1, self.dim))
+        S = int(xi.shape[0])
+        it = C.c_int32()
+        _check(load().fm_eikonal_solve(self._ptr, _dptr(s, torch.float64, (self.N,), "s"), S, xi.ctypes.data,
+                                       float(seed_radius), int(max_iter),
+                                       _dptr(out, torch.float64, (S, self.N), "T"), C.byref(it)))
+        return int(it.value)
+
+    def free(self):
+        if self._ptr and self._ptr.value:
+            load().fm_eikonal_free(self._ptr)
             self._ptr = C.c_void_p(None)
 
     def __del__(self):

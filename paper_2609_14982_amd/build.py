@@ -24,6 +24,10 @@ HIP_FLAGS = [
 # -ffp-contract=off keeps the setup's FP64 upwind decisions free of fused
 # multiply-adds, so they are reproducible bit for bit
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function"]
+HIP_SOURCES = ("device.hip", "krylov.hip", "model_map.hip", "eikonal.hip")
+# the first-arrival update rounds every product and sum as written (its
+# fixed point is compared with a NumPy evaluation of the same formulas)
+HIP_EXTRA = {"eikonal.hip": ["-ffp-contract=off"]}
 
 
 def _run(cmd, verbose):
@@ -42,7 +46,8 @@ def build_sanitize(verbose: bool = False) -> str:
     and undefined-behaviour sanitizers, linked with the kernels of an
     ordinary build, for host-side checks on the CPU: load it with the
     sanitizer runtimes preloaded and FMBTF_LIB pointing at it."""
-    if not all(os.path.exists(os.path.join(BUILD, o)) for o in ("device.o", "krylov.o", "model_map.o")):
+    hip_objs = [src.replace(".hip", ".o") for src in HIP_SOURCES]
+    if not all(os.path.exists(os.path.join(BUILD, o)) for o in hip_objs):
         build(verbose)
     out_dir = os.path.dirname(LIB_SANITIZE)
     os.makedirs(out_dir, exist_ok=True)
@@ -52,7 +57,7 @@ def build_sanitize(verbose: bool = False) -> str:
         _run(["g++", *HOST_FLAGS, *SANITIZE_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o",
               obj], verbose)
         objs.append(obj)
-    objs += [os.path.join(BUILD, o) for o in ("device.o", "krylov.o", "model_map.o")]
+    objs += [os.path.join(BUILD, o) for o in hip_objs]
     gcc_lib = subprocess.check_output(["gcc", "-print-file-name=libasan.so"], text=True).strip()
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB_SANITIZE, *objs, "-pthread",
           "-L", os.path.dirname(gcc_lib), "-lasan", "-lubsan"], verbose)
@@ -67,10 +72,10 @@ def build(verbose: bool = False) -> str:
         _run(["g++", *HOST_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj],
              verbose)
         objs.append(obj)
-    for src in ("device.hip", "krylov.hip", "model_map.hip"):
+    for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        _run([HIPCC, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj],
-             verbose)
+        _run([HIPCC, *HIP_FLAGS, *HIP_EXTRA.get(src, []), "-I", INCLUDE, "-I", CSRC, "-c",
+              os.path.join(CSRC, src), "-o", obj], verbose)
         objs.append(obj)
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-pthread"], verbose)
