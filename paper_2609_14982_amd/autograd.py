@@ -3,7 +3,8 @@
 ReceiverTraveltime is a torch.autograd.Function for the map
     s (nodal slowness [N])  ->  receiver traveltimes [S][R]
 whose forward pass runs a caller-supplied nonlinear first-arrival solver
-(s -> T[S][N], the state of Section 2.1) and builds the frozen states
+(s -> T[S][N], the state of Section 2.1; GpuTraveltimeSolver runs the
+library's GPU solver) and builds the frozen states
 (Algorithm 1, Phase I), and whose backward pass applies the source-summed
 transpose J^T = sum_alpha C_alpha A_alpha^{-T} P_alpha^T (Section 4.4) on the
 GPU.  The tangent is the frozen face-upwind transport with the calibrated
@@ -23,7 +24,35 @@ import numpy as np
 import torch
 
 from .binding import (FM_DS_BROADCAST, FM_FP64, FM_JT_SUMMED, FM_OUT_RECEIVERS, FM_W_RECEIVERS, Batch, Cgls,
-                      build_frozen_states)
+                      Eikonal, build_frozen_states)
+
+
+class GpuTraveltimeSolver:
+    """The nonlinear state on the GPU (fm_eikonal_*): a callable s [N] (host)
+    -> T [S][N] (host) for sources on the given nodes, with seed regions of
+    max-norm radius seed_radius (Algorithm 1, Phase I; Section 2.1)."""
+
+    def __init__(self, dim, n1, n2, n3, X, src, seed_radius=2.0):
+        self.dim, self.N = dim, n1 * n2 * n3
+        axes = (n1, n2, n3) if dim == 3 else (n1, n3)
+        src = np.asarray(src, dtype=np.int64)
+        # logical coordinates of the source nodes (axis 0 fastest)
+        xi = np.empty((src.size, dim))
+        r = src.copy()
+        for d in range(dim):
+            xi[:, d] = r % axes[d]
+            r = r // axes[d]
+        self.xi = xi
+        self.seed_radius = float(seed_radius)
+        self.iterations = 0
+        self._solver = Eikonal(dim, n1, n2, n3, X, src.size)
+
+    def __call__(self, s: np.ndarray) -> np.ndarray:
+        dev = torch.device("cuda")
+        T = torch.empty((self.xi.shape[0], self.N), dtype=torch.float64, device=dev)
+        self.iterations = self._solver.solve(torch.from_numpy(np.ascontiguousarray(s, dtype=np.float64)).to(dev),
+                                             self.xi, self.seed_radius, T)
+        return T.cpu().numpy()
 
 
 class TransportProblem:
