@@ -94,6 +94,82 @@ def measured_traffic(kernel, config, precision):
     return doc["per_launch"]["J"]["hbm_bytes"]
 
 
+def _csv_rows(root, suffix):
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(root, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def _per_dispatch(root, counter):
+    """{kernel name: [value per dispatch]} from a rocprofv3 --pmc run."""
+    per = {}
+    for r in _csv_rows(root, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (r["Kernel_Name"], r.get("Dispatch_Id", r.get("Correlation_Id")))
+        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for (name, _), v in per.items():
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def write_traffic(root, config, precision):
+    """Fabric bytes per launch of the sweep kernels from four rocprofv3 --pmc
+    runs (FETCH_SIZE and WRITE_SIZE of the benchmark and of a plain device
+    copy of known size, KiB per dispatch), scaled so that the copy reads and
+    writes what it moves; plus the trace's average durations."""
+    import hashlib
+    fetch = _per_dispatch(os.path.join(root, "fetch"), "FETCH_SIZE")
+    write = _per_dispatch(os.path.join(root, "write"), "WRITE_SIZE")
+    cf = _per_dispatch(os.path.join(root, "cfetch"), "FETCH_SIZE")
+    cw = _per_dispatch(os.path.join(root, "cwrite"), "WRITE_SIZE")
+    copy_bytes = (1 << 29) * 8
+    ck = max(cf, key=lambda k: np.mean(cf[k]))
+    cfk, cwk = float(np.mean(cf[ck])), float(np.mean(cw[max(cw, key=lambda k: np.mean(cw[k]))]))
+    fscale, wscale = copy_bytes / (cfk * 1024), copy_bytes / (cwk * 1024)
+
+    def pick(table, pattern):
+        names = [k for k in table if pattern in k]
+        if not names:
+            return None, []
+        name = max(names, key=lambda k: len(table[k]))
+        return name, table[name]
+
+    vt = "double" if precision == "fp64" else "float"
+    per_launch = {}
+    for label, pattern in (("J", f"k_split<0, {vt}"), ("JT", f"k_split<1, {vt}"), ("source_sum", f"k_sum_sources<{vt}")):
+        name, fv = pick(fetch, pattern)
+        _, wv = pick(write, pattern)
+        if name is None or not wv:
+            continue
+        fk, wk = float(np.mean(fv)), float(np.mean(wv))
+        per_launch[label] = {"kernel": name, "dispatches": len(fv), "fetch_kib": fk, "write_kib": wk,
+                             "hbm_bytes": int(round(fk * 1024 * fscale + wk * 1024 * wscale))}
+    stats = {}
+    for r in _csv_rows(os.path.join(root, "trace"), "kernel_stats.csv"):
+        if "k_split" in r["Name"] or "k_sum_sources" in r["Name"]:
+            stats[r["Name"]] = {"calls": int(r["Calls"]), "avg_ns": float(r["AverageNs"])}
+    h = hashlib.sha256()
+    for src in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    doc = {"workload": f"{config}: {precision}, the benchmark's default batch", "kernel_sources": list(KERNEL_SOURCES),
+           "kernel_source_sha256": h.hexdigest(),
+           "copy_calibration": {"bytes_read": copy_bytes, "bytes_written": copy_bytes, "copy_kernel": ck,
+                                "fetch_kib_per_dispatch": cfk, "write_kib_per_dispatch": cwk,
+                                "fetch_scale": fscale, "write_scale": wscale},
+           "per_launch": per_launch, "kernel_stats_ns": stats}
+    path = os.path.join(ROOT, "profiles", f"traffic_k_split_{config}_{precision}.json")
+    with open(path, "w") as f:
+        json.dump(doc, f, indent=1)
+    print(json.dumps({"written": path, "per_launch": per_launch}))
+
+
 def cpu_baseline(wl, n_src, B, seed):
     """The CPU oracle (explicit assembly + Gauss-Seidel directional sweeping to
     convergence, plain C, OpenMP over right-hand sides) on a bounded sample."""
@@ -174,7 +250,14 @@ def main():
                     help="only run a plain device copy of a known size (HBM counter calibration)")
     ap.add_argument("--level-histogram", action="store_true",
                     help="only build the states and print the level structure per source (no GPU)")
+    ap.add_argument("--write-traffic", metavar="DIR",
+                    help="only read the rocprofv3 outputs under DIR (fetch/, write/, cfetch/, cwrite/, trace/) "
+                         "and write profiles/traffic_k_split_<config>_<precision>.json (no GPU)")
     args = ap.parse_args()
+
+    if args.write_traffic:
+        write_traffic(args.write_traffic, args.config, args.precision)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; a run on several GPUs is not part of it "

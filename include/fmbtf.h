@@ -223,6 +223,29 @@ int fm_build_frozen_states_pt(const fm_grid* g, const double* X, int32_t S, cons
  */
 int fm_set_iterative_block_min(int32_t k_min);
 
+/*
+ * The GPU setup pass (Algorithm 1, Phase I): the same states as
+ * fm_build_frozen_states_w for sources on nodes, with the couplings of every
+ * source (face coefficients, upwind weights, identity rows, calibration,
+ * Sections 3.1-3.2, and the violating-edge count of eq. (graph-fractions))
+ * computed on the device from traveltimes already there, for all sources at
+ * once, bit-identical to the host's; host threads then find the SCCs and
+ * levels, factor the blocks and pack each state, overlapping the device work
+ * of the next sources.
+ *   T        device [S][N] traveltimes (8-byte aligned), e.g. fm_eikonal_solve's output
+ *   s        host [N]; G in g on the host; src_nodes host [S]
+ *   receivers as fm_build_frozen_states_w (host, [S][n_rcv][k_per_rcv], weights may be NULL)
+ *   nthreads host threads; hip_stream the stream of the device work (NULL: null stream)
+ * Device scratch of about min(S, nthreads) x N x 57 bytes (at most ~2 GB) is
+ * allocated and freed inside the call.  Errors: as fm_build_frozen_states_w
+ * (a T that is not finite or not 0 at the source gives FM_EINVAL); FM_EHIP for
+ * a failed HIP call.
+ */
+int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const double* T, const double* s,
+                               const int64_t* src_nodes, const int64_t* rcv_nodes, const double* rcv_weights,
+                               int32_t n_rcv, int32_t k_per_rcv, int32_t nthreads, void* hip_stream,
+                               fm_state** out);
+
 /* Structural statistics of a state (Section 5.2, eq. (graph-fractions)). */
 int fm_state_stats(const fm_state* st, fm_stats* out);
 

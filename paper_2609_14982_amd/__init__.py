@@ -28,6 +28,7 @@ from .binding import (  # noqa: F401
     State,
     build_frozen_state,
     build_frozen_states,
+    build_frozen_states_gpu,
     build_frozen_states_pt,
     set_iterative_block_min,
     exported_symbols,

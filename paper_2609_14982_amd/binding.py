@@ -23,7 +23,8 @@ _ERRNAMES = {FM_EINVAL: "FM_EINVAL", FM_ESINGULAR: "FM_ESINGULAR", FM_ENOMEM: "F
 
 SYMBOLS = (
     "fm_build_frozen_state", "fm_build_frozen_states", "fm_build_frozen_state_w", "fm_build_frozen_states_w",
-    "fm_build_frozen_state_pt", "fm_build_frozen_states_pt", "fm_set_iterative_block_min", "fm_state_stats",
+    "fm_build_frozen_state_pt", "fm_build_frozen_states_pt", "fm_build_frozen_states_gpu",
+    "fm_set_iterative_block_min", "fm_state_stats",
     "fm_state_export_operator", "fm_state_export_graph", "fm_state_free",
     "fm_batch_create", "fm_batch_set_stream", "fm_batch_tuning", "fm_batch_status", "fm_batch_split_info",
     "fm_apply_J", "fm_apply_J_static",
@@ -92,6 +93,7 @@ def load():
         "fm_build_frozen_state_pt": (C.c_int, [vp, vp, vp, vp, vp, C.c_double, vp, vp, i32, i32, vp]),
         "fm_build_frozen_states_pt": (C.c_int, [vp, vp, i32, vp, vp, vp, C.c_double, vp, vp, i32, i32, i32, vp]),
         "fm_set_iterative_block_min": (C.c_int, [i32]),
+        "fm_build_frozen_states_gpu": (C.c_int, [vp, i32, vp, vp, vp, vp, vp, i32, i32, i32, vp, vp]),
         "fm_eikonal_create": (C.c_int, [i32, i64, i64, i64, vp, i32, vp, vp]),
         "fm_eikonal_set_stream": (C.c_int, [vp, vp]),
         "fm_eikonal_solve": (C.c_int, [vp, vp, i32, vp, C.c_double, i32, vp, vp]),
@@ -285,6 +287,31 @@ def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nth
                                       rcv.ctypes.data if rcv.size else None, int(rcv.shape[1]),
                                       int(nthreads), outs))
     return [State(outs[a], N, dim, (n1, n2, n3), int(rcv.shape[1])) for a in range(S)]
+
+
+def build_frozen_states_gpu(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, rcv_weights=None, nthreads=None,
+                            stream=None):
+    """fm_build_frozen_states_gpu: T a device FP64 tensor [S][N] (the GPU setup
+    pass computes the couplings); receivers as build_frozen_states."""
+    import torch
+    lib = load()
+    G, s = _f64(G), _f64(s)
+    src = _i64(src_nodes)
+    S = int(src.shape[0])
+    N = int(n1) * int(n2) * int(n3)
+    if nthreads is None:
+        nthreads = min(16, os.cpu_count() or 1)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    g = _grid(dim, n1, n2, n3, G)
+    outs = (C.c_void_p * S)()
+    rcv, w = _receivers_pt(rcv_nodes, rcv_weights, S)
+    R, K = int(rcv.shape[1]), int(rcv.shape[2])
+    _check(lib.fm_build_frozen_states_gpu(C.byref(g), S, _dptr(T, torch.float64, (S, N), "T"), s.ctypes.data,
+                                          src.ctypes.data, rcv.ctypes.data if rcv.size else None,
+                                          w.ctypes.data if w is not None and w.size else None, R, K, int(nthreads),
+                                          C.c_void_p(stream.cuda_stream), outs))
+    return [State(outs[a], N, dim, (n1, n2, n3), R) for a in range(S)]
 
 
 def set_iterative_block_min(k_min):

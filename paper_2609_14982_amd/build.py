@@ -24,10 +24,11 @@ HIP_FLAGS = [
 # -ffp-contract=off keeps the setup's FP64 upwind decisions free of fused
 # multiply-adds, so they are reproducible bit for bit
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function"]
-HIP_SOURCES = ("device.hip", "krylov.hip", "model_map.hip", "eikonal.hip")
-# the first-arrival update rounds every product and sum as written (its
-# fixed point is compared with a NumPy evaluation of the same formulas)
-HIP_EXTRA = {"eikonal.hip": ["-ffp-contract=off"]}
+HIP_SOURCES = ("device.hip", "krylov.hip", "model_map.hip", "eikonal.hip", "setup_gpu.hip")
+# the first-arrival update and the GPU setup pass round every product and
+# sum as written (compared with a NumPy evaluation of the same formulas, and
+# with the host setup bit for bit)
+HIP_EXTRA = {"eikonal.hip": ["-ffp-contract=off"], "setup_gpu.hip": ["-ffp-contract=off"]}
 
 
 def _run(cmd, verbose):

@@ -113,6 +113,16 @@ struct PointSource {
     double rho;
 };
 
+// Couplings computed elsewhere (the GPU setup pass) for an on-grid source:
+// pmask [N], w6 [N][6], cal [N] exactly as parts 1-2 of build_state write
+// them, and the count of violating edges (T_j > T_i over the edges j -> i).
+struct Assembled {
+    const uint8_t* pmask;
+    const double* w6;
+    const double* cal;
+    int64_t n_vio;
+};
+
 struct DeviceState;   // defined in the HIP translation unit
 
 struct HostState {
@@ -149,9 +159,11 @@ namespace fm {
 // Host setup (setup.cpp).  Returns FM_OK or an FM_E* code with the message set.
 // Receiver r is sum_k rcv_w[r*K + k] x[rcv[r*K + k]] (rcv_w NULL: weights 1);
 // entries of weight 0 are dropped.
+// With pre (on-grid sources only), parts 1-2 take its couplings and T may
+// be NULL (the caller has checked it).
 int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 const int64_t* rcv, const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out,
-                const PointSource* ps = nullptr);
+                const PointSource* ps = nullptr, const Assembled* pre = nullptr);
 
 // Staging rows of block b: its right-hand sides, plus two iterate buffers
 // when it is solved iteratively.

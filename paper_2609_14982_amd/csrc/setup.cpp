@@ -72,24 +72,6 @@ inline double nodal_derivative(const Grid& g, const double* T, int64_t p, int ax
     return 0.5 * (T[p + st] - T[p - st]);
 }
 
-// a_f for the face between lo and lo + e_d (Section 3.1): G_f is the mean of
-// the two nodal metrics, the normal derivative the compact difference, each
-// tangential derivative the mean of the two nodal derivatives; the sum runs
-// over d' in axis order.
-inline double face_coefficient(const Grid& g, const double* T, int64_t lo, int d) {
-    int64_t hi = lo + g.stride[d];
-    double a = 0.0;
-    for (int dp = 0; dp < g.dim; dp++) {
-        double gd;
-        if (dp == d) gd = T[hi] - T[lo];
-        else gd = 0.5 * (nodal_derivative(g, T, lo, dp) + nodal_derivative(g, T, hi, dp));
-        double Gf = 0.5 * (metric(g, lo, d, dp) + metric(g, hi, d, dp));
-        double term = Gf * gd;
-        a = (dp == 0) ? term : a + term;
-    }
-    return a;
-}
-
 inline int64_t nbr(const Grid& g, int64_t p, int slot) {
     int axis = slot >> 1;
     return (slot & 1) ? p + g.stride[axis] : p - g.stride[axis];
@@ -168,8 +150,8 @@ void lu_inverse(int k, const double* lu, const int32_t* piv, double* x) {
 }
 
 int validate(const fm_grid* g, const double* T, const double* s, int64_t src, const int64_t* rcv,
-             const double* rcv_w, int32_t n_rcv, int32_t K, Grid& gr, const PointSource* ps) {
-    if (!g || !g->G || !T || !s) { set_error("null argument"); return FM_EINVAL; }
+             const double* rcv_w, int32_t n_rcv, int32_t K, Grid& gr, const PointSource* ps, bool need_T) {
+    if (!g || !g->G || (need_T && !T) || !s) { set_error("null argument"); return FM_EINVAL; }
     if (g->dim != 2 && g->dim != 3) { set_error("dim must be 2 or 3, got %d", g->dim); return FM_EINVAL; }
     if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) { set_error("grid sizes must be >= 1"); return FM_EINVAL; }
     if (g->dim == 2 && g->n2 != 1) { set_error("2-D grids need n2 == 1"); return FM_EINVAL; }
@@ -210,7 +192,7 @@ int validate(const fm_grid* g, const double* T, const double* s, int64_t src, co
         }
     }
     for (int64_t p = 0; p < gr.N; p++) {
-        if (!std::isfinite(T[p])) { set_error("T[%lld] is not finite", (long long)p); return FM_EINVAL; }
+        if (need_T && !std::isfinite(T[p])) { set_error("T[%lld] is not finite", (long long)p); return FM_EINVAL; }
         if (!(s[p] > 0.0) || !std::isfinite(s[p])) { set_error("s[%lld] must be finite and > 0", (long long)p); return FM_EINVAL; }
         const double* m = g->G + (size_t)gr.ncomp_g * p;
         for (int c = 0; c < gr.ncomp_g; c++)
@@ -218,7 +200,7 @@ int validate(const fm_grid* g, const double* T, const double* s, int64_t src, co
         for (int c = 0; c < gr.dim; c++)
             if (!(m[c] > 0.0)) { set_error("G[%lld] has a nonpositive diagonal", (long long)p); return FM_EINVAL; }
     }
-    if (!ps && T[src] != 0.0) { set_error("T at the source node must be 0, got %g", T[src]); return FM_EINVAL; }
+    if (need_T && !ps && T[src] != 0.0) { set_error("T at the source node must be 0, got %g", T[src]); return FM_EINVAL; }
     return FM_OK;
 }
 
@@ -250,12 +232,14 @@ void source_cell(const Grid& gr, const double* xi, int64_t corner[8], double wt[
 }  // namespace
 
 int build_state(const fm_grid* g, const double* T, const double* s, int64_t src, const int64_t* rcv,
-                const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out, const PointSource* ps) {
+                const double* rcv_w, int32_t n_rcv, int32_t K, fm_state** out, const PointSource* ps,
+                const Assembled* pre) {
     auto t0 = std::chrono::steady_clock::now();
     if (!out) { set_error("null output pointer"); return FM_EINVAL; }
     *out = nullptr;
+    if (pre && ps) { set_error("precomputed couplings take sources on a node only"); return FM_EINVAL; }
     Grid gr;
-    int rc = validate(g, T, s, src, rcv, rcv_w, n_rcv, K, gr, ps);
+    int rc = validate(g, T, s, src, rcv, rcv_w, n_rcv, K, gr, ps, pre == nullptr);
     if (rc != FM_OK) return rc;
     fm_state* st = new (std::nothrow) fm_state();
     if (!st) { set_error("out of host memory"); return FM_ENOMEM; }
@@ -319,16 +303,49 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         st->cal.assign(N, 0.0);
         const int nslot = 2 * gr.dim;
         int64_t E = 0;
-        for (int64_t p = 0; p < N; p++) {
+        if (pre) {
+            std::copy(pre->pmask, pre->pmask + N, st->pmask.begin());
+            std::copy(pre->w6, pre->w6 + (size_t)N * 6, st->w6.begin());
+            std::copy(pre->cal, pre->cal + N, st->cal.begin());
+            for (int64_t p = 0; p < N; p++) E += __builtin_popcount(st->pmask[p]);
+        }
+        // a_f of every face once (Section 3.1): G_f is the mean of the two
+        // nodal metrics, the normal derivative the compact difference, each
+        // tangential derivative the mean of the two nodal derivatives
+        // (computed once per node); the sum runs over d' in axis order.
+        // af[p][d] belongs to the face between p and p + e_d.
+        std::vector<double> af;
+        if (!pre) {
+            std::vector<double> nd((size_t)N * gr.dim);
+            for (int64_t p = 0; p < N; p++)
+                for (int d = 0; d < gr.dim; d++) nd[(size_t)p * gr.dim + d] = nodal_derivative(gr, T, p, d);
+            af.assign((size_t)N * gr.dim, 0.0);
+            for (int64_t lo = 0; lo < N; lo++)
+                for (int d = 0; d < gr.dim; d++) {
+                    if (!has_nbr(gr, lo, 2 * d + 1)) continue;
+                    const int64_t hi = lo + gr.stride[d];
+                    double a = 0.0;
+                    for (int dp = 0; dp < gr.dim; dp++) {
+                        double gd;
+                        if (dp == d) gd = T[hi] - T[lo];
+                        else gd = 0.5 * (nd[(size_t)lo * gr.dim + dp] + nd[(size_t)hi * gr.dim + dp]);
+                        double Gf = 0.5 * (metric(gr, lo, d, dp) + metric(gr, hi, d, dp));
+                        double term = Gf * gd;
+                        a = (dp == 0) ? term : a + term;
+                    }
+                    af[(size_t)lo * gr.dim + d] = a;
+                }
+        }
+        for (int64_t p = 0; p < (pre ? 0 : N); p++) {
             double c6[6] = {0, 0, 0, 0, 0, 0};
             for (int slot = 0; slot < nslot; slot++) {
                 if (!has_nbr(gr, p, slot)) continue;
                 int d = slot >> 1;
                 if (slot & 1) {
-                    double a = face_coefficient(gr, T, p, d);           // plus face of p
+                    double a = af[(size_t)p * gr.dim + d];                            // plus face of p
                     c6[slot] = -a > 0.0 ? -a : 0.0;
                 } else {
-                    double a = face_coefficient(gr, T, p - gr.stride[d], d);   // minus face of p
+                    double a = af[(size_t)(p - gr.stride[d]) * gr.dim + d];           // minus face of p
                     c6[slot] = a > 0.0 ? a : 0.0;
                 }
             }
@@ -451,7 +468,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 for (int slot = 0; slot < nslot; slot++) {
                     if (!(pm & (1u << slot))) continue;
                     int32_t u = (int32_t)nbr(gr, v, slot);
-                    if (T[u] > T[v]) n_vio++;
+                    if (!pre && T[u] > T[v]) n_vio++;
                     int32_t cu = st->comp[u];
                     if (cu == c) continue;
                     lev = std::max(lev, st->clev_f[cu] + 1);
@@ -475,6 +492,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             }
             st->clev_r[c] = lev;
         }
+        if (pre) n_vio = pre->n_vio;
         int32_t L_f = 0, L_r = 0;
         for (int32_t c = 0; c < ncomp; c++) {
             L_f = std::max(L_f, st->clev_f[c] + 1);
@@ -674,64 +692,76 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             blk_pos.assign(nblk, 0);
             pos_of.assign(N, 0);
             int32_t next_tail = lvl_ptr[L];
-            // components in id order; singletons of one level then come in
-            // ascending component id; sort each level's singletons by node id
+            // blocks: in component id order inside a level, members ascending
             for (int32_t c = 0; c < ncomp; c++) {
-                int32_t k = st->cptr[c + 1] - st->cptr[c];
-                int32_t l = clev[c];
-                if (k == 1) {
-                    const int32_t v = st->cnodes[st->cptr[c]];
-                    pos_of[v] = skip(v) ? next_tail++ : next_sc[l]++;
-                } else {
-                    int32_t b = comp_blk[c];
-                    blk_id[next_b[l]++] = b;
-                    blk_pos[b] = next_bl[l];
-                    for (int32_t m = 0; m < k; m++) pos_of[st->cnodes[st->cptr[c] + m]] = next_bl[l]++;
-                }
+                const int32_t k = st->cptr[c + 1] - st->cptr[c];
+                if (k == 1) continue;
+                const int32_t l = clev[c];
+                const int32_t b = comp_blk[c];
+                blk_id[next_b[l]++] = b;
+                blk_pos[b] = next_bl[l];
+                for (int32_t m = 0; m < k; m++) pos_of[st->cnodes[st->cptr[c] + m]] = next_bl[l]++;
             }
             // each level's singleton run: nodes with at most three neighbours
             // in ascending node id, then those with more (their further
             // weights are a dependent load, on which a whole wave waits, so
-            // they are kept together in the level's last batches)
-            std::vector<int32_t> order(N);
-            for (int64_t p = 0; p < N; p++) order[pos_of[p]] = (int32_t)p;
+            // they are kept together in the level's last batches); placed by
+            // counting, walking the nodes in ascending id
             auto many = [&](int32_t v) { return __builtin_popcount(fwd ? st->pmask[v] : st->smask[v]) > 3; };
-            for (int32_t l = 0; l < L; l++) {
-                std::sort(order.begin() + lvl_ptr[l], order.begin() + lvl_ptr[l] + lvl_nsc[l],
-                          [&](int32_t a, int32_t b) {
-                              const bool ma = many(a), mb = many(b);
-                              return ma != mb ? mb : a < b;
-                          });
-                for (int32_t q = lvl_ptr[l]; q < lvl_ptr[l] + lvl_nsc[l]; q++) pos_of[order[q]] = q;
+            std::vector<int32_t> next_many(L);
+            {
+                std::vector<int32_t> n_few(L, 0);
+                for (int64_t p = 0; p < N; p++) {
+                    const int32_t c = st->comp[p];
+                    if (st->cptr[c + 1] - st->cptr[c] != 1 || skip((int32_t)p) || many((int32_t)p)) continue;
+                    n_few[clev[c]]++;
+                }
+                for (int32_t l = 0; l < L; l++) next_many[l] = lvl_ptr[l] + n_few[l];
+            }
+            for (int64_t p = 0; p < N; p++) {
+                const int32_t c = st->comp[p];
+                if (st->cptr[c + 1] - st->cptr[c] != 1) continue;
+                const int32_t v = (int32_t)p;
+                const int32_t l = clev[c];
+                pos_of[v] = skip(v) ? next_tail++ : many(v) ? next_many[l]++ : next_sc[l]++;
             }
             // records: a fixed [c, w1, w2, w3] per position, further weights of
             // the rare nodes with more than three neighbours in an overflow area
-            // after the N fixed records
+            // after the N fixed records, in position order; written walking
+            // the nodes in ascending id (the position order needs the
+            // overflow offsets first)
             meta.assign(N, 0);
             wts.assign((size_t)N * 4, 0.0);
-            std::vector<double> ovf;
-            for (int64_t q = 0; q < N; q++) {
-                int32_t v = order[q];
-                int32_t cv_ = st->comp[v];
-                uint8_t full = fwd ? st->pmask[v] : st->smask[v];
+            auto external = [&](int32_t v, int slot, int32_t cv_) {
+                const uint8_t full = fwd ? st->pmask[v] : st->smask[v];
+                if (!(full & (1u << slot))) return false;
+                return st->comp[(int32_t)nbr(gr, v, slot)] != cv_;   // not internal to the block
+            };
+            std::vector<int64_t> off_at((size_t)N + 1, 0);
+            for (int64_t p = 0; p < N; p++) {
+                const int32_t v = (int32_t)p, cv_ = st->comp[v];
+                int t = 0;
+                for (int slot = 0; slot < nslot; slot++) t += external(v, slot, cv_) ? 1 : 0;
+                off_at[(size_t)pos_of[v] + 1] = t > 3 ? t - 3 : 0;
+            }
+            for (int64_t q = 0; q < N; q++) off_at[q + 1] += off_at[q];
+            std::vector<double> ovf((size_t)off_at[N], 0.0);
+            for (int64_t p = 0; p < N; p++) {
+                const int32_t v = (int32_t)p, cv_ = st->comp[v];
+                const int64_t q = pos_of[v];
                 uint8_t mask = 0;
                 double* rec = wts.data() + (size_t)q * 4;
                 rec[0] = st->cal[v];
                 int t = 0;
-                int64_t off = 0;
+                const int64_t off = off_at[q] < off_at[q + 1] ? off_at[q] : 0;
                 for (int slot = 0; slot < nslot; slot++) {
-                    if (!(full & (1u << slot))) continue;
-                    int32_t u = (int32_t)nbr(gr, v, slot);
-                    if (st->comp[u] == cv_) continue;   // internal to the block
+                    if (!external(v, slot, cv_)) continue;
+                    const int32_t u = (int32_t)nbr(gr, v, slot);
                     mask |= (uint8_t)(1u << slot);
                     // forward: w_{v,u}; reverse: u is a successor, weight w_{u,v}
-                    double w = fwd ? st->w6[(size_t)v * 6 + slot] : st->w6[(size_t)u * 6 + (slot ^ 1)];
-                    if (t < 3) {
-                        rec[1 + t] = w;
-                    } else {
-                        if (t == 3) off = (int64_t)ovf.size();
-                        ovf.push_back(w);
-                    }
+                    const double w = fwd ? st->w6[(size_t)v * 6 + slot] : st->w6[(size_t)u * 6 + (slot ^ 1)];
+                    if (t < 3) rec[1 + t] = w;
+                    else ovf[(size_t)(off + (t - 3))] = w;
                     t++;
                 }
                 if (off > (int64_t)kOffMask) throw std::length_error("record overflow area too large");

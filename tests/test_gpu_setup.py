@@ -1,0 +1,148 @@
+"""The GPU setup pass (fm_build_frozen_states_gpu): couplings of every
+source computed on the device (Sections 3.1-3.2), the rest of Phase I on the
+host from them.
+
+* c1 (2-D), the curved fixture (six SCCs) and c3 (3-D, blocks up to 693
+  nodes): W and c bit-identical to the oracle's assembly and to the host
+  setup, the same SCC partition and identical levels in both directions,
+  identical structure statistics, and J / J^T bit-identical to the states
+  of the host setup;
+* the singular fixture gives FM_ESINGULAR; a traveltime that is not finite
+  or not 0 at the source gives FM_EINVAL;
+* c4 at full size (64 sources): identical statistics and operators on
+  sampled sources, and the setup time beside the host's.
+"""
+import os
+import time
+
+import numpy as np
+import pytest
+
+import workloads as W
+from helpers import seeded_ds, states_for
+from oracle import diag
+from oracle.assembly import assemble_workload
+
+torch = pytest.importorskip("torch")
+fm = pytest.importorskip("paper_2609_14982_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_states(wl, S=None):
+    S = wl.S if S is None else S
+    T = torch.from_numpy(np.ascontiguousarray(wl.T[:S])).to("cuda")
+    return fm.build_frozen_states_gpu(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, T, wl.s, wl.src[:S], wl.rcv,
+                                      rcv_weights=getattr(wl, "rcv_w", None), nthreads=8)
+
+
+def _same_state(a, b):
+    for x, y in zip(a.export_operator(), b.export_operator()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.export_graph(), b.export_graph()):
+        assert np.array_equal(x, y)
+    sa, sb = a.stats(), b.stats()
+    sa.pop("setup_seconds")
+    sb.pop("setup_seconds")
+    assert sa == sb, (sa, sb)
+
+
+def _check_workload(wl, S, B):
+    host = states_for(fm, wl, S)
+    gpu = _gpu_states(wl, S)
+    for a in range(S):
+        _same_state(gpu[a], host[a])
+    # the oracle's explicit W and c, bit for bit
+    for a in (0, S - 1):
+        op = assemble_workload(wl, a)
+        rowptr, col, w, c = gpu[a].export_operator()
+        Wo = op.W.tocsr()
+        Wo.sort_indices()
+        assert np.array_equal(rowptr, Wo.indptr) and np.array_equal(col, Wo.indices)
+        assert np.array_equal(w, Wo.data) and np.array_equal(c, op.c)
+        comp = gpu[a].export_graph()[0]
+        order = np.argsort(comp, kind="stable")
+        groups = np.split(order, np.nonzero(np.diff(comp[order]))[0] + 1)
+        mine = [np.sort(g) for g in groups if g.size > 1]
+        assert diag.same_partition(mine, diag.scc_summary(op.W))
+    # the applies of both sets of states give the same bits
+    dev = torch.device("cuda:0")
+    ds = torch.from_numpy(seeded_ds(wl, B, 5100, S=S)).to(dev)
+    outs = []
+    for states in (host, gpu):
+        batch = fm.Batch(states, B, fm.FM_FP64)
+        x = torch.empty((S, wl.N, B), dtype=torch.float64, device=dev)
+        g = torch.empty((wl.N, B), dtype=torch.float64, device=dev)
+        batch.apply_J(ds, fm.FM_DS_PER_PAIR, x, fm.FM_OUT_NODES)
+        batch.apply_JT(x, fm.FM_W_NODES, g, fm.FM_JT_SUMMED)
+        batch.status()
+        outs.append((x, g))
+        batch.free()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_c1_matches_host_and_oracle():
+    wl = W.config("c1")
+    print(f"case gpu setup c1 {wl.n1}x{wl.n3}, S={wl.S}", flush=True)
+    _check_workload(wl, wl.S, 4)
+
+
+def test_curved_fixture_matches_host_and_oracle():
+    wl = W.curved_state(41, 41, 25, A=500.0, eps_T=0.05)
+    wl.rcv = np.array([wl.node(i, j, 0) for j in range(0, 41, 4) for i in range(0, 41, 4)], dtype=np.int64)
+    print("case gpu setup curved 41x41x25 (6 SCCs)", flush=True)
+    _check_workload(wl, wl.S, 8)
+
+
+def test_c3_matches_host_and_oracle():
+    wl = W.config("c3")
+    print(f"case gpu setup c3 101x101x51, S={wl.S}", flush=True)
+    host = states_for(fm, wl)
+    gpu = _gpu_states(wl)
+    for a in range(wl.S):
+        _same_state(gpu[a], host[a])
+    print(f"  blocks per source {[s.stats()['n_scc'] for s in gpu]}", flush=True)
+
+
+def test_singular_block_and_bad_traveltimes():
+    G = np.tile([1.0, 1.0, 0.65], (9, 1))
+    T = np.array([0.0, 3.9, 3.4, 0.8, 0.5, 1.1, 1.8, 0.9, 0.9])
+    s = np.ones(9)
+    dev = torch.device("cuda:0")
+    with pytest.raises(fm.FmError) as ei:
+        fm.build_frozen_states_gpu(2, 3, 1, 3, G, torch.from_numpy(T[None]).to(dev), s, [0])
+    assert ei.value.code == fm.binding.FM_ESINGULAR and "4 nodes" in str(ei.value)
+    Tn = T.copy()
+    Tn[3] = np.nan
+    with pytest.raises(fm.FmError) as ei:
+        fm.build_frozen_states_gpu(2, 3, 1, 3, G, torch.from_numpy(Tn[None]).to(dev), s, [0])
+    assert ei.value.code == fm.binding.FM_EINVAL
+    with pytest.raises(fm.FmError) as ei:
+        fm.build_frozen_states_gpu(2, 3, 1, 3, G, torch.from_numpy(T[None]).to(dev), s, [1])
+    assert ei.value.code == fm.binding.FM_EINVAL
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_c4_full_size_setup_time():
+    wl = W.config("c4")
+    threads = min(16, os.cpu_count() or 1)
+    print(f"case gpu setup c4 201x201x101, S={wl.S}, {threads} host threads", flush=True)
+    T = torch.from_numpy(wl.T).to("cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gpu = fm.build_frozen_states_gpu(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, T, wl.s, wl.src, wl.rcv, nthreads=threads)
+    t_gpu = time.perf_counter() - t0
+    print(f"  GPU setup pass: {t_gpu:.2f} s", flush=True)
+    del T
+    t0 = time.perf_counter()
+    host = fm.build_frozen_states(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T, wl.s, wl.src, wl.rcv, nthreads=threads)
+    t_host = time.perf_counter() - t0
+    print(f"  host setup: {t_host:.2f} s", flush=True)
+    for a in range(wl.S):
+        sa, sb = gpu[a].stats(), host[a].stats()
+        sa.pop("setup_seconds")
+        sb.pop("setup_seconds")
+        assert sa == sb, a
+    for a in (0, 23):
+        _same_state(gpu[a], host[a])
