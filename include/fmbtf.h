@@ -93,6 +93,8 @@ typedef struct fm_stats {
     int32_t max_iter;       /* most series terms of such a block (either direction) */
     int64_t dense_k2;       /* sum of k^2 over the blocks kept as dense inverses */
     int64_t iter_nnz;       /* in-block couplings stored for the iterative blocks */
+    double block_residual;  /* max over the dense blocks of ||A_C X e_j - e_j||_inf on four columns
+                               j of the stored inverse X (0 without dense blocks) */
 } fm_stats;
 
 /* Launch schedule of a batch; zero fields take the library default. */

@@ -57,7 +57,8 @@ class fm_stats(C.Structure):
                 ("n_unr", C.c_int64), ("f_vio", C.c_double), ("f_cyc", C.c_double),
                 ("f_unr", C.c_double), ("setup_seconds", C.c_double), ("state_bytes", C.c_int64),
                 ("n_seed", C.c_int32), ("n_direct", C.c_int32), ("n_iter_blocks", C.c_int32),
-                ("max_iter", C.c_int32), ("dense_k2", C.c_int64), ("iter_nnz", C.c_int64)]
+                ("max_iter", C.c_int32), ("dense_k2", C.c_int64), ("iter_nnz", C.c_int64),
+                ("block_residual", C.c_double)]
 
 
 class fm_tuning(C.Structure):

@@ -612,6 +612,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         pk.max_blk_k = largest;
         pk.inv.assign((size_t)inv_total, 0.0);
         pk.invt.assign((size_t)inv_total, 0.0);
+        double blk_residual = 0.0;
         {
             std::vector<double> a, x;
             std::vector<int32_t> piv, local(0);
@@ -649,6 +650,23 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 }
                 x.assign((size_t)k * k, 0.0);
                 lu_inverse(k, a.data(), piv.data(), x.data());
+                // accuracy of the stored inverse: ||A_C X e_j - e_j||_inf on
+                // four columns, with A_C = I - W_CC from the couplings
+                for (int32_t j : {0, k / 3, (2 * k) / 3, k - 1}) {
+                    for (int32_t i = 0; i < k; i++) {
+                        const int32_t v = mem[i];
+                        double r = x[(size_t)i * k + j] - (i == j ? 1.0 : 0.0);
+                        const uint8_t pm = st->pmask[v];
+                        for (int slot = 0; slot < nslot; slot++) {
+                            if (!(pm & (1u << slot))) continue;
+                            const int32_t u = (int32_t)nbr(gr, v, slot);
+                            if (st->comp[u] != c) continue;
+                            const int32_t m = (int32_t)(std::lower_bound(mem, mem + k, u) - mem);
+                            r -= st->w6[(size_t)v * 6 + slot] * x[(size_t)m * k + j];
+                        }
+                        blk_residual = std::max(blk_residual, std::fabs(r));
+                    }
+                }
                 double* dst = pk.inv.data() + pk.blk_inv[b];
                 for (int32_t i = 0; i < k; i++)
                     for (int32_t j = 0; j < k; j++) dst[(size_t)j * k + i] = x[(size_t)i * k + j];
@@ -906,6 +924,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         S.n_iter_blocks = 0;
         S.max_iter = 0;
         S.iter_nnz = (int64_t)pk.sp_col.size();
+        S.block_residual = blk_residual;
         for (int32_t b = 0; b < nblk; b++)
             if (pk.blk_it[2 * (size_t)b]) {
                 S.n_iter_blocks++;

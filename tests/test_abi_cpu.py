@@ -164,3 +164,16 @@ def test_singular_scc_block_is_reported():
         fm.build_frozen_state(2, 3, 1, 3, G, T, s, 0)
     assert ei.value.code == fm.binding.FM_ESINGULAR
     assert "4 nodes" in str(ei.value)
+
+
+def test_block_inverse_residuals_are_recorded():
+    """Section 4.3 factors every block with pivoting; the setup also checks
+    the stored inverse, ||A_C X e_j - e_j||_inf on four columns, and records
+    the largest value in the statistics (0 when no block keeps an inverse)."""
+    wl = W.curved_state(41, 41, 25, A=500.0, eps_T=0.05)
+    st = fm.build_frozen_states(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T, wl.s, wl.src)[0].stats()
+    assert st["n_scc"] == 6 and 0.0 < st["block_residual"] <= 1e-13
+    flat = W.config("c1")
+    st = fm.build_frozen_states(flat.dim, flat.n1, flat.n2, flat.n3, flat.G, flat.T, flat.s, flat.src)[0].stats()
+    if st["n_scc"] == 0:
+        assert st["block_residual"] == 0.0
