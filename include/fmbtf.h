@@ -107,7 +107,8 @@ typedef struct fm_tuning {
     int32_t unroll;         /* nodes per thread in flight inside a level: 1, 2 or 4 (rhs groups);
                                split, 4 lanes per node (FP64 B=8, FP32 B=16): 2, 3, 4 with
                                512 threads, 4 with 256; 8 lanes per node (FP64 B=16, FP32 B=32):
-                               2, 4 with 512 threads, 3, 4 with 256 */
+                               2, 4 with 512 threads, 3, 4 with 256; 16 lanes per node (FP64
+                               B=32, FP32 B=64): 2 with 512 threads, 2, 3 with 256 */
     int32_t split;          /* workgroups sharing one source and all B rhs (node split):
                                0 = choose (the rhs-group kernel when no split fits),
                                1 = off (rhs groups), 2, 4, 8, 16 = that many */

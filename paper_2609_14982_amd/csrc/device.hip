@@ -537,7 +537,8 @@ static const void* split_fn() {
 // The node-split kernels that are built (lanes per node, threads, unroll).
 #define FM_SPLIT_SHAPES(X)                                             \
     X(4, 256, 4) X(4, 512, 2) X(4, 512, 3) X(4, 512, 4)                \
-    X(8, 256, 3) X(8, 256, 4) X(8, 512, 2) X(8, 512, 4)
+    X(8, 256, 3) X(8, 256, 4) X(8, 512, 2) X(8, 512, 4)                \
+    X(16, 256, 2) X(16, 256, 3) X(16, 512, 2)
 
 // kind 0: primal; 1: transpose from nodes; 2: transpose from receivers
 template <typename V, int L_, int N_, int U_>
@@ -630,7 +631,7 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     // the node split defaults to 512 threads and batches of 256-384 nodes (a
     // workgroup's share of a typical level in one round trip)
     const int nt = asked.threads ? asked.threads : 512;
-    const int u = asked.unroll ? asked.unroll : (lpn == 8 ? 4 : 3);
+    const int u = asked.unroll ? asked.unroll : (lpn == 16 ? 2 : lpn == 8 ? 4 : 3);
     const void* kf = split_kernel(0, fp64, lpn, nt, u);
     const void* kr = split_kernel(1, fp64, lpn, nt, u);
     const void* kq = split_kernel(2, fp64, lpn, nt, u);
@@ -650,7 +651,7 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
             return FM_EINVAL;
         }
         set_error("no node-split kernel for B=%d in this precision with %d threads and unroll %d (B must be %s; "
-                  "see the built shapes)", b->B, nt, u, fp64 ? "8 or 16" : "16 or 32");
+                  "see the built shapes)", b->B, nt, u, fp64 ? "8, 16 or 32" : "16, 32 or 64");
         return FM_EINVAL;
     }
     // the kernel's few bytes of static LDS come out of the same 160 KB

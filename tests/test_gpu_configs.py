@@ -51,20 +51,28 @@ def _pairing(d, y, p, g):
     return abs(a - b) / max(abs(a), abs(b))
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_c2_receivers_and_source_sum(c2, prec):
+@pytest.mark.parametrize("prec,tuning", [("fp64", None), ("fp32", None), ("fp64", {"split": 1}),
+                                         ("fp64", {"split": 4, "threads": 256, "unroll": 3}),
+                                         ("fp64", {"split": 8, "threads": 256, "unroll": 2})])
+def test_c2_receivers_and_source_sum(c2, prec, tuning):
+    """c2's 32 rhs: FP64 rows of 256 bytes take the node split with 16 lanes
+    per node (the library's choice) as well as the rhs-group kernel; FP32
+    rows of 128 bytes take 8 lanes per node."""
     wl, states, ops = c2
     B, R = wl.B, wl.rcv.shape[0]
     pr = fm.FM_FP64 if prec == "fp64" else fm.FM_FP32
     tol = TOL64 if prec == "fp64" else TOL32
-    b = fm.Batch(states, B, pr)
-    print(f"c2 {prec} schedule {b.tuning()}", flush=True)
+    b = fm.Batch(states, B, pr, tuning=tuning)
+    used = b.tuning()
+    print(f"c2 {prec} schedule {used}", flush=True)
     b.free()
+    if tuning is None or tuning.get("split", 1) > 1:
+        assert used["split"] > 1
     p = seeded_ds(wl, B, 2100, per_pair=False)
-    d = gpu_run(fm, torch, states, B, pr, "J", p, fm.FM_DS_BROADCAST, fm.FM_OUT_RECEIVERS)
+    d = gpu_run(fm, torch, states, B, pr, "J", p, fm.FM_DS_BROADCAST, fm.FM_OUT_RECEIVERS, tuning)
     assert rel_l2_pairs(d, oracle_J(ops, p, False, out="receivers")) <= tol
     y = np.random.default_rng(2101).standard_normal((wl.S, R, B))
-    g = gpu_run(fm, torch, states, B, pr, "JT", y, fm.FM_W_RECEIVERS, fm.FM_JT_SUMMED)
+    g = gpu_run(fm, torch, states, B, pr, "JT", y, fm.FM_W_RECEIVERS, fm.FM_JT_SUMMED, tuning)
     assert rel_l2(g, O.apply_JT_summed(ops, list(y), "receivers")) <= tol
     if prec == "fp64":
         for k in range(B):
