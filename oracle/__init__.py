@@ -9,6 +9,7 @@ convergence, dense LU, SuperLU).
 
 Modules
   assembly   face-upwind assembly of W and the calibration c      (Section 3.1, 3.2)
+             and the 26-neighbour (cube) stencil variant
   solve      J and J^T by sweeping / dense LU / SuperLU            (Sections 3.6, 4.4)
   diag       graph diagnostics: SCCs, Kahn residual, f_vio, ...    (Sections 3.3-3.5, 4.1-4.2)
   sweep.c    the Gauss-Seidel sweep kernel in plain C              (Section 3.6)

@@ -17,6 +17,10 @@ Readings where the paper defers to an uncited reference or is silent:
     c_i = l_i / s_i with l = A T then gives c_src = 0 (T_src = 0) and
     c_i = T_i / s_i on inflow-less rows.
 
+The 26-neighbour (cube) stencil (cube_couplings) is a variant the paper does
+not define: the same row form and calibration with upstream couplings that
+interpolate along the node's backward characteristic on its 3x3x3 cube.
+
 All sums are evaluated left to right in a fixed order (axis order for a_f,
 slot order minus/plus per axis for d_p and for (W T)_p), with no fused
 multiply-add, so the sign of every a_f is a deterministic FP64 decision.
@@ -139,21 +143,142 @@ class OracleOperator:
         return self.W.T.tocsr()
 
 
-def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None, rcv_w=None, identity_rows=None) -> OracleOperator:
+def node_directions(dim, n1, n2, n3, G, T):
+    """a = G grad_xi T at every node from the nodal metric and the nodal
+    derivatives (central inside, one-sided on the first and last node of an
+    axis), summed over d' in axis order; [N, dim], logical axis order
+    (Section 2.3 defines a; the cube stencil evaluates it at the node)."""
+    shape = _grid_shape(dim, n1, n2, n3)
+    N = n1 * n2 * n3
+    Tg = np.asarray(T, dtype=np.float64).reshape(shape)
+    Gm = _metric_full(np.asarray(G, dtype=np.float64), dim, shape)
+    nd = len(shape)
+    D = [_central(Tg, nd - 1 - dd) for dd in range(dim)]
+    out = np.empty((N, dim))
+    for d in range(dim):
+        acc = None
+        for dp in range(dim):
+            term = Gm[d][dp] * D[dp]
+            acc = term if acc is None else acc + term
+        out[:, d] = acc.reshape(N)
+    return out
+
+
+def cube_slot(off):
+    """Neighbour slot 0..25 of a logical offset (o_0, o_1, o_2) in {-1,0,1}^3
+    (o_2 = 0 in 2-D): 3-digit base-3 number of o + 1, axis 0 lowest, with the
+    centre (13) left out."""
+    b = (off[..., 0] + 1) + 3 * (off[..., 1] + 1) + 9 * (off[..., 2] + 1)
+    return b - (b > 13)
+
+
+def cube_couplings(dim, n1, n2, n3, G, T):
+    """Upstream couplings of the 26-neighbour (cube) stencil: the backward
+    characteristic of the node, p - t a with t = 1 / max_d |a_d| (unit logical
+    spacing), leaves the node's 3x3x3 cube through the face of the dominant
+    axis, and the transport value there is interpolated linearly on the
+    simplex of the cube's Kuhn (Freudenthal) triangulation that contains it.
+    With the axes sorted by r_d = |a_d| / max|a| (descending, ties to the lower
+    axis) and u_d = -sign(a_d) the upstream step, the vertices are the partial
+    sums u_(1) e_(1), + u_(2) e_(2), + u_(3) e_(3) with couplings
+    r_(1) - r_(2), r_(2) - r_(3), r_(3) (2-D: r_(1) - r_(2), r_(2)).  An axis
+    whose upstream neighbour lies outside the grid has its component of a set
+    to 0 first (no inflow from outside, as a missing face contributes nothing
+    in the face rule).
+
+    Returns (slot, node, coupling), each [N, dim]; coupling 0 marks an unused
+    vertex.  Nodes whose projected a vanishes get no vertex.
+
+    parity: pinned by linear exactness along the characteristic on affine
+    traveltimes (flat and anisotropic metrics, 2-D and 3-D), by reduction to
+    the face rule for axis-aligned directions, and by the upwind-side,
+    in-grid and vertex-count invariants (tests/test_oracle_cube.py).
+    """
+    N = n1 * n2 * n3
+    a = node_directions(dim, n1, n2, n3, G, T)
+    n = np.array([n1, n2, n3] if dim == 3 else [n1, n3], dtype=np.int64)
+    stride = np.array([1, n1, n1 * n2] if dim == 3 else [1, n1], dtype=np.int64)
+    ids = np.arange(N, dtype=np.int64)
+    coord = (ids[:, None] // stride[None, :]) % n[None, :]
+    up = np.where(a > 0.0, -1, np.where(a < 0.0, 1, 0)).astype(np.int64)
+    inside = (coord + up >= 0) & (coord + up <= n[None, :] - 1)
+    a = np.where(inside, a, 0.0)
+    up = np.where(inside, up, 0)
+    amax = np.max(np.abs(a), axis=1)
+    live = amax > 0.0
+    r = np.zeros_like(a)
+    r[live] = np.abs(a[live]) / amax[live][:, None]
+    order = np.argsort(-r, axis=1, kind="stable")
+    rs = np.take_along_axis(r, order, axis=1)
+    off = np.zeros((N, 3), dtype=np.int64)
+    slot = np.zeros((N, dim), dtype=np.int64)
+    node = np.zeros((N, dim), dtype=np.int64)
+    coup = np.zeros((N, dim))
+    rows = np.arange(N)
+    for t in range(dim):
+        ax = order[:, t]
+        off[rows, ax] += up[rows, ax]
+        slot[:, t] = cube_slot(off)
+        node[:, t] = ids + off[:, :dim] @ stride
+        coup[:, t] = rs[:, t] - rs[:, t + 1] if t + 1 < dim else rs[:, t]
+    coup[~live] = 0.0
+    return slot, node, coup
+
+
+def _cube_rows(dim, n1, n2, n3, G, T, active):
+    """Normalised rows of the cube stencil: couplings in ascending slot order,
+    d = their sum in that order, w = c / d (eq. (discrete-row))."""
+    slot, node, coup = cube_couplings(dim, n1, n2, n3, G, T)
+    key = np.where(coup > 0.0, slot, 99)
+    srt = np.argsort(key, axis=1, kind="stable")
+    slot = np.take_along_axis(slot, srt, axis=1)
+    node = np.take_along_axis(node, srt, axis=1)
+    coup = np.take_along_axis(coup, srt, axis=1)
+    N = coup.shape[0]
+    dsum = np.zeros(N)
+    for t in range(dim):
+        dsum = dsum + coup[:, t]
+    act = active & (dsum > 0.0)
+    wslots = []
+    for t in range(dim):
+        w = np.zeros(N)
+        m = act & (coup[:, t] > 0.0)
+        w[m] = coup[m, t] / dsum[m]
+        wslots.append((w, node[:, t]))
+    return wslots
+
+
+def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None, rcv_w=None, identity_rows=None,
+             stencil=6) -> OracleOperator:
     """Assemble W and c (Section 3.1 eq. (discrete-row), Section 3.2).
 
     identity_rows: further nodes whose rows are identity rows besides src
     (the source-seed rows of an off-grid point source, oracle.source); their
     calibration is then replaced by the seed derivative there.
 
+    stencil: 6 for the face-based upwinding of Section 3.1; 26 for the cube
+    stencil (cube_couplings), whose dependencies reach the edge and corner
+    neighbours; both normalise the couplings and calibrate the right-hand
+    side the same way.
+
     parity: pinned by the manufactured tangent test (first-order convergence to
     eq. (test-dT), Table 1), the flat-grid causal-order case, the 1-D closed
-    form, the exact scaling identity and the reversal criterion.
+    form, the exact scaling identity and the reversal criterion; the cube
+    stencil by the pins listed in cube_couplings.
     """
     shape = _grid_shape(dim, n1, n2, n3)
     N = n1 * n2 * n3
     T = np.asarray(T, dtype=np.float64).reshape(N)
     s = np.asarray(s, dtype=np.float64).reshape(N)
+    if stencil not in (6, 26):
+        raise ValueError("stencil must be 6 or 26")
+    if stencil == 26:
+        active = np.ones(N, dtype=bool)
+        active[src] = False
+        if identity_rows is not None:
+            active[np.asarray(identity_rows, dtype=np.int64)] = False
+        return _finish(dim, n1, n2, n3, T, s, src, rcv, rcv_w,
+                       _cube_rows(dim, n1, n2, n3, G, T, active))
     a_faces, _ = face_coefficients(dim, n1, n2, n3, G, T)
     nd = len(shape)
     ids = np.arange(N, dtype=np.int64).reshape(shape)
@@ -182,13 +307,21 @@ def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None, rcv_w=None, identity_rows=
     active[src] = False
     if identity_rows is not None:
         active[np.asarray(identity_rows, dtype=np.int64)] = False
-    rows, cols, vals = [], [], []
     wslots = []
     for cs, js in zip(slot_c, slot_j):
         w = np.zeros(N)
         m = active & (cs > 0.0)
         w[m] = cs[m] / dsum[m]
         wslots.append((w, js))
+    return _finish(dim, n1, n2, n3, T, s, src, rcv, rcv_w, wslots)
+
+
+def _finish(dim, n1, n2, n3, T, s, src, rcv, rcv_w, wslots) -> OracleOperator:
+    """W from the per-slot weights, and c = (T - W T) / s with W T summed in
+    slot order (Section 3.2)."""
+    N = T.shape[0]
+    rows, cols, vals = [], [], []
+    for w, js in wslots:
         sel = np.nonzero(w > 0.0)[0]
         rows.append(sel)
         cols.append(js[sel])
@@ -216,6 +349,7 @@ def assemble(dim, n1, n2, n3, G, T, s, src, rcv=None, rcv_w=None, identity_rows=
 
 
 def assemble_workload(wl, alpha: int) -> OracleOperator:
-    """Assemble the operator of source alpha of a workloads.Workload."""
+    """Assemble the operator of source alpha of a workloads.Workload (its
+    stencil attribute, 6 when absent)."""
     return assemble(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T[alpha], wl.s, int(wl.src[alpha]),
-                    wl.rcv, getattr(wl, "rcv_w", None))
+                    wl.rcv, getattr(wl, "rcv_w", None), stencil=getattr(wl, "stencil", 6))
