@@ -231,6 +231,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5, help="untimed LSQR iterations before the timed ones")
     ap.add_argument("--config", default="c4", choices=["c2", "c3", "c4"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--stencil", type=int, default=6, choices=[6, 26],
+                    help="dependency stencil: 6 (face-based upwinding) or 26 (the cube variant)")
     ap.add_argument("--sources", type=int, default=0, help="use only the first S sources (0: all)")
     ap.add_argument("--rhs-per-group", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
@@ -255,8 +257,9 @@ def main():
                          "and write profiles/traffic_k_split_<config>_<precision>.json (no GPU)")
     args = ap.parse_args()
 
+    tag = args.config + ("_cube" if args.stencil == 26 else "")
     if args.write_traffic:
-        write_traffic(args.write_traffic, args.config, args.precision)
+        write_traffic(args.write_traffic, tag, args.precision)
         return
 
     if args.gpus != 1:
@@ -283,6 +286,9 @@ def main():
 
     t0 = time.perf_counter()
     wl = W.config(args.config, with_T=False)
+    wl.stencil = args.stencil
+    if args.stencil == 26:
+        args.no_sweep = True     # the sweeping baseline takes face-stencil states only
     if args.sources:
         wl.src = wl.src[: args.sources]
     log(f"workload {args.config}: grid {wl.n1}x{wl.n2}x{wl.n3} N={wl.N} S={wl.S} B={wl.B} "
@@ -291,7 +297,8 @@ def main():
     W.eikonal(wl)
     log(f"first-arrival traveltimes for {wl.S} sources: {time.perf_counter() - t1:.1f}s")
     t1 = time.perf_counter()
-    states = fm.build_frozen_states(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T, wl.s, wl.src, wl.rcv)
+    states = fm.build_frozen_states(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T, wl.s, wl.src, wl.rcv,
+                                    stencil=args.stencil)
     setup_wall = time.perf_counter() - t1
     stats = [st.stats() for st in states]
     log(f"setup (host, {min(16, os.cpu_count() or 1)} threads): {setup_wall:.1f}s; "
@@ -398,7 +405,7 @@ def main():
     bytes_J = algorithmic_bytes(stats, B, vbytes, vbytes)
     gbs_J = bytes_J / (tJ.mean() * 1e-3) / 1e9
     gbs_T = bytes_J / (tT.mean() * 1e-3) / 1e9
-    traffic = measured_traffic(kname, args.config, args.precision) if not args.sources else None
+    traffic = measured_traffic(kname, tag, args.precision) if not args.sources else None
     roof = {"bound": "hbm", "achieved": round(gbs_J, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs_J / PEAK_HBM_GBS, 4), "traffic": traffic,
             "traffic_kind": "fabric bytes per launch: rocprofv3 FETCH_SIZE + WRITE_SIZE scaled by a plain copy "
@@ -501,7 +508,9 @@ def main():
         "dtype": "f64" if prec == fm.FM_FP64 else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {wl.n1}x{wl.n2}x{wl.n3} deformed grid, "
-                               f"{S} sources x {B} rhs, {R} receivers",
+                               f"{S} sources x {B} rhs, {R} receivers"
+                               + (", 26-neighbour cube stencil" if args.stencil == 26 else ""),
+                   "stencil": args.stencil,
                    "schedule": batch.tuning(),
                    "schedule_cached": tune_cached,
                    "schedule_search": ([{"split": t["split"], "threads": t["threads"], "unroll": t["unroll"],

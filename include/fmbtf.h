@@ -7,6 +7,7 @@
  *
  *   A = I - W                    face-upwind frozen transport, Section 3.1,
  *                                eq. (discrete-row) and eq. (transport-system)
+ *                                (or the 26-neighbour cube stencil, fm_grid)
  *   C = diag(c), c_i = l_i / s_i with l = A T    Section 3.2
  *   J_alpha   = P_alpha A^{-1} C                 eq. (source-jacobian), M = I, D = 0
  *   J_alpha^T = C A^{-T} P_alpha^T               eq. (source-transpose)
@@ -68,6 +69,22 @@ typedef struct fm_grid {
     int32_t dim;            /* 2 or 3 */
     int64_t n1, n2, n3;     /* nodes per logical axis; n2 = 1 in 2-D */
     const double* G;        /* host pointer, metric as described above */
+    int32_t stencil;        /* dependency stencil of the build calls:
+                               0 or 6: the face-based upwinding of Section 3.1
+                               (at most six neighbour dependencies per row);
+                               26: the cube stencil, a variant the paper does
+                               not define: a row interpolates the transport
+                               value where the node's backward characteristic
+                               (direction -a, a = G grad_xi T at the node)
+                               leaves its 3x3x3 cube of nodes, linearly on the
+                               Kuhn simplex that holds that point (at most dim
+                               dependencies among the 26 neighbours), then is
+                               normalised and calibrated as in Sections
+                               3.1-3.2; an axis whose upstream neighbour lies
+                               outside the grid has its component of a set to
+                               0 first.  Any other value: FM_EINVAL.  The GPU
+                               setup pass and the sweeping baseline take the
+                               face stencil only. */
 } fm_grid;
 
 typedef struct fm_state fm_state;   /* one frozen source: W, c, graph, levels, SCC factors */

@@ -47,7 +47,7 @@ class FmError(RuntimeError):
 
 class fm_grid(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n1", C.c_int64), ("n2", C.c_int64), ("n3", C.c_int64),
-                ("G", C.c_void_p)]
+                ("G", C.c_void_p), ("stencil", C.c_int32)]
 
 
 class fm_stats(C.Structure):
@@ -166,10 +166,11 @@ def _i64(a):
     return np.ascontiguousarray(a, dtype=np.int64)
 
 
-def _grid(dim, n1, n2, n3, G):
+def _grid(dim, n1, n2, n3, G, stencil=6):
     g = fm_grid()
     g.dim, g.n1, g.n2, g.n3 = int(dim), int(n1), int(n2), int(n3)
     g.G = G.ctypes.data
+    g.stencil = int(stencil)
     return g
 
 
@@ -224,13 +225,14 @@ class State:
             pass
 
 
-def build_frozen_state(dim, n1, n2, n3, G, T, s, src_node, rcv_nodes=(), rcv_weights=None) -> State:
+def build_frozen_state(dim, n1, n2, n3, G, T, s, src_node, rcv_nodes=(), rcv_weights=None, stencil=6) -> State:
     """fm_build_frozen_state with numpy host inputs.  With rcv_weights, the
     receivers interpolate: rcv_nodes and rcv_weights are [R][K] and receiver r
-    samples sum_k rcv_weights[r][k] x[rcv_nodes[r][k]] (fm_build_frozen_state_w)."""
+    samples sum_k rcv_weights[r][k] x[rcv_nodes[r][k]] (fm_build_frozen_state_w).
+    stencil: 6 (faces) or 26 (cube), fm_grid.stencil."""
     lib = load()
     G, T, s = _f64(G), _f64(T), _f64(s)
-    g = _grid(dim, n1, n2, n3, G)
+    g = _grid(dim, n1, n2, n3, G, stencil)
     out = C.c_void_p()
     if rcv_weights is None:
         rcv = _i64(rcv_nodes)
@@ -249,17 +251,19 @@ def build_frozen_state(dim, n1, n2, n3, G, T, s, src_node, rcv_nodes=(), rcv_wei
     return State(out.value, int(n1) * int(n2) * int(n3), dim, (n1, n2, n3), int(R))
 
 
-def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nthreads=None, rcv_weights=None):
+def build_frozen_states(dim, n1, n2, n3, G, T, s, src_nodes, rcv_nodes=None, nthreads=None, rcv_weights=None,
+                        stencil=6):
     """fm_build_frozen_states: T [S][N]; rcv_nodes [R] (shared) or [S][R].
     With rcv_weights (fm_build_frozen_states_w): rcv_nodes and rcv_weights of
-    one shape, [R][K] (shared) or [S][R][K], interpolating receivers."""
+    one shape, [R][K] (shared) or [S][R][K], interpolating receivers.
+    stencil: 6 (faces) or 26 (cube), fm_grid.stencil."""
     lib = load()
     G, T, s = _f64(G), _f64(T), _f64(s)
     src = _i64(src_nodes)
     S = int(src.shape[0])
     if nthreads is None:
         nthreads = min(16, os.cpu_count() or 1)
-    g = _grid(dim, n1, n2, n3, G)
+    g = _grid(dim, n1, n2, n3, G, stencil)
     outs = (C.c_void_p * S)()
     N = int(n1) * int(n2) * int(n3)
     if rcv_weights is not None:
@@ -343,7 +347,7 @@ def _receivers_pt(rcv_nodes, rcv_weights, S):
 
 
 def build_frozen_states_pt(dim, n1, n2, n3, G, X, T, s, xi_src, seed_radius, rcv_nodes=None, rcv_weights=None,
-                           nthreads=None):
+                           nthreads=None, stencil=6):
     """fm_build_frozen_states_pt: off-grid point sources at logical
     coordinates xi_src [S][dim] with seed regions of max-norm radius
     seed_radius; X [N][dim] physical node coordinates, T [S][N] (straight-ray
@@ -357,7 +361,7 @@ def build_frozen_states_pt(dim, n1, n2, n3, G, X, T, s, xi_src, seed_radius, rcv
         raise ValueError("T must be [S][N] with one row per source")
     if nthreads is None:
         nthreads = min(16, os.cpu_count() or 1)
-    g = _grid(dim, n1, n2, n3, G)
+    g = _grid(dim, n1, n2, n3, G, stencil)
     outs = (C.c_void_p * S)()
     N = int(n1) * int(n2) * int(n3)
     rcv, w = _receivers_pt(rcv_nodes, rcv_weights, S)

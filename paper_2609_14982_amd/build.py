@@ -67,17 +67,22 @@ def build_sanitize(verbose: bool = False) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    jobs = []
     for src in ("setup.cpp", "capi.cpp"):
         obj = os.path.join(BUILD, src.replace(".cpp", ".o"))
-        _run(["g++", *HOST_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj],
-             verbose)
-        objs.append(obj)
+        jobs.append((["g++", *HOST_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj], obj))
     for src in HIP_SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-        _run([HIPCC, *HIP_FLAGS, *HIP_EXTRA.get(src, []), "-I", INCLUDE, "-I", CSRC, "-c",
-              os.path.join(CSRC, src), "-o", obj], verbose)
-        objs.append(obj)
+        jobs.append(([HIPCC, *HIP_FLAGS, *HIP_EXTRA.get(src, []), "-I", INCLUDE, "-I", CSRC, "-c",
+                      os.path.join(CSRC, src), "-o", obj], obj))
+    # the translation units compile independently (device.hip, the largest,
+    # first so that it overlaps the rest)
+    from concurrent.futures import ThreadPoolExecutor
+    workers = max(1, min(len(jobs), os.cpu_count() or 1, 8))
+    with ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(_run, cmd, verbose) for cmd, _ in sorted(jobs, key=lambda j: "device.hip" not in j[0][-3])]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, "-pthread"], verbose)
     os.replace(tmp, LIB)

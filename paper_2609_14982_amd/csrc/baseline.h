@@ -62,6 +62,7 @@ __global__ __launch_bounds__(NT) void k_gs_sweep(GsArgs g) {
     cx.st2 = a.st2;
     cx.N = a.N;
     cx.rcv_in = false;
+    cx.cube = false;          // face-stencil states only
     const V* __restrict__ in = (const V*)a.in +
         ((DIR == kFwd && a.in_mode == FM_DS_BROADCAST) ? 0 : (size_t)alpha * NB);
     V* __restrict__ X = (V*)a.work + (size_t)alpha * NB;

@@ -77,6 +77,8 @@ struct SrcDev {
     const int32_t* rcv_idx;     // [E] receiver of each sorted entry
     const double* rcv_ew;       // [E] weight of each sorted entry
     const PtDev* pt;            // off-grid source tables, or nullptr
+    const int32_t* fovf;        // cube stencil: overflow offset per position, or nullptr
+    const int32_t* rovf;
     int32_t L_f, L_r, n_rcv, n_ent;
 };
 
@@ -156,6 +158,7 @@ struct ApplyArgs {
     int64_t st1, st2;       // node strides of logical axes 1 and 2
     int32_t R;              // receivers per source (receiver layouts)
     int32_t in_mode, out_mode;
+    int32_t cube;           // cube-stencil records (26-bit neighbour masks)
     int32_t xB;             // values per row of work ([S][N][xB], xB >= B; rows padded to 128 bytes
                             // when work is the batch's own scratch of a node-split batch)
     const void* in;         // J: ds ; J^T: w

@@ -202,21 +202,20 @@ int fm_state_stats(const fm_state* st, fm_stats* out) {
 int fm_state_export_operator(const fm_state* st, int64_t* rowptr, int32_t* col, double* w, double* c) {
     fm::clear_error();
     if (!st) { fm::set_error("null state"); return FM_EINVAL; }
-    const int nslot = 2 * st->dim;
+    const int nslot = st->nslot();
     int64_t e = 0;
     for (int64_t p = 0; p < st->N; p++) {
         if (rowptr) rowptr[p] = e;
-        // neighbours in ascending node id: -z, -y, -x, +x, +y, +z
+        // neighbours in ascending node id: face slots -z, -y, -x, +x, +y, +z;
+        // cube slots are already in that order
         static const int order3[6] = {4, 2, 0, 1, 3, 5};
         static const int order2[4] = {2, 0, 1, 3};
         const int* order = st->dim == 3 ? order3 : order2;
         for (int q = 0; q < nslot; q++) {
-            int slot = order[q];
+            int slot = st->stencil == 26 ? q : order[q];
             if (!(st->pmask[p] & (1u << slot))) continue;
-            int axis = slot >> 1;
-            int64_t j = (slot & 1) ? p + st->stride[axis] : p - st->stride[axis];
-            if (col) col[e] = (int32_t)j;
-            if (w) w[e] = st->w6[(size_t)p * 6 + slot];
+            if (col) col[e] = (int32_t)st->neighbour(p, slot);
+            if (w) w[e] = st->weight(p, slot);
             e++;
         }
     }

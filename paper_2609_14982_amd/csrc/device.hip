@@ -124,6 +124,8 @@ int upload_state(HostState* st) {
     size_t o_tk = ar.add<uint8_t>(pk.sc_kind.size());
     size_t o_tw = ar.add<double>(pk.sc_w.size());
     size_t o_pt = ar.add<PtDev>(has_pt ? 1 : 0);
+    size_t o_fovf = ar.add<int32_t>(pk.fovf.size());
+    size_t o_rovf = ar.add<int32_t>(pk.rovf.size());
     size_t total = ar.add<char>(0) + 256;
     DeviceState* ds = new DeviceState();
     hipError_t e = hipMalloc(&ds->blob, total);
@@ -169,6 +171,8 @@ int upload_state(HostState* st) {
     rc = rc ? rc : put(b, o_rp, pk.rcv_pos);
     rc = rc ? rc : put(b, o_ri, pk.rcv_idx);
     rc = rc ? rc : put(b, o_rew, pk.rcv_ew);
+    rc = rc ? rc : put(b, o_fovf, pk.fovf);
+    rc = rc ? rc : put(b, o_rovf, pk.rovf);
     if (has_pt) {
         rc = rc ? rc : put(b, o_sn, pk.seed_node);
         rc = rc ? rc : put(b, o_sp, pk.seed_ptr);
@@ -241,6 +245,8 @@ int upload_state(HostState* st) {
     d.rcv_idx = (const int32_t*)(b + o_ri);
     d.rcv_ew = (const double*)(b + o_rew);
     d.pt = has_pt ? (const PtDev*)(b + o_pt) : nullptr;
+    d.fovf = pk.fovf.empty() ? nullptr : (const int32_t*)(b + o_fovf);
+    d.rovf = pk.rovf.empty() ? nullptr : (const int32_t*)(b + o_rovf);
     d.L_f = pk.L_f;
     d.L_r = pk.L_r;
     d.n_rcv = (int32_t)pk.rcv_ptr.size() - 1;
@@ -534,28 +540,41 @@ static const void* split_fn() {
     return (const void*)k_split<DIR, V, LPN, NT, U, MODE>;
 }
 
-// The node-split kernels that are built (lanes per node, threads, unroll).
+// The node-split kernels that are built (lanes per node, threads, unroll),
+// for face-stencil states and, fewer, for cube-stencil states (the library
+// defaults for every lane count and the 256-thread shapes).
 #define FM_SPLIT_SHAPES(X)                                             \
     X(4, 256, 4) X(4, 512, 2) X(4, 512, 3) X(4, 512, 4)                \
     X(8, 256, 3) X(8, 256, 4) X(8, 512, 2) X(8, 512, 4)                \
     X(16, 256, 2) X(16, 256, 3) X(16, 512, 2)
+#define FM_SPLIT_SHAPES_CUBE(X)                                        \
+    X(4, 256, 4) X(4, 512, 3) X(8, 256, 3) X(8, 512, 4)                \
+    X(16, 256, 2) X(16, 512, 2)
 
-// kind 0: primal; 1: transpose from nodes; 2: transpose from receivers
-template <typename V, int L_, int N_, int U_>
+// kind 0: primal; 1: transpose from nodes; 2: transpose from receivers;
+// mode bit 1 (2) added for the cube-stencil records
+template <typename V, int L_, int N_, int U_, int CUBE>
 static const void* split_kind(int kind) {
     switch (kind) {
-        case 0: return split_fn<kFwd, V, L_, N_, U_, 0>();
-        case 1: return split_fn<kRev, V, L_, N_, U_, 0>();
-        case 2: return split_fn<kRev, V, L_, N_, U_, 1>();
+        case 0: return split_fn<kFwd, V, L_, N_, U_, 2 * CUBE>();
+        case 1: return split_fn<kRev, V, L_, N_, U_, 2 * CUBE>();
+        case 2: return split_fn<kRev, V, L_, N_, U_, 2 * CUBE + 1>();
     }
     return nullptr;
 }
 
-static const void* split_kernel(int kind, bool fp64, int lpn, int nt, int u) {
+static const void* split_kernel(int kind, bool fp64, bool cube, int lpn, int nt, int u) {
 #define FM_SPLIT_PTR(L_, N_, U_) \
-    if (lpn == L_ && nt == N_ && u == U_) return fp64 ? split_kind<double, L_, N_, U_>(kind) : split_kind<float, L_, N_, U_>(kind);
+    if (lpn == L_ && nt == N_ && u == U_) return fp64 ? split_kind<double, L_, N_, U_, 0>(kind) : split_kind<float, L_, N_, U_, 0>(kind);
+#define FM_SPLIT_PTR_CUBE(L_, N_, U_) \
+    if (lpn == L_ && nt == N_ && u == U_) return fp64 ? split_kind<double, L_, N_, U_, 1>(kind) : split_kind<float, L_, N_, U_, 1>(kind);
+    if (cube) {
+        FM_SPLIT_SHAPES_CUBE(FM_SPLIT_PTR_CUBE)
+        return nullptr;
+    }
     FM_SPLIT_SHAPES(FM_SPLIT_PTR)
 #undef FM_SPLIT_PTR
+#undef FM_SPLIT_PTR_CUBE
     return nullptr;
 }
 
@@ -570,17 +589,28 @@ static hipError_t launch_split_dir(int lpn, int nt, int u, const ApplyArgs& a, c
                                    size_t lds, hipStream_t st) {
 #define FM_SPLIT_LAUNCH(L_, N_, U_) \
     if (lpn == L_ && nt == N_ && u == U_) return launch_split_one<DIR, V, L_, N_, U_, MODE>(a, s, grid, lds, st);
-    FM_SPLIT_SHAPES(FM_SPLIT_LAUNCH)
+    if constexpr ((MODE & 2) != 0) {
+        FM_SPLIT_SHAPES_CUBE(FM_SPLIT_LAUNCH)
+    } else {
+        FM_SPLIT_SHAPES(FM_SPLIT_LAUNCH)
+    }
 #undef FM_SPLIT_LAUNCH
     return hipErrorInvalidValue;
 }
 
+// mode bit 0: transpose input at the receivers; bit 1: cube-stencil records
 template <typename V>
 static hipError_t launch_split_v(bool fwd, int mode, int lpn, int nt, int u, const ApplyArgs& a, const SplitArgs& s,
                                  int grid, size_t lds, hipStream_t st) {
-    if (fwd) return launch_split_dir<kFwd, V, 0>(lpn, nt, u, a, s, grid, lds, st);
-    return mode ? launch_split_dir<kRev, V, 1>(lpn, nt, u, a, s, grid, lds, st)
-                : launch_split_dir<kRev, V, 0>(lpn, nt, u, a, s, grid, lds, st);
+    switch (mode | (fwd ? 4 : 0)) {
+        case 4: return launch_split_dir<kFwd, V, 0>(lpn, nt, u, a, s, grid, lds, st);
+        case 6: return launch_split_dir<kFwd, V, 2>(lpn, nt, u, a, s, grid, lds, st);
+        case 0: return launch_split_dir<kRev, V, 0>(lpn, nt, u, a, s, grid, lds, st);
+        case 1: return launch_split_dir<kRev, V, 1>(lpn, nt, u, a, s, grid, lds, st);
+        case 2: return launch_split_dir<kRev, V, 2>(lpn, nt, u, a, s, grid, lds, st);
+        case 3: return launch_split_dir<kRev, V, 3>(lpn, nt, u, a, s, grid, lds, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 static int split_lpn(const fm_batch* b) {
@@ -613,7 +643,7 @@ static hipError_t launch_split(const fm_batch* b, bool fwd, const ApplyArgs& a0)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int lpn = split_lpn(b), nt = b->tun.threads, u = b->tun.unroll;
-    const int mode = !fwd && a.in_mode == FM_W_RECEIVERS ? 1 : 0;
+    const int mode = (!fwd && a.in_mode == FM_W_RECEIVERS ? 1 : 0) | (b->states[0]->stencil == 26 ? 2 : 0);
     if (b->prec == FM_FP64)
         return launch_split_v<double>(fwd, mode, lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream);
     return launch_split_v<float>(fwd, mode, lpn, nt, u, a, s, b->split_grid, b->split_lds, b->stream);
@@ -632,9 +662,10 @@ static int prepare_split(fm_batch* b, fm_tuning& t, const fm_tuning& asked) {
     // workgroup's share of a typical level in one round trip)
     const int nt = asked.threads ? asked.threads : 512;
     const int u = asked.unroll ? asked.unroll : (lpn == 16 ? 2 : lpn == 8 ? 4 : 3);
-    const void* kf = split_kernel(0, fp64, lpn, nt, u);
-    const void* kr = split_kernel(1, fp64, lpn, nt, u);
-    const void* kq = split_kernel(2, fp64, lpn, nt, u);
+    const bool cube = b->states[0]->stencil == 26;
+    const void* kf = split_kernel(0, fp64, cube, lpn, nt, u);
+    const void* kr = split_kernel(1, fp64, cube, lpn, nt, u);
+    const void* kq = split_kernel(2, fp64, cube, lpn, nt, u);
     const bool built = kf && kr && kq;
     if (t.split != 0 && t.split != 2 && t.split != 4 && t.split != 8 && t.split != 16) {
         set_error("split must be 0, 1, 2, 4, 8 or 16");
@@ -908,7 +939,7 @@ int batch_create(fm_state* const* states, int32_t S, int32_t B, int32_t precisio
     for (int32_t i = 0; i < S; i++) {
         HostState* si = static_cast<HostState*>(states[i]);
         if (!si) { set_error("null state %d", i); return FM_EINVAL; }
-        if (!si->same_grid(*s0)) { set_error("state %d has another grid shape", i); return FM_EINVAL; }
+        if (!si->same_grid(*s0)) { set_error("state %d has another grid shape or stencil", i); return FM_EINVAL; }
         if ((int32_t)si->pk.rcv_ptr.size() - 1 != R) { set_error("state %d has another receiver count", i); return FM_EINVAL; }
         maxk = std::max<int64_t>(maxk, si->pk.max_blk_rows);
     }
@@ -1059,6 +1090,7 @@ ApplyArgs batch_args(const fm_batch* b) {
     a.st1 = b->st1;
     a.st2 = b->st2;
     a.R = b->R;
+    a.cube = b->states[0]->stencil == 26 ? 1 : 0;
     return a;
 }
 
@@ -1171,6 +1203,10 @@ int apply_JT(fm_batch* b, const void* w, int32_t w_mode, void* out, int32_t out_
 
 static int upload_natural(HostState* st, int prec) {
     DeviceState* ds = st->dev;
+    if (st->stencil != 6) {
+        set_error("the directional-sweeping baseline takes face-stencil states only");
+        return FM_EINVAL;
+    }
     if (!ds->blob_nat) {
         std::vector<uint64_t> fm_, rm_;
         std::vector<double> fr, rr;
@@ -1429,7 +1465,7 @@ static int tune_key(fm_state* const* states, int32_t S, int32_t B, int32_t preci
     for (int32_t i = 0; i < S; i++) {
         const HostState* st = static_cast<const HostState*>(states[i]);
         if (!st) { set_error("null state %d", i); return FM_EINVAL; }
-        const int64_t dims[5] = {st->dim, st->n[0], st->n[1], st->n[2], st->src};
+        const int64_t dims[6] = {st->dim, st->n[0], st->n[1], st->n[2], st->src, st->stencil};
         h = fnv1a(h, dims, sizeof(dims));
         h = fnv1a_vec(h, st->pk.flvl_nsc);
         h = fnv1a_vec(h, st->pk.rlvl_nsc);
@@ -1505,6 +1541,7 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
     list.push_back(fm_tuning{0, 0, 0, 0, 0, 1, 0});   // rhs groups, library defaults
     const int vw = precision == FM_FP64 ? 2 : 4;
     const int lpn = B % vw == 0 ? B / vw : 0;
+    const bool cube = static_cast<const HostState*>(states[0])->stencil == 26;
 #define FM_SPLIT_CAND(L_, N_, U_)                                           \
     if (lpn == L_) {                                                        \
         for (int P : {2, 4, 8, 16}) list.push_back(fm_tuning{0, N_, 0, 0, U_, P, 0}); \
@@ -1516,7 +1553,11 @@ int autotune(fm_state* const* states, int32_t S, int32_t B, int32_t precision, v
             list.push_back(fm_tuning{0, N_, 0, 0, U_, 0, 7});               \
         }                                                                   \
     }
-    FM_SPLIT_SHAPES(FM_SPLIT_CAND)
+    if (cube) {
+        FM_SPLIT_SHAPES_CUBE(FM_SPLIT_CAND)
+    } else {
+        FM_SPLIT_SHAPES(FM_SPLIT_CAND)
+    }
 #undef FM_SPLIT_CAND
     hipStream_t st = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1630,7 +1671,7 @@ int apply_J_static(fm_state* const* states, int32_t S, int32_t B, int32_t precis
     for (int32_t i = 0; i < S; i++) {
         HostState* si = static_cast<HostState*>(states[i]);
         if (!si) { set_error("null state %d", i); return FM_EINVAL; }
-        if (!si->same_grid(*s0)) { set_error("state %d has another grid shape", i); return FM_EINVAL; }
+        if (!si->same_grid(*s0)) { set_error("state %d has another grid shape or stencil", i); return FM_EINVAL; }
         if ((int32_t)si->pk.rcv_ptr.size() - 1 != R) { set_error("state %d has another receiver count", i); return FM_EINVAL; }
         if (!si->dev || si->dev->device != dev || (precision == FM_FP32 && !si->dev->blob32)) {
             set_error("state %d is not resident on device %d in FP%d: create a batch over it once first "

@@ -34,6 +34,13 @@ void clear_error();
 // with weight w_{i,node}.  For members of a nontrivial SCC only the
 // neighbours outside the component are listed; couplings inside the
 // component live in the block's dense factors.
+//
+// States of the 26-neighbour (cube) stencil use a 26-bit mask in bits 32..57
+// instead (bits 58..63 zero); slot b is the logical offset o in {-1,0,1}^3
+// whose base-3 number (o_0 + 1) + 3 (o_1 + 1) + 9 (o_2 + 1), centre left out,
+// is b (ascending slots are ascending node ids; the opposite of b is 25 - b).
+// Their overflow offsets are in a per-position array of their own (fovf /
+// rovf).
 // ---------------------------------------------------------------------------
 constexpr int kNodeBits = 31;
 constexpr uint64_t kNodeMask = (1ull << kNodeBits) - 1;
@@ -42,6 +49,16 @@ constexpr int kOffShift = 32;
 constexpr int kOffBits = 26;
 constexpr uint64_t kOffMask = (1ull << kOffBits) - 1;
 constexpr int kMaskShift = 58;
+constexpr int kCubeMaskShift = 32;
+constexpr uint64_t kCubeMask = (1ull << 26) - 1;
+
+// Neighbour slots of the cube stencil: offset of slot b along each axis.
+inline void cube_offset(int slot, int o[3]) {
+    const int b = slot + (slot >= 13 ? 1 : 0);
+    o[0] = b % 3 - 1;
+    o[1] = (b / 3) % 3 - 1;
+    o[2] = b / 9 - 1;
+}
 
 struct Packed {
     int32_t L_f = 0, L_r = 0, nblk = 0;
@@ -85,6 +102,8 @@ struct Packed {
     std::vector<int32_t> sp_ptr, sp_col, spt_ptr, spt_col;
     std::vector<double> sp_w, spt_w;
     int64_t max_blk_rows = 0;          // most FP64 rows one block stages (k, or 3k iterative)
+    // cube stencil only: overflow offset of each position's further weights
+    std::vector<int32_t> fovf, rovf;
     // off-grid point source (all empty for an on-grid source).  Seed node
     // seed_node[e] is an identity row whose right-hand side is
     // sum_i seed_w[i] ds[seed_col[i]] over i in [seed_ptr[e], seed_ptr[e+1]);
@@ -131,10 +150,28 @@ struct HostState {
     int64_t stride[3] = {1, 1, 1};
     int64_t N = 0;
     int64_t src = 0;
-    // natural-order operator
-    std::vector<uint8_t> pmask, smask;
-    std::vector<double> w6;         // [N][6] weight per neighbour slot (0 if none)
+    int stencil = 6;                // 6: face-based upwinding; 26: cube stencil
+    // natural-order operator: predecessor and successor slot masks, and the
+    // weights, per slot ([N][6], 0 if none) for the face stencil, by rank in
+    // ascending slot order ([N][3]) for the cube stencil (see weight())
+    std::vector<uint32_t> pmask, smask;
+    std::vector<double> wrow;
     std::vector<double> cal;        // [N]
+    int nslot() const { return stencil == 26 ? 26 : 2 * dim; }
+    // w_{p, neighbour in slot}
+    double weight(int64_t p, int slot) const {
+        if (stencil == 26) return wrow[(size_t)p * 3 + __builtin_popcount(pmask[p] & ((1u << slot) - 1u))];
+        return wrow[(size_t)p * 6 + slot];
+    }
+    int64_t neighbour(int64_t p, int slot) const {
+        if (stencil == 26) {
+            int o[3];
+            cube_offset(slot, o);
+            return p + o[0] * stride[0] + o[1] * stride[1] + o[2] * stride[2];
+        }
+        return (slot & 1) ? p + stride[slot >> 1] : p - stride[slot >> 1];
+    }
+    int opposite(int slot) const { return stencil == 26 ? 25 - slot : slot ^ 1; }
     // graph
     std::vector<int32_t> comp;      // component id, numbered in topological order
     int32_t ncomp = 0;
@@ -145,7 +182,7 @@ struct HostState {
     DeviceState* dev = nullptr;
     // the grid shape, to check that the states of one batch agree
     bool same_grid(const HostState& o) const {
-        return dim == o.dim && n[0] == o.n[0] && n[1] == o.n[1] && n[2] == o.n[2];
+        return dim == o.dim && n[0] == o.n[0] && n[1] == o.n[1] && n[2] == o.n[2] && stencil == o.stencil;
     }
 };
 

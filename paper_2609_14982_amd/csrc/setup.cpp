@@ -42,6 +42,7 @@ struct Grid {
     int64_t N;
     const double* G;
     int ncomp_g;   // metric components per node: 3 (2-D) or 6 (3-D)
+    int stencil;   // 6 (faces) or 26 (cube)
 };
 
 // Full symmetric metric entry (a, b) of node p.
@@ -73,6 +74,11 @@ inline double nodal_derivative(const Grid& g, const double* T, int64_t p, int ax
 }
 
 inline int64_t nbr(const Grid& g, int64_t p, int slot) {
+    if (g.stencil == 26) {
+        int o[3];
+        cube_offset(slot, o);
+        return p + o[0] * g.stride[0] + o[1] * g.stride[1] + o[2] * g.stride[2];
+    }
     int axis = slot >> 1;
     return (slot & 1) ? p + g.stride[axis] : p - g.stride[axis];
 }
@@ -83,6 +89,8 @@ inline bool has_nbr(const Grid& g, int64_t p, int slot) {
     int64_t c = coord(g, p, axis);
     return (slot & 1) ? (c + 1 < g.n[axis]) : (c > 0);
 }
+
+inline int opposite(const Grid& g, int slot) { return g.stencil == 26 ? 25 - slot : slot ^ 1; }
 
 // Dense LU with partial pivoting (largest magnitude, ties to the lowest row),
 // in place on a row-major k x k matrix.  Returns the index of the first pivot
@@ -165,6 +173,11 @@ int validate(const fm_grid* g, const double* T, const double* s, int64_t src, co
     gr.N = gr.n[0] * gr.n[1] * gr.n[2];
     gr.G = g->G;
     gr.ncomp_g = g->dim == 3 ? 6 : 3;
+    gr.stencil = g->stencil == 0 ? 6 : g->stencil;
+    if (gr.stencil != 6 && gr.stencil != 26) {
+        set_error("stencil must be 0 or 6 (faces) or 26 (cube), got %d", g->stencil);
+        return FM_EINVAL;
+    }
     if (gr.N >= (int64_t)kNodeMask) { set_error("grid too large: %lld nodes", (long long)gr.N); return FM_EINVAL; }
     if (!ps && (src < 0 || src >= gr.N)) { set_error("source node %lld out of range", (long long)src); return FM_EINVAL; }
     if (ps) {
@@ -249,6 +262,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         for (int a = 0; a < 3; a++) { st->n[a] = gr.n[a]; st->stride[a] = gr.stride[a]; }
         st->N = N;
         st->src = src;
+        st->stencil = gr.stencil;
 
         // ---- 0: an off-grid source's seed region (identity rows) ----
         // seed rows take the derivative of the straight-ray seed time
@@ -298,14 +312,16 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         }
 
         // ---- 1-2: couplings, weights, calibration (Sections 3.1-3.2) ----
+        const bool cube = gr.stencil == 26;
+        if (pre && cube) { set_error("precomputed couplings are face-stencil couplings"); delete st; return FM_EINVAL; }
         st->pmask.assign(N, 0);
-        st->w6.assign((size_t)N * 6, 0.0);
+        st->wrow.assign((size_t)N * (cube ? 3 : 6), 0.0);
         st->cal.assign(N, 0.0);
-        const int nslot = 2 * gr.dim;
+        const int nslot = cube ? 26 : 2 * gr.dim;
         int64_t E = 0;
         if (pre) {
             std::copy(pre->pmask, pre->pmask + N, st->pmask.begin());
-            std::copy(pre->w6, pre->w6 + (size_t)N * 6, st->w6.begin());
+            std::copy(pre->w6, pre->w6 + (size_t)N * 6, st->wrow.begin());
             std::copy(pre->cal, pre->cal + N, st->cal.begin());
             for (int64_t p = 0; p < N; p++) E += __builtin_popcount(st->pmask[p]);
         }
@@ -314,11 +330,13 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         // tangential derivative the mean of the two nodal derivatives
         // (computed once per node); the sum runs over d' in axis order.
         // af[p][d] belongs to the face between p and p + e_d.
-        std::vector<double> af;
+        std::vector<double> af, nd;
         if (!pre) {
-            std::vector<double> nd((size_t)N * gr.dim);
+            nd.resize((size_t)N * gr.dim);
             for (int64_t p = 0; p < N; p++)
                 for (int d = 0; d < gr.dim; d++) nd[(size_t)p * gr.dim + d] = nodal_derivative(gr, T, p, d);
+        }
+        if (!pre && !cube) {
             af.assign((size_t)N * gr.dim, 0.0);
             for (int64_t lo = 0; lo < N; lo++)
                 for (int d = 0; d < gr.dim; d++) {
@@ -336,7 +354,66 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                     af[(size_t)lo * gr.dim + d] = a;
                 }
         }
-        for (int64_t p = 0; p < (pre ? 0 : N); p++) {
+        // cube stencil: a = G grad T at the node; the backward characteristic
+        // p - a / max|a| leaves the 3x3x3 cube on the dominant axis's face,
+        // where the value is interpolated on the Kuhn simplex holding it:
+        // axes sorted by r_d = |a_d| / max|a| (descending, ties to the lower
+        // axis), vertices the partial sums of the upstream steps, couplings
+        // r_(t) - r_(t+1) (the last r_(dim)).  An axis whose upstream
+        // neighbour is outside the grid has its component set to 0 first.
+        for (int64_t p = 0; p < (pre || !cube ? 0 : N); p++) {
+            double a[3] = {0.0, 0.0, 0.0}, r[3] = {0.0, 0.0, 0.0};
+            int up[3] = {0, 0, 0};
+            double amax = 0.0;
+            for (int d = 0; d < gr.dim; d++) {
+                double acc = 0.0;
+                for (int dp = 0; dp < gr.dim; dp++) {
+                    const double term = metric(gr, p, d, dp) * nd[(size_t)p * gr.dim + dp];
+                    acc = dp == 0 ? term : acc + term;
+                }
+                up[d] = acc > 0.0 ? -1 : (acc < 0.0 ? 1 : 0);
+                const int64_t c = coord(gr, p, d) + up[d];
+                if (c < 0 || c > gr.n[d] - 1) { acc = 0.0; up[d] = 0; }
+                a[d] = acc;
+                amax = std::max(amax, std::fabs(acc));
+            }
+            uint32_t mask = 0;
+            double acc = 0.0;
+            if (!ident[p] && amax > 0.0) {
+                int ord[3] = {0, 1, 2};
+                for (int d = 0; d < gr.dim; d++) r[d] = std::fabs(a[d]) / amax;
+                for (int i = 1; i < gr.dim; i++)
+                    for (int j = i; j > 0 && r[ord[j - 1]] < r[ord[j]]; j--) std::swap(ord[j - 1], ord[j]);
+                int o[3] = {0, 0, 0}, vs[3];
+                double vc[3];
+                int nv = 0;
+                for (int t = 0; t < gr.dim; t++) {
+                    o[ord[t]] += up[ord[t]];
+                    const double c = t + 1 < gr.dim ? r[ord[t]] - r[ord[t + 1]] : r[ord[t]];
+                    if (!(c > 0.0)) continue;
+                    const int b = (o[0] + 1) + 3 * (o[1] + 1) + 9 * (o[2] + 1);
+                    vs[nv] = b - (b > 13 ? 1 : 0);
+                    vc[nv++] = c;
+                }
+                for (int i = 1; i < nv; i++)         // ascending slot order
+                    for (int j = i; j > 0 && vs[j - 1] > vs[j]; j--) {
+                        std::swap(vs[j - 1], vs[j]);
+                        std::swap(vc[j - 1], vc[j]);
+                    }
+                double dsum = 0.0;
+                for (int i = 0; i < nv; i++) dsum = dsum + vc[i];
+                for (int i = 0; i < nv; i++) {
+                    const double w = vc[i] / dsum;
+                    st->wrow[(size_t)p * 3 + i] = w;
+                    mask |= 1u << vs[i];
+                    acc = acc + w * T[nbr(gr, p, vs[i])];
+                    E++;
+                }
+            }
+            st->pmask[p] = mask;
+            st->cal[p] = (T[p] - acc) / s[p];
+        }
+        for (int64_t p = 0; p < (pre || cube ? 0 : N); p++) {
             double c6[6] = {0, 0, 0, 0, 0, 0};
             for (int slot = 0; slot < nslot; slot++) {
                 if (!has_nbr(gr, p, slot)) continue;
@@ -352,14 +429,14 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             double dsum = 0.0;
             for (int slot = 0; slot < nslot; slot++) dsum = dsum + c6[slot];
             double acc = 0.0;
-            uint8_t mask = 0;
+            uint32_t mask = 0;
             if (!ident[p] && dsum > 0.0) {
                 for (int slot = 0; slot < nslot; slot++) {
                     if (c6[slot] > 0.0) {
                         double w = c6[slot] / dsum;
                         if (w > 0.0) {
-                            st->w6[(size_t)p * 6 + slot] = w;
-                            mask |= (uint8_t)(1u << slot);
+                            st->wrow[(size_t)p * 6 + slot] = w;
+                            mask |= 1u << slot;
                             acc = acc + w * T[nbr(gr, p, slot)];
                             E++;
                         }
@@ -374,9 +451,9 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             for (int32_t p : st->pk.seed_node) st->cal[p] = 0.0;   // their right-hand side is the seed row
         st->smask.assign(N, 0);
         for (int64_t p = 0; p < N; p++) {
-            uint8_t m = st->pmask[p];
+            uint32_t m = st->pmask[p];
             for (int slot = 0; slot < nslot; slot++)
-                if (m & (1u << slot)) st->smask[nbr(gr, p, slot)] |= (uint8_t)(1u << (slot ^ 1));
+                if (m & (1u << slot)) st->smask[nbr(gr, p, slot)] |= 1u << opposite(gr, slot);
         }
 
         // ---- 3-4: SCCs by iterative Tarjan over predecessor edges ----
@@ -464,7 +541,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             uint8_t un = nontrivial ? 1 : 0;
             for (int32_t m = st->cptr[c]; m < st->cptr[c + 1]; m++) {
                 int32_t v = st->cnodes[m];
-                uint8_t pm = st->pmask[v];
+                uint32_t pm = st->pmask[v];
                 for (int slot = 0; slot < nslot; slot++) {
                     if (!(pm & (1u << slot))) continue;
                     int32_t u = (int32_t)nbr(gr, v, slot);
@@ -482,7 +559,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             int32_t lev = 0;
             for (int32_t m = st->cptr[c]; m < st->cptr[c + 1]; m++) {
                 int32_t v = st->cnodes[m];
-                uint8_t sm = st->smask[v];
+                uint32_t sm = st->smask[v];
                 for (int slot = 0; slot < nslot; slot++) {
                     if (!(sm & (1u << slot))) continue;
                     int32_t cu = st->comp[nbr(gr, v, slot)];
@@ -536,13 +613,13 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             std::vector<double> wv;
             for (int32_t i = 0; i < k; i++) {
                 const int32_t v = mem[i];
-                const uint8_t pm = st->pmask[v];
+                const uint32_t pm = st->pmask[v];
                 std::vector<std::pair<int32_t, double>> row;
                 for (int slot = 0; slot < nslot; slot++) {
                     if (!(pm & (1u << slot))) continue;
                     const int32_t u = (int32_t)nbr(gr, v, slot);
                     if (st->comp[u] != c) continue;
-                    row.push_back({(int32_t)(std::lower_bound(mem, mem + k, u) - mem), st->w6[(size_t)v * 6 + slot]});
+                    row.push_back({(int32_t)(std::lower_bound(mem, mem + k, u) - mem), st->weight(v, slot)});
                 }
                 std::sort(row.begin(), row.end());
                 for (auto& e : row) { cl.push_back(e.first); wv.push_back(e.second); }
@@ -626,13 +703,13 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 for (int32_t i = 0; i < k; i++) {
                     int32_t v = mem[i];
                     a[(size_t)i * k + i] = 1.0;
-                    uint8_t pm = st->pmask[v];
+                    uint32_t pm = st->pmask[v];
                     for (int slot = 0; slot < nslot; slot++) {
                         if (!(pm & (1u << slot))) continue;
                         int32_t u = (int32_t)nbr(gr, v, slot);
                         if (st->comp[u] != c) continue;
                         int32_t j = (int32_t)(std::lower_bound(mem, mem + k, u) - mem);
-                        a[(size_t)i * k + j] -= st->w6[(size_t)v * 6 + slot];
+                        a[(size_t)i * k + j] -= st->weight(v, slot);
                     }
                 }
                 double norm = 0.0;
@@ -656,13 +733,13 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                     for (int32_t i = 0; i < k; i++) {
                         const int32_t v = mem[i];
                         double r = x[(size_t)i * k + j] - (i == j ? 1.0 : 0.0);
-                        const uint8_t pm = st->pmask[v];
+                        const uint32_t pm = st->pmask[v];
                         for (int slot = 0; slot < nslot; slot++) {
                             if (!(pm & (1u << slot))) continue;
                             const int32_t u = (int32_t)nbr(gr, v, slot);
                             if (st->comp[u] != c) continue;
                             const int32_t m = (int32_t)(std::lower_bound(mem, mem + k, u) - mem);
-                            r -= st->w6[(size_t)v * 6 + slot] * x[(size_t)m * k + j];
+                            r -= st->weight(v, slot) * x[(size_t)m * k + j];
                         }
                         blk_residual = std::max(blk_residual, std::fabs(r));
                     }
@@ -679,7 +756,8 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         auto pack_direction = [&](bool fwd, std::vector<uint64_t>& meta, std::vector<double>& wts,
                                   std::vector<int32_t>& lvl_ptr, std::vector<int32_t>& lvl_nsc,
                                   std::vector<int32_t>& blk_ptr, std::vector<int32_t>& blk_id,
-                                  std::vector<int32_t>& blk_pos, std::vector<int32_t>& pos_of, int32_t L) {
+                                  std::vector<int32_t>& blk_pos, std::vector<int32_t>& pos_of, int32_t L,
+                                  std::vector<int32_t>& ovf_pos) {
             const std::vector<int32_t>& clev = fwd ? st->clev_f : st->clev_r;
             // an off-grid source's seed nodes take no part in the forward walk
             // (a pass before it writes their values): they get the last
@@ -751,7 +829,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             meta.assign(N, 0);
             wts.assign((size_t)N * 4, 0.0);
             auto external = [&](int32_t v, int slot, int32_t cv_) {
-                const uint8_t full = fwd ? st->pmask[v] : st->smask[v];
+                const uint32_t full = fwd ? st->pmask[v] : st->smask[v];
                 if (!(full & (1u << slot))) return false;
                 return st->comp[(int32_t)nbr(gr, v, slot)] != cv_;   // not internal to the block
             };
@@ -764,10 +842,12 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             }
             for (int64_t q = 0; q < N; q++) off_at[q + 1] += off_at[q];
             std::vector<double> ovf((size_t)off_at[N], 0.0);
+            if (cube) ovf_pos.assign(N, 0);
+            else ovf_pos.clear();
             for (int64_t p = 0; p < N; p++) {
                 const int32_t v = (int32_t)p, cv_ = st->comp[v];
                 const int64_t q = pos_of[v];
-                uint8_t mask = 0;
+                uint32_t mask = 0;
                 double* rec = wts.data() + (size_t)q * 4;
                 rec[0] = st->cal[v];
                 int t = 0;
@@ -775,12 +855,18 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 for (int slot = 0; slot < nslot; slot++) {
                     if (!external(v, slot, cv_)) continue;
                     const int32_t u = (int32_t)nbr(gr, v, slot);
-                    mask |= (uint8_t)(1u << slot);
+                    mask |= 1u << slot;
                     // forward: w_{v,u}; reverse: u is a successor, weight w_{u,v}
-                    const double w = fwd ? st->w6[(size_t)v * 6 + slot] : st->w6[(size_t)u * 6 + (slot ^ 1)];
+                    const double w = fwd ? st->weight(v, slot) : st->weight(u, opposite(gr, slot));
                     if (t < 3) rec[1 + t] = w;
                     else ovf[(size_t)(off + (t - 3))] = w;
                     t++;
+                }
+                if (cube) {
+                    if (off > INT32_MAX) throw std::length_error("record overflow area too large");
+                    ovf_pos[q] = (int32_t)off;
+                    meta[q] = (uint64_t)(uint32_t)v | ((uint64_t)mask << kCubeMaskShift);
+                    continue;
                 }
                 if (off > (int64_t)kOffMask) throw std::length_error("record overflow area too large");
                 meta[q] = (uint64_t)(uint32_t)v | ((uint64_t)off << kOffShift) | ((uint64_t)mask << kMaskShift);
@@ -792,9 +878,9 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         pk.L_f = L_f;
         pk.L_r = L_r;
         pack_direction(true, pk.fmeta, pk.fwts, pk.flvl_ptr, pk.flvl_nsc, pk.fblk_ptr, pk.fblk_id,
-                       pk.blk_fpos, fpos_of, L_f);
+                       pk.blk_fpos, fpos_of, L_f, pk.fovf);
         pack_direction(false, pk.rmeta, pk.rwts, pk.rlvl_ptr, pk.rlvl_nsc, pk.rblk_ptr, pk.rblk_id,
-                       pk.blk_rpos, rpos_of, L_r);
+                       pk.blk_rpos, rpos_of, L_r, pk.rovf);
         pk.cal_nat = st->cal;
 
         // receivers (P_alpha, Section 4.4): the entries of each receiver in
@@ -963,7 +1049,7 @@ void pack_natural(const HostState* st, bool fwd, std::vector<uint64_t>& meta, st
     rec.assign((size_t)N * 4, 0.0);
     std::vector<double> ovf;
     for (int64_t v = 0; v < N; v++) {
-        uint8_t mask = fwd ? st->pmask[v] : st->smask[v];
+        uint32_t mask = fwd ? st->pmask[v] : st->smask[v];
         double* r = rec.data() + (size_t)v * 4;
         r[0] = st->cal[v];
         int t = 0;
@@ -972,7 +1058,7 @@ void pack_natural(const HostState* st, bool fwd, std::vector<uint64_t>& meta, st
             if (!(mask & (1u << slot))) continue;
             int axis = slot >> 1;
             int64_t u = (slot & 1) ? v + st->stride[axis] : v - st->stride[axis];
-            double w = fwd ? st->w6[(size_t)v * 6 + slot] : st->w6[(size_t)u * 6 + (slot ^ 1)];
+            double w = fwd ? st->weight(v, slot) : st->weight(u, slot ^ 1);
             if (t < 3) {
                 r[1 + t] = w;
             } else {

@@ -146,6 +146,10 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     if (g->n1 < 1 || g->n2 < 1 || g->n3 < 1) { set_error("grid sizes must be >= 1"); return FM_EINVAL; }
     if (g->dim == 2 && g->n2 != 1) { set_error("2-D grids need n2 == 1"); return FM_EINVAL; }
     if (k_per_rcv < 1) { set_error("entries per receiver must be >= 1"); return FM_EINVAL; }
+    if (g->stencil != 0 && g->stencil != 6) {
+        set_error("the GPU setup pass builds face-stencil states only (stencil %d)", g->stencil);
+        return FM_EINVAL;
+    }
     if ((uintptr_t)T_dev & 7u) { set_error("T must be 8-byte aligned"); return FM_EINVAL; }
     SetupDims d{};
     d.dim = g->dim;

@@ -169,6 +169,23 @@ __device__ __forceinline__ uint32_t nbr_row(uint32_t row, int slot, int32_t a0, 
     return row + (uint32_t)((slot & 1) ? m : -m);
 }
 
+// Cube-stencil slot b: the offset o in {-1,0,1}^3 whose base-3 number
+// (o_0 + 1) + 3 (o_1 + 1) + 9 (o_2 + 1), centre left out, is b.
+__device__ __forceinline__ uint32_t nbr_row_cube(uint32_t row, int slot, int32_t a0, int32_t a1, int32_t a2) {
+    const int b = slot + (slot >= 13 ? 1 : 0);
+    const int q = (b * 11) >> 5;          // b / 3 for 0 <= b < 27
+    const int o0 = b - 3 * q - 1;
+    const int q2 = (q * 11) >> 5;         // q / 3
+    const int o1 = q - 3 * q2 - 1;
+    const int o2 = q2 - 1;
+    return row + (uint32_t)(o0 * a0 + o1 * a1 + o2 * a2);
+}
+
+template <bool CUBE>
+__device__ __forceinline__ uint32_t nbr_at(uint32_t row, int slot, const Strides32& sx) {
+    return CUBE ? nbr_row_cube(row, slot, sx.a0, sx.a1, sx.a2) : nbr_row(row, slot, sx.a0, sx.a1, sx.a2);
+}
+
 template <typename V, int VW>
 __device__ __forceinline__ Pack<V, VW> ldb(const char* base, uint32_t off) {
     return ld<V, VW>(reinterpret_cast<const V*>(base + off));
@@ -188,15 +205,22 @@ struct RcvLds {
     bool on;
 };
 
-template <int DIR, typename V, int VW>
+template <int DIR, typename V, int VW, bool CUBE>
 __device__ __forceinline__ void fetch32(Node32<V, VW>& p, uint64_t m, int pos, const char* __restrict__ wtc,
                                         const char* __restrict__ inc, uint32_t rowb, uint32_t xrowb, uint32_t lane_off,
                                         const Ctx& cx, const SrcDev& sd, const LevelDesc& d, const V* in,
                                         const RcvLds& rl) {
     const uint32_t node = (uint32_t)(m & kNodeMask);
     p.row = node * xrowb + lane_off;
-    p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
-    p.mask = (uint32_t)(m >> kMaskShift);
+    if (CUBE) {
+        // 26-bit mask; the overflow offset of a node with more than three
+        // neighbours is in the per-position array
+        p.mask = (uint32_t)((m >> kCubeMaskShift) & kCubeMask);
+        p.ovf = __builtin_popcount(p.mask) > 3 ? (uint32_t)gld((DIR == kFwd ? sd.fovf : sd.rovf) + pos) : 0u;
+    } else {
+        p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
+        p.mask = (uint32_t)(m >> kMaskShift);
+    }
     p.rec = ldb_stream<V, 4>(wtc, (uint32_t)pos * (uint32_t)(4 * sizeof(V)));
     if (DIR == kFwd || !cx.rcv_in) {
         p.inp = ldb_stream<V, VW>(inc, node * rowb + lane_off);
@@ -235,13 +259,13 @@ __device__ __forceinline__ void rcv_add(Node32<V, VW>& p, int pos, const LevelDe
     }
 }
 
-template <typename V, int VW>
+template <typename V, int VW, bool CUBE>
 __device__ __forceinline__ void nbrs32(const Node32<V, VW>& p, const char* __restrict__ Xc, const Strides32 sx,
                                        Pack<V, VW> xv[3]) {
     uint32_t m = p.mask;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-        if (m != 0u) xv[t] = ldb<V, VW>(Xc, nbr_row(p.row, __builtin_ctz(m), sx.a0, sx.a1, sx.a2));
+        if (m != 0u) xv[t] = ldb<V, VW>(Xc, nbr_at<CUBE>(p.row, __builtin_ctz(m), sx));
         m &= m - 1u;
     }
 }
@@ -249,7 +273,7 @@ __device__ __forceinline__ void nbrs32(const Node32<V, VW>& p, const char* __res
 // x_node = c*ds + sum_j w_j x_j (primal) or r + sum_i w_i lambda_i
 // (transpose) in ascending slot order (the order of the rhs-group kernel,
 // hence the same bits); neighbours past the third (rare) are loaded here.
-template <int DIR, typename V, int VW, typename T>
+template <int DIR, typename V, int VW, typename T, bool CUBE>
 __device__ __forceinline__ void acc32(const Node32<V, VW>& p, const Pack<V, VW> xv[3], const V* __restrict__ ovf_base,
                                       const char* __restrict__ Xc, const Strides32 sx, T acc[VW]) {
     uint32_t m = p.mask;
@@ -264,7 +288,7 @@ __device__ __forceinline__ void acc32(const Node32<V, VW>& p, const Pack<V, VW> 
         m &= m - 1u;
     }
     for (int t = 3; m != 0u; ++t) {
-        const Pack<V, VW> x = ldb<V, VW>(Xc, nbr_row(p.row, __builtin_ctz(m), sx.a0, sx.a1, sx.a2));
+        const Pack<V, VW> x = ldb<V, VW>(Xc, nbr_at<CUBE>(p.row, __builtin_ctz(m), sx));
         m &= m - 1u;
         const T w = (T)gld(ovf_base + p.ovf + (t - 3));
 #pragma unroll
@@ -275,7 +299,7 @@ __device__ __forceinline__ void acc32(const Node32<V, VW>& p, const Pack<V, VW> 
 // Phase 1 of the level's blocks: b_C of this workgroup's share of every
 // block's members into the staging rows (LPN lanes per member), summed in
 // FP64 whatever the vector precision.
-template <int DIR, typename V, int LPN, int NT>
+template <int DIR, typename V, int LPN, int NT, bool CUBE>
 __device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDesc& d, const uint64_t* __restrict__ meta,
                                                 const char* __restrict__ wtc, const char* __restrict__ inc,
                                                 const V* __restrict__ in, const V* __restrict__ ovf_base,
@@ -294,13 +318,13 @@ __device__ __forceinline__ void split_block_rhs(const SrcDev& sd, const LevelDes
         share(k, P, part, lo, hi);
         for (int mi = lo + slot0; mi < hi; mi += SLOTS) {
             Node32<V, VW> p;
-            fetch32<DIR, V, VW>(p, ld_meta(meta + bp + mi), bp + mi, wtc, inc, ROWB, xrowb, lane_off, cx, sd, d, in,
+            fetch32<DIR, V, VW, CUBE>(p, ld_meta(meta + bp + mi), bp + mi, wtc, inc, ROWB, xrowb, lane_off, cx, sd, d, in,
                                 rl);
             Pack<V, VW> xv[3];
-            nbrs32<V, VW>(p, Xc, sx, xv);
+            nbrs32<V, VW, CUBE>(p, Xc, sx, xv);
             if (DIR == kRev && cx.rcv_in && rl.on) rcv_add<V, VW>(p, bp + mi, d, rl, cx.B, cx.rhs0);
             Pack<double, VW> o;
-            acc32<DIR, V, VW, double>(p, xv, ovf_base, Xc, sx, o.v);
+            acc32<DIR, V, VW, double, CUBE>(p, xv, ovf_base, Xc, sx, o.v);
             st<double, VW>(stage + (moff + mi) * SB + cx.rhs0, o);
         }
     }
@@ -569,7 +593,8 @@ __device__ __forceinline__ void cursor_next(Cursor& c, const SrcDev& sd, int L, 
     }
 }
 
-// RCV (transpose only): input given at the receivers.  The two input modes
+// MODE bit 0 (transpose only): input given at the receivers; bit 1: the
+// records of a cube-stencil state (26-bit neighbour masks).  The two input modes
 // are separate kernels; with a run-time choice between them inside the batch
 // loop the compiler placed its memory waits for one path only, and the
 // receiver path ran 15 % slower.  (The optional per-source output stays a
@@ -577,9 +602,10 @@ __device__ __forceinline__ void cursor_next(Cursor& c, const SrcDev& sd, int L, 
 // At least two waves per SIMD (at most 256 registers per lane), so that two
 // 256-thread workgroups of different sources share a CU and one streams
 // while the other waits at a level barrier.
-template <int DIR, typename V, int LPN, int NT, int U, int RCV_>
+template <int DIR, typename V, int LPN, int NT, int U, int MODE>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_split(ApplyArgs a, SplitArgs s) {
-    constexpr bool RCV = DIR == kRev && RCV_ != 0;
+    constexpr bool RCV = DIR == kRev && (MODE & 1) != 0;
+    constexpr bool CUBE = (MODE & 2) != 0;   // 26-neighbour stencil records
     constexpr int VW = 16 / (int)sizeof(V);
     constexpr int B = LPN * VW;
     constexpr int SLOTS = NT / LPN;
@@ -619,6 +645,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
     cx.st2 = a.st2;
     cx.N = a.N;
     cx.rcv_in = RCV;
+    cx.cube = CUBE;
     const V* __restrict__ in;
     // node values: rows of a.xB >= B values (padded to whole 128-byte lines
     // when the array is the batch's own scratch, so no line holds two nodes)
@@ -707,7 +734,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
         for (int q = 0; q < U; ++q) {
             ops[q].ok = mw[q] != ~0ull;
             if (ops[q].ok)
-                fetch32<DIR, V, VW>(ops[q], mw[q], c.d.p0 + c.base + slot0 + q * SLOTS, wtc, inc, ROWB, XROWB, lane_off, cx,
+                fetch32<DIR, V, VW, CUBE>(ops[q], mw[q], c.d.p0 + c.base + slot0 + q * SLOTS, wtc, inc, ROWB, XROWB, lane_off, cx,
                                     sd, c.d, in, rl);
         }
     };
@@ -723,7 +750,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             if (!pre) fetch_batch(cC, mC);
 #pragma unroll
             for (int q = 0; q < U; ++q)
-                if (ops[q].ok) nbrs32<V, VW>(ops[q], Xc, sx, xv[q]);
+                if (ops[q].ok) nbrs32<V, VW, CUBE>(ops[q], Xc, sx, xv[q]);
             if (RCV && rl.on) {
 #pragma unroll
                 for (int q = 0; q < U; ++q)
@@ -738,7 +765,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
                 ook[q] = ops[q].ok;
                 orow[q] = ops[q].row;
                 oscale[q] = ops[q].rec.v[0];
-                if (ook[q]) acc32<DIR, V, VW, V>(ops[q], xv[q], ovf_base, Xc, sx, o[q].v);
+                if (ook[q]) acc32<DIR, V, VW, V, CUBE>(ops[q], xv[q], ovf_base, Xc, sx, o[q].v);
             }
             // The next level's first batch reads records and inputs that no
             // level writes.  At the end of a level without blocks they are
@@ -764,7 +791,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2))) void k_
             // a level with blocks fetches the next level's first batch after
             // its block products (that state is not kept live across them)
             if (blocks)
-                split_block_rhs<DIR, V, LPN, NT>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, XROWB, lane_off, stage,
+                split_block_rhs<DIR, V, LPN, NT, CUBE>(sd, cC.d, meta, wtc, inc, in, ovf_base, Xc, sx, XROWB, lane_off, stage,
                                                  SB, cx, P, part, slot0, rl);
             group_barrier(g, P);
             if (first) {

@@ -66,11 +66,21 @@ struct Ctx {
     int64_t st1, st2;
     int64_t N;
     bool rcv_in;            // transpose input given at receivers
+    bool cube;              // cube-stencil records (26-bit masks)
 };
 
 __device__ __forceinline__ int64_t slot_off(int slot, int64_t st1, int64_t st2) {
     int64_t st = (slot >> 1) == 0 ? 1 : ((slot >> 1) == 1 ? st1 : st2);
     return (slot & 1) ? st : -st;
+}
+
+// Cube-stencil slot b: node offset of the logical offset o in {-1,0,1}^3
+// whose base-3 number (o_0 + 1) + 3 (o_1 + 1) + 9 (o_2 + 1), centre left
+// out, is b.
+__device__ __forceinline__ int64_t cube_slot_off(int slot, int64_t st1, int64_t st2) {
+    const int b = slot + (slot >= 13 ? 1 : 0);
+    const int o0 = b % 3 - 1, o1 = (b / 3) % 3 - 1, o2 = b / 9 - 1;
+    return (int64_t)o0 + (int64_t)o1 * st1 + (int64_t)o2 * st2;
 }
 
 // Everything one lane needs for one node of a traversal step.
@@ -89,8 +99,13 @@ __device__ __forceinline__ void fetch_static(NodeOps<V, VW>& p, uint64_t m, int 
                                              const V* __restrict__ in, const Ctx& cx, const SrcDev& sd,
                                              const LevelDesc& d) {
     p.node = (int64_t)(m & kNodeMask);
-    p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
-    p.mask = (uint32_t)(m >> kMaskShift);
+    if (cx.cube) {
+        p.mask = (uint32_t)((m >> kCubeMaskShift) & kCubeMask);
+        p.ovf = __builtin_popcount(p.mask) > 3 ? (uint32_t)(DIR == kFwd ? sd.fovf : sd.rovf)[pos] : 0u;
+    } else {
+        p.ovf = (uint32_t)((m >> kOffShift) & kOffMask);
+        p.mask = (uint32_t)(m >> kMaskShift);
+    }
     p.rec = ld<V, 4>(wts + (size_t)pos * 4);
     if (DIR == kFwd || !cx.rcv_in) {
         p.inp = ld<V, VW>(in + p.node * cx.B + cx.rhs0);
@@ -113,6 +128,21 @@ __device__ __forceinline__ void fetch_static(NodeOps<V, VW>& p, uint64_t m, int 
 template <int DIR, typename V, int VW, typename T>
 __device__ __forceinline__ void combine(const NodeOps<V, VW>& p, const V* __restrict__ ovf_base,
                                         const V* __restrict__ X, const Ctx& cx, T acc[VW]) {
+    if (cx.cube) {
+        // the k-th set bit (ascending slot) takes the k-th weight
+#pragma unroll
+        for (int v = 0; v < VW; ++v) acc[v] = (DIR == kFwd) ? (T)p.rec.v[0] * (T)p.inp.v[v] : (T)p.inp.v[v];
+        uint32_t m = p.mask;
+        for (int t = 0; m != 0u; ++t) {
+            const int s = __builtin_ctz(m);
+            m &= m - 1u;
+            const Pack<V, VW> x = ld<V, VW>(X + (p.node + cube_slot_off(s, cx.st1, cx.st2)) * cx.B + cx.rhs0);
+            const V w = t == 0 ? p.rec.v[1] : (t == 1 ? p.rec.v[2] : (t == 2 ? p.rec.v[3] : ovf_base[p.ovf + (t - 3)]));
+#pragma unroll
+            for (int v = 0; v < VW; ++v) acc[v] += (T)w * (T)x.v[v];
+        }
+        return;
+    }
     Pack<V, VW> xv[kSlots];
 #pragma unroll
     for (int s = 0; s < kSlots; ++s)
@@ -267,6 +297,7 @@ __global__ __launch_bounds__(NT) void k_sweep(ApplyArgs a) {
     cx.st2 = a.st2;
     cx.N = a.N;
     cx.rcv_in = DIR == kRev && a.in_mode == FM_W_RECEIVERS;
+    cx.cube = a.cube != 0;
     const V* __restrict__ in;
     V* __restrict__ X = (V*)a.work + (size_t)alpha * NB;
     V* __restrict__ outp = nullptr;

@@ -28,7 +28,8 @@ def rel_l2(x, ref):
 def states_for(fm, wl, S=None):
     S = wl.S if S is None else S
     return fm.build_frozen_states(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T[:S], wl.s, wl.src[:S],
-                                  wl.rcv, nthreads=8, rcv_weights=getattr(wl, "rcv_w", None))
+                                  wl.rcv, nthreads=8, rcv_weights=getattr(wl, "rcv_w", None),
+                                  stencil=getattr(wl, "stencil", 6))
 
 
 def oracle_ops(wl, S=None):

@@ -31,7 +31,8 @@ def test_library_exports_every_declared_symbol():
 
 
 def _state(wl, a=0):
-    return fm.build_frozen_state(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T[a], wl.s, int(wl.src[a]), wl.rcv)
+    return fm.build_frozen_state(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T[a], wl.s, int(wl.src[a]), wl.rcv,
+                                 stencil=getattr(wl, "stencil", 6))
 
 
 def _compare_operator(wl, a=0):

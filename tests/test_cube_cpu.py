@@ -1,0 +1,61 @@
+"""The 26-neighbour (cube) stencil through the C ABI on the CPU (no GPU
+calls): the host setup's W and c are bit-identical to the oracle's cube
+assembly (same FP64 operations in the same order), and its SCC partition,
+condensation levels and structural statistics match the oracle's graph
+diagnostics, on 2-D and 3-D deformed grids, the curved-wavefront fixture and
+c3; an unknown stencil value is rejected.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from test_abi_cpu import _compare_graph, _compare_operator
+
+fm = pytest.importorskip("paper_2609_14982_amd")
+
+
+def _cube(wl):
+    wl.stencil = 26
+    return wl
+
+
+def test_cube_setup_matches_oracle_c1():
+    wl = _cube(W.config("c1"))
+    st, op = _compare_operator(wl)
+    _compare_graph(st, op, wl.T[0])
+    # dependencies beyond the faces occur (corner neighbours in 2-D)
+    rowptr, col, _, _ = st.export_operator()
+    rows = np.repeat(np.arange(wl.N), np.diff(rowptr))
+    d = np.abs(col - rows)
+    assert np.any((d != 1) & (d != wl.n1))
+
+
+@pytest.mark.parametrize("n", [(21, 21, 13), (41, 41, 25)])
+def test_cube_setup_matches_oracle_curved(n):
+    wl = _cube(W.curved_state(*n, A=500.0, eps_T=0.05))
+    st, op = _compare_operator(wl)
+    _compare_graph(st, op, wl.T[0])
+    print("cube stencil, curved", n, {k: st.stats()[k] for k in ("E", "n_scc", "largest_scc", "levels_fwd")})
+
+
+def test_cube_setup_matches_oracle_deformed_3d():
+    wl = _cube(W.smooth_3d(25, 23, 13, topo_amp=0.2))
+    st, op = _compare_operator(wl)
+    _compare_graph(st, op, wl.T[0])
+
+
+@pytest.mark.slow
+def test_cube_setup_matches_oracle_c3_one_source():
+    wl = _cube(W.config("c3"))
+    st, op = _compare_operator(wl, 3)
+    _compare_graph(st, op, wl.T[3])
+    print("cube stencil, c3 source 3", st.stats())
+
+
+def test_unknown_stencil_is_rejected():
+    wl = W.config("c1")
+    for bad in (5, 8, 27, -1):
+        with pytest.raises(fm.FmError) as e:
+            fm.build_frozen_state(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T[0], wl.s, int(wl.src[0]), wl.rcv,
+                                  stencil=bad)
+        assert e.value.code == fm.binding.FM_EINVAL and "stencil" in str(e.value)

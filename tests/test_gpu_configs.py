@@ -1,8 +1,9 @@
 """Parity of the remaining benchmark configurations against the oracle:
 
 * c2 (401 x 201 2-D deformed grid, 16 sources x 32 rhs, 100 receivers),
-  FP64 (32 rhs per node take the rhs-group kernel) and FP32 (the node split,
-  four values per 16-byte lane access): J from a broadcast model block to
+  FP64 (the node split with 16 lanes per node, and the rhs-group kernel) and
+  FP32 (the node split, four values per 16-byte lane access): J from a
+  broadcast model block to
   receivers and the source-summed J^T from receiver data, against SuperLU
   solves of the explicit operator (FP64 bar 1e-11, FP32 bar 1e-4), and the
   transpose pairing;
