@@ -279,7 +279,9 @@ int fm_state_export_operator(const fm_state* st, int64_t* rowptr, int32_t* col, 
 
 /*
  * Copy the graph analysis out: comp [N] SCC id (ids number the components in
- * a topological order of the condensation DAG), level_fwd [N] and level_rev [N]
+ * ascending forward level, then by smallest member node: a topological order
+ * of the condensation DAG that both setup paths share), level_fwd [N] and
+ * level_rev [N]
  * (longest-path level of the node's component from the sources / towards the
  * sinks of the condensation DAG).  Any pointer may be NULL.
  */

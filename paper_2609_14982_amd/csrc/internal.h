@@ -135,11 +135,24 @@ struct PointSource {
 // Couplings computed elsewhere (the GPU setup pass) for an on-grid source:
 // pmask [N], w6 [N][6], cal [N] exactly as parts 1-2 of build_state write
 // them, and the count of violating edges (T_j > T_i over the edges j -> i).
+// Optionally the graph work too: trim [N] marks the nodes that Kahn's
+// elimination removes forward (bit 0: not on or downstream of a cycle) and
+// backward (bit 1: not on or upstream of one), so the SCC search runs on
+// the rest only (every cycle lies in it); levels() then computes the
+// longest-path levels of the condensation DAG for the partition given as
+// comp [N] (ncomp components, members cnodes[cptr[c] .. cptr[c+1])), with
+// the predecessor / successor masks, into clev_f / clev_r [ncomp];
+// it returns FM_OK or an FM_E* code with the message set.
 struct Assembled {
     const uint8_t* pmask;
     const double* w6;
     const double* cal;
     int64_t n_vio;
+    const uint8_t* trim = nullptr;
+    int (*levels)(void* ctx, int64_t N, int32_t ncomp, const int32_t* comp, const int32_t* cptr,
+                  const int32_t* cnodes, const uint32_t* pmask, const uint32_t* smask, int32_t* clev_f,
+                  int32_t* clev_r) = nullptr;
+    void* ctx = nullptr;
 };
 
 struct DeviceState;   // defined in the HIP translation unit
@@ -173,7 +186,7 @@ struct HostState {
     }
     int opposite(int slot) const { return stencil == 26 ? 25 - slot : slot ^ 1; }
     // graph
-    std::vector<int32_t> comp;      // component id, numbered in topological order
+    std::vector<int32_t> comp;      // component id: ascending forward level, then smallest member
     int32_t ncomp = 0;
     std::vector<int32_t> cptr, cnodes;      // members per component (ascending node id)
     std::vector<int32_t> clev_f, clev_r;    // per component

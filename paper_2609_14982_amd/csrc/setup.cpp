@@ -470,8 +470,17 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         cs.reserve(1024);
         st->comp.assign(N, -1);
         int32_t counter = 0, ncomp = 0;
+        // with a trim from the GPU setup pass the search runs on the nodes
+        // that neither elimination removed (every cycle lies among them);
+        // every other node is its own component
+        const uint8_t* trim = pre && pre->levels ? pre->trim : nullptr;
         for (int64_t root = 0; root < N; root++) {
             if (idx[root] >= 0) continue;
+            if (trim && (trim[root] & 3)) {
+                idx[root] = counter++;
+                st->comp[root] = ncomp++;
+                continue;
+            }
             idx[root] = low[root] = counter++;
             tstack.push_back((int32_t)root);
             onstk[root] = 1;
@@ -484,6 +493,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                     int slot = cs.back()++;
                     if (!(st->pmask[v] & (1u << slot))) continue;
                     int32_t u = (int32_t)nbr(gr, v, slot);
+                    if (trim && (trim[u] & 3)) continue;
                     if (idx[u] < 0) {
                         idx[u] = low[u] = counter++;
                         tstack.push_back(u);
@@ -535,7 +545,16 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         st->clev_r.assign(ncomp, 0);
         std::vector<uint8_t> unres(ncomp, 0);   // on or downstream of a cycle (Proposition 2)
         int64_t n_vio = 0;
-        for (int32_t c = 0; c < ncomp; c++) {
+        if (trim) {
+            // levels on the device; the nodes the forward elimination
+            // leaves are exactly those on or downstream of a cycle
+            int rc = pre->levels(pre->ctx, N, ncomp, st->comp.data(), st->cptr.data(), st->cnodes.data(),
+                                 st->pmask.data(), st->smask.data(), st->clev_f.data(), st->clev_r.data());
+            if (rc != FM_OK) { delete st; return rc; }
+            for (int64_t p = 0; p < N; p++)
+                if (!(trim[p] & 1)) unres[st->comp[p]] = 1;
+        }
+        for (int32_t c = 0; c < (trim ? 0 : ncomp); c++) {
             int32_t lev = 0;
             bool nontrivial = st->cptr[c + 1] - st->cptr[c] > 1;
             uint8_t un = nontrivial ? 1 : 0;
@@ -555,7 +574,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             st->clev_f[c] = lev;
             unres[c] = un;
         }
-        for (int32_t c = ncomp - 1; c >= 0; c--) {
+        for (int32_t c = trim ? -1 : ncomp - 1; c >= 0; c--) {
             int32_t lev = 0;
             for (int32_t m = st->cptr[c]; m < st->cptr[c + 1]; m++) {
                 int32_t v = st->cnodes[m];
@@ -574,6 +593,34 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         for (int32_t c = 0; c < ncomp; c++) {
             L_f = std::max(L_f, st->clev_f[c] + 1);
             L_r = std::max(L_r, st->clev_r[c] + 1);
+        }
+        // component ids in ascending forward level, then smallest member
+        // (a topological order that does not depend on how the SCCs were
+        // found): members, levels and flags follow the new ids
+        {
+            std::vector<int32_t> start(L_f + 1, 0), newid(ncomp, -1);
+            for (int32_t c = 0; c < ncomp; c++) start[st->clev_f[c] + 1]++;
+            for (int32_t l = 0; l < L_f; l++) start[l + 1] += start[l];
+            for (int64_t p = 0; p < N; p++) {
+                const int32_t c = st->comp[p];
+                if (newid[c] < 0) newid[c] = start[st->clev_f[c]]++;
+            }
+            std::vector<int32_t> lf(ncomp), lr(ncomp);
+            std::vector<uint8_t> un(ncomp);
+            for (int32_t c = 0; c < ncomp; c++) {
+                lf[newid[c]] = st->clev_f[c];
+                lr[newid[c]] = st->clev_r[c];
+                un[newid[c]] = unres[c];
+            }
+            st->clev_f.swap(lf);
+            st->clev_r.swap(lr);
+            unres.swap(un);
+            for (int64_t p = 0; p < N; p++) st->comp[p] = newid[st->comp[p]];
+            std::fill(st->cptr.begin(), st->cptr.end(), 0);
+            for (int64_t p = 0; p < N; p++) st->cptr[st->comp[p] + 1]++;
+            for (int32_t c = 0; c < ncomp; c++) st->cptr[c + 1] += st->cptr[c];
+            std::vector<int32_t> fill(st->cptr.begin(), st->cptr.end() - 1);
+            for (int64_t p = 0; p < N; p++) st->cnodes[fill[st->comp[p]]++] = (int32_t)p;
         }
 
         // ---- 6: factor every nontrivial block, keep A_C^{-1} ----
@@ -823,56 +870,61 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
             }
             // records: a fixed [c, w1, w2, w3] per position, further weights of
             // the rare nodes with more than three neighbours in an overflow area
-            // after the N fixed records, in position order; written walking
-            // the nodes in ascending id (the position order needs the
-            // overflow offsets first)
-            meta.assign(N, 0);
-            wts.assign((size_t)N * 4, 0.0);
-            auto external = [&](int32_t v, int slot, int32_t cv_) {
-                const uint32_t full = fwd ? st->pmask[v] : st->smask[v];
-                if (!(full & (1u << slot))) return false;
-                return st->comp[(int32_t)nbr(gr, v, slot)] != cv_;   // not internal to the block
-            };
+            // after the N fixed records, in position order.  First the
+            // external-neighbour masks in node order (a block member lists
+            // only neighbours outside its component) and the overflow counts
+            // per position, then the records in position order (sequential
+            // writes)
+            std::vector<uint32_t> extm((size_t)N);
             std::vector<int64_t> off_at((size_t)N + 1, 0);
             for (int64_t p = 0; p < N; p++) {
                 const int32_t v = (int32_t)p, cv_ = st->comp[v];
-                int t = 0;
-                for (int slot = 0; slot < nslot; slot++) t += external(v, slot, cv_) ? 1 : 0;
+                uint32_t full = fwd ? st->pmask[v] : st->smask[v], m = 0;
+                while (full) {
+                    const int slot = __builtin_ctz(full);
+                    full &= full - 1u;
+                    if (st->comp[(int32_t)nbr(gr, v, slot)] != cv_) m |= 1u << slot;
+                }
+                extm[v] = m;
+                const int t = __builtin_popcount(m);
                 off_at[(size_t)pos_of[v] + 1] = t > 3 ? t - 3 : 0;
             }
             for (int64_t q = 0; q < N; q++) off_at[q + 1] += off_at[q];
-            std::vector<double> ovf((size_t)off_at[N], 0.0);
-            if (cube) ovf_pos.assign(N, 0);
-            else ovf_pos.clear();
-            for (int64_t p = 0; p < N; p++) {
-                const int32_t v = (int32_t)p, cv_ = st->comp[v];
-                const int64_t q = pos_of[v];
-                uint32_t mask = 0;
+            if (cube) {
+                if (off_at[N] > INT32_MAX) throw std::length_error("record overflow area too large");
+                ovf_pos.assign(N, 0);
+            } else {
+                if (off_at[N] > (int64_t)kOffMask + 1) throw std::length_error("record overflow area too large");
+                ovf_pos.clear();
+            }
+            std::vector<int32_t> node_at((size_t)N);
+            for (int64_t p = 0; p < N; p++) node_at[pos_of[p]] = (int32_t)p;
+            meta.assign(N, 0);
+            wts.assign((size_t)N * 4 + (size_t)off_at[N] + 4, 0.0);
+            double* ovf = wts.data() + (size_t)N * 4;
+            for (int64_t q = 0; q < N; q++) {
+                const int32_t v = node_at[q];
+                const uint32_t mask = extm[v];
                 double* rec = wts.data() + (size_t)q * 4;
                 rec[0] = st->cal[v];
-                int t = 0;
                 const int64_t off = off_at[q] < off_at[q + 1] ? off_at[q] : 0;
-                for (int slot = 0; slot < nslot; slot++) {
-                    if (!external(v, slot, cv_)) continue;
-                    const int32_t u = (int32_t)nbr(gr, v, slot);
-                    mask |= 1u << slot;
+                uint32_t m = mask;
+                for (int t = 0; m; t++) {
+                    const int slot = __builtin_ctz(m);
+                    m &= m - 1u;
                     // forward: w_{v,u}; reverse: u is a successor, weight w_{u,v}
-                    const double w = fwd ? st->weight(v, slot) : st->weight(u, opposite(gr, slot));
+                    const double w = fwd ? st->weight(v, slot)
+                                         : st->weight((int32_t)nbr(gr, v, slot), opposite(gr, slot));
                     if (t < 3) rec[1 + t] = w;
                     else ovf[(size_t)(off + (t - 3))] = w;
-                    t++;
                 }
                 if (cube) {
-                    if (off > INT32_MAX) throw std::length_error("record overflow area too large");
                     ovf_pos[q] = (int32_t)off;
                     meta[q] = (uint64_t)(uint32_t)v | ((uint64_t)mask << kCubeMaskShift);
-                    continue;
+                } else {
+                    meta[q] = (uint64_t)(uint32_t)v | ((uint64_t)off << kOffShift) | ((uint64_t)mask << kMaskShift);
                 }
-                if (off > (int64_t)kOffMask) throw std::length_error("record overflow area too large");
-                meta[q] = (uint64_t)(uint32_t)v | ((uint64_t)off << kOffShift) | ((uint64_t)mask << kMaskShift);
             }
-            wts.insert(wts.end(), ovf.begin(), ovf.end());
-            wts.resize(wts.size() + 4, 0.0);
         };
         std::vector<int32_t> fpos_of, rpos_of;
         pk.L_f = L_f;

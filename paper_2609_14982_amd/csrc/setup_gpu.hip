@@ -1,4 +1,4 @@
-// The GPU setup pass (Algorithm 1, Phase I, lines 7-8): the couplings of
+// The GPU setup pass (Algorithm 1, Phase I: the frozen states): the couplings of
 // every source's frozen operator computed on the device, for all sources of
 // a batch at once, from traveltimes that are already there (the GPU
 // first-arrival solver's output, or an upload).
@@ -12,8 +12,13 @@
 // flows in), the calibration c_i = (T_i - sum_j w_ij T_j) / s_i, and the
 // count of violating edges (T_j > T_i for an edge j -> i).  Every product and
 // sum is rounded as written and in the host's order (-ffp-contract=off), so
-// the couplings equal the host's bit for bit; the host then finishes the
-// state (SCCs, levels, block factors, packing) from them.
+// the couplings equal the host's bit for bit.  Then the graph work: Kahn's
+// elimination forward and backward trims every node that is not both on or
+// downstream and on or upstream of a cycle (Section 3.5, Proposition 2), the
+// host finds the SCCs among the rest only, and the longest-path levels of
+// the condensation DAG in both directions come from Kahn's elimination over
+// the components on the device (Section 4.1); the host finishes the state
+// (block factors, packing) from them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -131,6 +136,299 @@ __global__ void k_setup_couplings(SetupDims g, int32_t S, const double* __restri
     }
 }
 
+// Successor masks from the predecessor masks: slot b of v is set when the
+// neighbour in slot b has v as a predecessor (its opposite slot set).
+__global__ void k_setup_smask(SetupDims g, int32_t S, const uint8_t* __restrict__ pmask, uint8_t* __restrict__ smask) {
+    const int nslot = 2 * g.dim;
+    const int64_t total = (int64_t)S * g.N;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t alpha = t / g.N, p = t - alpha * g.N;
+        const uint8_t* pm = pmask + alpha * g.N;
+        uint8_t m = 0;
+        for (int slot = 0; slot < nslot; slot++) {
+            const int d = slot >> 1;
+            const int64_t c = coord_of(g, p, d);
+            if ((slot & 1) ? c + 1 >= g.n[d] : c == 0) continue;
+            const int64_t q = (slot & 1) ? p + g.stride[d] : p - g.stride[d];
+            if (pm[q] & (1u << (slot ^ 1))) m |= (uint8_t)(1u << slot);
+        }
+        smask[t] = m;
+    }
+}
+
+// Kahn's elimination on one source per workgroup (Sections 3.5, 4.1): a
+// component whose external in-edges (predecessors for the forward order,
+// successors for the reverse one) are all eliminated joins the next
+// frontier; the round in which a component leaves the frontier is its
+// longest-path level.  Component ids: a node that is its own component has
+// its node id, the members of nontrivial component b share the id N + b
+// (IDENT: every node is its own component; the elimination then stops at
+// the cycles, and the nodes it never reaches keep level -1).  Frontiers are
+// compacted per wave: a ballot of the lanes that push, one LDS atomic for
+// the wave, and each lane's slot from the count of pushing lanes below it.
+struct KahnArgs {
+    SetupDims g;
+    const uint8_t* pmask;        // predecessor masks [S][N]
+    const uint8_t* smask;        // successor masks [S][N]
+    const int32_t* cid;          // [N] component id of each node (not IDENT)
+    const int32_t* bptr;         // [nblk + 1] members of the nontrivial components
+    const int32_t* bmem;
+    int32_t nblk;
+    int32_t* cnt;                // scratch [S][N + nblk]
+    int32_t* f0;
+    int32_t* f1;
+    int32_t* lev;                // [S][N + nblk] level of each component id (-2: not an id)
+};
+
+__device__ __forceinline__ void frontier_push(int32_t* __restrict__ F, int* s_n, bool want, int32_t val) {
+    const uint64_t b = __ballot(want);
+    if (b == 0) return;
+    const int lane = (int)__lane_id();
+    const int leader = __ffsll((unsigned long long)b) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(s_n, __popcll(b));
+    base = __shfl(base, leader);
+    const int below = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    if (want) F[base + below] = val;
+}
+
+template <bool REV, bool IDENT>
+__global__ __launch_bounds__(1024) void k_kahn(KahnArgs k) {
+    const SetupDims& g = k.g;
+    const int64_t N = g.N;
+    const int32_t nc = (int32_t)N + (IDENT ? 0 : k.nblk);
+    const int64_t off = (int64_t)blockIdx.x * nc;
+    const int64_t moff = (int64_t)blockIdx.x * N;
+    const uint8_t* __restrict__ inm = (REV ? k.smask : k.pmask) + moff;
+    const uint8_t* __restrict__ outm = (REV ? k.pmask : k.smask) + moff;
+    int32_t* __restrict__ cnt = k.cnt + off;
+    int32_t* F = k.f0 + off;
+    int32_t* Fn = k.f1 + off;
+    int32_t* __restrict__ lev = k.lev + off;
+    __shared__ int s_n;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
+    auto cid_of = [&](int64_t v) -> int32_t { return IDENT ? (int32_t)v : k.cid[v]; };
+    // component ids of the neighbours of m along the set bits of b (-1 elsewhere), loads in flight together
+    auto nbr_ids = [&](int64_t m, uint32_t b, int32_t cu[6]) {
+#pragma unroll
+        for (int slot = 0; slot < 6; slot++) {
+            cu[slot] = -1;
+            if ((b >> slot) & 1u) {
+                const int d = slot >> 1;
+                cu[slot] = cid_of((slot & 1) ? m + g.stride[d] : m - g.stride[d]);
+            }
+        }
+    };
+    // external in-edges per component; the components without any start
+    for (int32_t c = threadIdx.x; c - (int32_t)threadIdx.x < nc; c += blockDim.x) {
+        bool start = false;
+        if (c < nc) {
+            int32_t n_in = 0;
+            bool own = true;
+            int32_t j0 = -1, j1 = 0;     // one member: c itself
+            if (c >= N) {
+                j0 = k.bptr[c - N];
+                j1 = k.bptr[c - N + 1];
+            } else if (!IDENT && k.cid[c] != c) {
+                own = false;             // a member of a nontrivial component
+                j1 = -1;
+            }
+            for (int32_t j = j0; j < j1; j++) {
+                const int64_t m = j < 0 ? c : k.bmem[j];
+                int32_t cu[6];
+                nbr_ids(m, inm[m], cu);
+#pragma unroll
+                for (int slot = 0; slot < 6; slot++) n_in += (cu[slot] >= 0 && cu[slot] != c) ? 1 : 0;
+            }
+            cnt[c] = n_in;
+            lev[c] = own ? -1 : -2;
+            start = own && n_in == 0;
+        }
+        frontier_push(F, &s_n, start, c);
+    }
+    __syncthreads();
+    int cur = s_n;
+    for (int32_t r = 0; cur > 0; r++) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_n = 0;
+        __syncthreads();
+        for (int i = threadIdx.x; i - (int)threadIdx.x < cur; i += blockDim.x) {
+            const bool live = i < cur;
+            const int32_t c = live ? F[i] : 0;
+            if (live) lev[c] = r;
+            int32_t j = -1, j1 = live ? 0 : -1;
+            if (live && c >= N) {
+                j = k.bptr[c - N];
+                j1 = k.bptr[c - N + 1];
+            }
+            // one member per step, every lane of the wave at the same pushes
+            for (;;) {
+                const bool has = j < j1;
+                if (!__any(has)) break;
+                int32_t cu[6];
+                bool ready[6];
+#pragma unroll
+                for (int slot = 0; slot < 6; slot++) ready[slot] = false;
+                if (has) {
+                    const int64_t m = j < 0 ? c : k.bmem[j];
+                    nbr_ids(m, outm[m], cu);
+#pragma unroll
+                    for (int slot = 0; slot < 6; slot++)
+                        if (cu[slot] >= 0 && cu[slot] != c) ready[slot] = atomicSub(cnt + cu[slot], 1) == 1;
+                } else {
+#pragma unroll
+                    for (int slot = 0; slot < 6; slot++) cu[slot] = 0;
+                }
+#pragma unroll
+                for (int slot = 0; slot < 6; slot++) frontier_push(Fn, &s_n, ready[slot], cu[slot]);
+                j++;
+            }
+        }
+        __syncthreads();
+        cur = s_n;
+        int32_t* t = F;
+        F = Fn;
+        Fn = t;
+    }
+}
+
+// Nodes removed by the forward (bit 0) and the reverse (bit 1) elimination.
+__global__ void k_trim_flags(int64_t total, const int32_t* __restrict__ lf, const int32_t* __restrict__ lr,
+                             uint8_t* __restrict__ flags) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x)
+        flags[t] = (uint8_t)((lf[t] >= 0 ? 1 : 0) | (lr[t] >= 0 ? 2 : 0));
+}
+
+// Per host thread: a stream, device buffers and pinned host staging for the
+// condensation levels of the states it finishes.
+struct LevelCtx {
+    SetupDims g;
+    hipStream_t stream = nullptr;
+    int64_t cap = 0;             // N + the most nontrivial components seen
+    int32_t *cid = nullptr, *bptr = nullptr, *bmem = nullptr, *cnt = nullptr, *f0 = nullptr, *f1 = nullptr,
+            *lf = nullptr, *lr = nullptr;
+    uint8_t *pm = nullptr, *sm = nullptr;
+    char* host = nullptr;        // pinned: cid, masks, block lists in; levels out
+    void release() {
+        for (void* p : {(void*)cid, (void*)bptr, (void*)bmem, (void*)cnt, (void*)f0, (void*)f1, (void*)lf, (void*)lr,
+                        (void*)pm, (void*)sm})
+            if (p) (void)hipFree(p);
+        if (host) (void)hipHostFree(host);
+        if (stream) (void)hipStreamDestroy(stream);
+        cid = bptr = bmem = cnt = f0 = f1 = lf = lr = nullptr;
+        pm = sm = nullptr;
+        host = nullptr;
+        stream = nullptr;
+        cap = 0;
+    }
+};
+
+int device_levels(void* ctxp, int64_t N, int32_t ncomp, const int32_t* comp, const int32_t* cptr, const int32_t* cnodes,
+                  const uint32_t* pmask, const uint32_t* smask, int32_t* clev_f, int32_t* clev_r) {
+    LevelCtx& x = *static_cast<LevelCtx*>(ctxp);
+    // component ids for the device: node ids for singletons, N + b for the
+    // b-th nontrivial component (in comp order)
+    int32_t nblk = 0;
+    int64_t nmem = 0;
+    for (int32_t c = 0; c < ncomp; c++)
+        if (cptr[c + 1] - cptr[c] > 1) {
+            nblk++;
+            nmem += cptr[c + 1] - cptr[c];
+        }
+    const int64_t need = N + nblk;
+    hipError_t e = hipSuccess;
+    if (!x.stream) e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
+    if (e == hipSuccess && x.cap < need) {
+        const int64_t cap = std::max<int64_t>(need, N + N / 64 + 64);
+        x.release();
+        e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
+        x.cap = cap;
+        for (int32_t** p : {&x.cid, &x.bmem, &x.cnt, &x.f0, &x.f1, &x.lf, &x.lr})
+            if (e == hipSuccess) e = hipMalloc(p, sizeof(int32_t) * (size_t)cap);
+        if (e == hipSuccess) e = hipMalloc(&x.bptr, sizeof(int32_t) * ((size_t)cap + 1));
+        if (e == hipSuccess) e = hipMalloc(&x.pm, (size_t)N);
+        if (e == hipSuccess) e = hipMalloc(&x.sm, (size_t)N);
+        if (e == hipSuccess) e = hipHostMalloc((void**)&x.host, sizeof(int32_t) * (size_t)(4 * cap + 2) + 2 * (size_t)N);
+    }
+    if (e != hipSuccess) {
+        set_error("GPU setup pass (levels): %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    int32_t* h_cid = (int32_t*)x.host;                 // [N]
+    int32_t* h_bptr = h_cid + N;                        // [nblk + 1]
+    int32_t* h_bmem = h_bptr + (nblk + 1);              // [nmem]
+    uint8_t* h_pm = (uint8_t*)(h_bmem + nmem);          // [N]
+    uint8_t* h_sm = h_pm + N;                           // [N]
+    int32_t* h_lf = (int32_t*)x.host;                   // out: [need] twice, after the inputs are consumed
+    int32_t* h_lr = h_lf + need;
+    {
+        int32_t b = 0;
+        h_bptr[0] = 0;
+        for (int32_t c = 0; c < ncomp; c++) {
+            const int32_t k = cptr[c + 1] - cptr[c];
+            if (k == 1) {
+                h_cid[cnodes[cptr[c]]] = cnodes[cptr[c]];
+                continue;
+            }
+            for (int32_t j = cptr[c]; j < cptr[c + 1]; j++) {
+                h_cid[cnodes[j]] = (int32_t)N + b;
+                h_bmem[h_bptr[b] + (j - cptr[c])] = cnodes[j];
+            }
+            h_bptr[b + 1] = h_bptr[b] + k;
+            b++;
+        }
+        for (int64_t v = 0; v < N; v++) {
+            h_pm[v] = (uint8_t)pmask[v];
+            h_sm[v] = (uint8_t)smask[v];
+        }
+    }
+    hipStream_t s = x.stream;
+    e = hipMemcpyAsync(x.cid, h_cid, sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(x.bptr, h_bptr, sizeof(int32_t) * ((size_t)nblk + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && nmem) e = hipMemcpyAsync(x.bmem, h_bmem, sizeof(int32_t) * (size_t)nmem, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(x.pm, h_pm, (size_t)N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(x.sm, h_sm, (size_t)N, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        KahnArgs k{};
+        k.g = x.g;
+        k.pmask = x.pm;
+        k.smask = x.sm;
+        k.cid = x.cid;
+        k.bptr = x.bptr;
+        k.bmem = x.bmem;
+        k.nblk = nblk;
+        k.cnt = x.cnt;
+        k.f0 = x.f0;
+        k.f1 = x.f1;
+        k.lev = x.lf;
+        hipLaunchKernelGGL((k_kahn<false, false>), dim3(1), dim3(1024), 0, s, k);
+        k.lev = x.lr;
+        hipLaunchKernelGGL((k_kahn<true, false>), dim3(1), dim3(1024), 0, s, k);
+        e = hipGetLastError();
+    }
+    // the inputs in the staging area are consumed once the kernels have run
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_lf, x.lf, sizeof(int32_t) * (size_t)need, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_lr, x.lr, sizeof(int32_t) * (size_t)need, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error("GPU setup pass (levels): %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    int32_t b = 0;
+    for (int32_t c = 0; c < ncomp; c++) {
+        const int32_t id = cptr[c + 1] - cptr[c] > 1 ? (int32_t)N + b++ : cnodes[cptr[c]];
+        clev_f[c] = h_lf[id];
+        clev_r[c] = h_lr[id];
+        if (clev_f[c] < 0 || clev_r[c] < 0) {
+            set_error("GPU setup pass: component %d was never eliminated (the partition leaves a cycle)", c);
+            return FM_EHIP;
+        }
+    }
+    return FM_OK;
+}
+
 }  // namespace
 
 }  // namespace fm
@@ -173,21 +471,37 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     // sources go through the device in chunks of up to nt (about 2 GB of
     // couplings at most); host threads finish the states of one chunk while
     // the device computes the next
-    const int32_t chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t)(2LL << 30) / (N * 57)));
+    // (couplings 57 bytes per node, the eliminations' masks, counters,
+    // frontiers and levels 22 more)
+    const int32_t chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t)(2LL << 30) / (N * 79)));
     double *dG = nullptr, *ds = nullptr, *dw = nullptr, *dc = nullptr;
-    uint8_t* dm = nullptr;
+    uint8_t *dm = nullptr, *dsm = nullptr, *dtr = nullptr;
+    int32_t *dcnt = nullptr, *df0 = nullptr, *df1 = nullptr, *dlf = nullptr, *dlr = nullptr;
     int64_t* dsrc = nullptr;
     unsigned long long* dnv = nullptr;
     int* dbad = nullptr;
+    char* hst = nullptr;         // pinned staging of one chunk's couplings and trim flags
+    int dev = 0;
+    std::vector<LevelCtx> lctx(nt);
+    for (LevelCtx& x : lctx) x.g = d;
     auto release = [&]() {
-        for (void* p : {(void*)dG, (void*)ds, (void*)dw, (void*)dc, (void*)dm, (void*)dsrc, (void*)dnv, (void*)dbad})
+        for (void* p : {(void*)dG, (void*)ds, (void*)dw, (void*)dc, (void*)dm, (void*)dsrc, (void*)dnv, (void*)dbad,
+                        (void*)dsm, (void*)dtr, (void*)dcnt, (void*)df0, (void*)df1, (void*)dlf, (void*)dlr})
             if (p) (void)hipFree(p);
+        for (LevelCtx& x : lctx) x.release();
+        if (hst) (void)hipHostFree(hst);
     };
-    hipError_t e = hipMalloc(&dG, sizeof(double) * (size_t)N * d.ncomp_g);
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipMalloc(&dG, sizeof(double) * (size_t)N * d.ncomp_g);
     if (e == hipSuccess) e = hipMalloc(&ds, sizeof(double) * (size_t)N);
     if (e == hipSuccess) e = hipMalloc(&dw, sizeof(double) * 6 * (size_t)N * chunk);
     if (e == hipSuccess) e = hipMalloc(&dc, sizeof(double) * (size_t)N * chunk);
     if (e == hipSuccess) e = hipMalloc(&dm, (size_t)N * chunk);
+    if (e == hipSuccess) e = hipMalloc(&dsm, (size_t)N * chunk);
+    if (e == hipSuccess) e = hipMalloc(&dtr, (size_t)N * chunk);
+    for (int32_t** p : {&dcnt, &df0, &df1, &dlf, &dlr})
+        if (e == hipSuccess) e = hipMalloc(p, sizeof(int32_t) * (size_t)N * chunk);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&hst, (size_t)N * chunk * (2 + 7 * sizeof(double)));
     if (e == hipSuccess) e = hipMalloc(&dsrc, sizeof(int64_t) * S);
     if (e == hipSuccess) e = hipMalloc(&dnv, sizeof(unsigned long long) * S);
     if (e == hipSuccess) e = hipMalloc(&dbad, sizeof(int) * S);
@@ -202,7 +516,7 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
         return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
     }
     struct Couplings {
-        std::vector<uint8_t> m;
+        std::vector<uint8_t> m, t;
         std::vector<double> w, c;
     };
     std::vector<Couplings> buf(S);
@@ -217,7 +531,12 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     int32_t ready = 0;         // sources whose couplings are on the host
     bool stop = false;         // the device side failed: workers finish what they hold
     std::atomic<int32_t> next{0};
-    auto worker = [&]() {
+    auto worker = [&](int id) {
+        if (hipSetDevice(dev) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+            return;
+        }
         for (;;) {
             int32_t a;
             {
@@ -227,6 +546,9 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
                 a = next.fetch_add(1);
             }
             Assembled pre{buf[a].m.data(), buf[a].w.data(), buf[a].c.data(), (int64_t)nv[a]};
+            pre.trim = buf[a].t.data();
+            pre.levels = device_levels;
+            pre.ctx = &lctx[id];
             fm_state* stt = nullptr;
             const int r = build_state(g, nullptr, s, src_nodes[a],
                                       n_rcv > 0 ? rcv_nodes + (size_t)a * per_src : nullptr,
@@ -236,12 +558,13 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             res[a] = stt;
             if (r != FM_OK) msgs[a] = fm_last_error();
             std::vector<uint8_t>().swap(buf[a].m);
+            std::vector<uint8_t>().swap(buf[a].t);
             std::vector<double>().swap(buf[a].w);
             std::vector<double>().swap(buf[a].c);
         }
     };
     std::vector<std::thread> th;
-    for (int i = 0; i < nt; i++) th.emplace_back(worker);
+    for (int i = 0; i < nt; i++) th.emplace_back(worker, i);
     int rc = FM_OK;
     std::string msg;
     for (int32_t a0 = 0; a0 < S; a0 += chunk) {
@@ -250,19 +573,34 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
         const int grid = (int)std::min<int64_t>((total + 255) / 256, 65535);
         hipLaunchKernelGGL(k_setup_couplings, dim3(grid), dim3(256), 0, st, d, n, dG, T_dev + (size_t)a0 * N, ds,
                            dsrc + a0, dw, dm, dc, dnv + a0, dbad + a0);
-        e = hipGetLastError();
-        for (int32_t k = 0; k < n && e == hipSuccess; k++) {
-            Couplings& cp = buf[a0 + k];
-            cp.m.resize((size_t)N);
-            cp.w.resize((size_t)N * 6);
-            cp.c.resize((size_t)N);
-            e = hipMemcpyAsync(cp.m.data(), dm + (size_t)k * N, (size_t)N, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(cp.w.data(), dw + (size_t)k * N * 6, sizeof(double) * 6 * (size_t)N,
-                                   hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(cp.c.data(), dc + (size_t)k * N, sizeof(double) * (size_t)N, hipMemcpyDeviceToHost, st);
+        // trimming: Kahn's elimination forward and backward, one workgroup
+        // per source; the nodes neither removes hold every cycle
+        hipLaunchKernelGGL(k_setup_smask, dim3(grid), dim3(256), 0, st, d, n, dm, dsm);
+        {
+            KahnArgs k{};
+            k.g = d;
+            k.pmask = dm;
+            k.smask = dsm;
+            k.cnt = dcnt;
+            k.f0 = df0;
+            k.f1 = df1;
+            k.lev = dlf;
+            hipLaunchKernelGGL((k_kahn<false, true>), dim3(n), dim3(1024), 0, st, k);
+            k.lev = dlr;
+            hipLaunchKernelGGL((k_kahn<true, true>), dim3(n), dim3(1024), 0, st, k);
         }
+        hipLaunchKernelGGL(k_trim_flags, dim3(grid), dim3(256), 0, st, total, dlf, dlr, dtr);
+        e = hipGetLastError();
+        // one copy per array into pinned staging, then into each source's
+        // own buffers for the host threads
+        uint8_t* hm = (uint8_t*)hst;
+        uint8_t* ht = hm + (size_t)chunk * N;
+        double* hw = (double*)(ht + (size_t)chunk * N);
+        double* hc = hw + (size_t)chunk * N * 6;
+        if (e == hipSuccess) e = hipMemcpyAsync(hm, dm, (size_t)n * N, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(ht, dtr, (size_t)n * N, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hw, dw, sizeof(double) * 6 * (size_t)n * N, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(hc, dc, sizeof(double) * (size_t)n * N, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipMemcpyAsync(nv.data() + a0, dnv + a0, sizeof(unsigned long long) * n, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipMemcpyAsync(bad.data() + a0, dbad + a0, sizeof(int) * n, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -270,6 +608,13 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             rc = FM_EHIP;
             msg = std::string("GPU setup pass failed: ") + hipGetErrorString(e);
             break;
+        }
+        for (int32_t k = 0; k < n; k++) {
+            Couplings& cp = buf[a0 + k];
+            cp.m.assign(hm + (size_t)k * N, hm + (size_t)(k + 1) * N);
+            cp.t.assign(ht + (size_t)k * N, ht + (size_t)(k + 1) * N);
+            cp.w.assign(hw + (size_t)k * N * 6, hw + (size_t)(k + 1) * N * 6);
+            cp.c.assign(hc + (size_t)k * N, hc + (size_t)(k + 1) * N);
         }
         for (int32_t k = 0; k < n && rc == FM_OK; k++)
             if (bad[a0 + k]) {
