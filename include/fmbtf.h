@@ -249,17 +249,25 @@ int fm_set_iterative_block_min(int32_t k_min);
  * source (face coefficients, upwind weights, identity rows, calibration,
  * Sections 3.1-3.2, and the violating-edge count of eq. (graph-fractions))
  * computed on the device from traveltimes already there, for all sources at
- * once, bit-identical to the host's; host threads then find the SCCs and
- * levels, factor the blocks and pack each state, overlapping the device work
- * of the next sources.
+ * once, bit-identical to the host's.  On the device too, one workgroup per
+ * source: Kahn's elimination forward and backward (Section 3.5) trims the
+ * nodes that lie on no path between cycles, and after the host's SCC search
+ * over the remaining core, Kahn's elimination over the components gives the
+ * longest-path levels of the condensation DAG in both directions (Section
+ * 4.1).  Host threads factor the blocks and pack each state, overlapping
+ * the device work of the next sources.  The states equal those of
+ * fm_build_frozen_states_w (component ids included).
  *   T        device [S][N] traveltimes (8-byte aligned), e.g. fm_eikonal_solve's output
  *   s        host [N]; G in g on the host; src_nodes host [S]
  *   receivers as fm_build_frozen_states_w (host, [S][n_rcv][k_per_rcv], weights may be NULL)
  *   nthreads host threads; hip_stream the stream of the device work (NULL: null stream)
- * Device scratch of about min(S, nthreads) x N x 57 bytes (at most ~2 GB) is
- * allocated and freed inside the call.  Errors: as fm_build_frozen_states_w
- * (a T that is not finite or not 0 at the source gives FM_EINVAL); FM_EHIP for
- * a failed HIP call.
+ * Device scratch of about min(S, nthreads) x N x 79 bytes (at most ~2 GB),
+ * pinned host staging of the same chunk x N x 58 bytes, and per host thread
+ * about 40 x N bytes of device memory and 18 x N bytes of pinned host memory
+ * are allocated and freed inside the call.  Face stencil only (fm_grid.stencil
+ * 0 or 6, else FM_EINVAL).  Errors: as fm_build_frozen_states_w (a T that is
+ * not finite or not 0 at the source gives FM_EINVAL); FM_EHIP for a failed
+ * HIP call.
  */
 int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const double* T, const double* s,
                                const int64_t* src_nodes, const int64_t* rcv_nodes, const double* rcv_weights,
