@@ -567,7 +567,8 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     for (int i = 0; i < nt; i++) th.emplace_back(worker, i);
     int rc = FM_OK;
     std::string msg;
-    for (int32_t a0 = 0; a0 < S; a0 += chunk) {
+    // the device work of one chunk: couplings, successor masks, trimming
+    auto launch_chunk = [&](int32_t a0) {
         const int32_t n = std::min(chunk, S - a0);
         const int64_t total = (int64_t)n * N;
         const int grid = (int)std::min<int64_t>((total + 255) / 256, 65535);
@@ -576,21 +577,23 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
         // trimming: Kahn's elimination forward and backward, one workgroup
         // per source; the nodes neither removes hold every cycle
         hipLaunchKernelGGL(k_setup_smask, dim3(grid), dim3(256), 0, st, d, n, dm, dsm);
-        {
-            KahnArgs k{};
-            k.g = d;
-            k.pmask = dm;
-            k.smask = dsm;
-            k.cnt = dcnt;
-            k.f0 = df0;
-            k.f1 = df1;
-            k.lev = dlf;
-            hipLaunchKernelGGL((k_kahn<false, true>), dim3(n), dim3(1024), 0, st, k);
-            k.lev = dlr;
-            hipLaunchKernelGGL((k_kahn<true, true>), dim3(n), dim3(1024), 0, st, k);
-        }
+        KahnArgs k{};
+        k.g = d;
+        k.pmask = dm;
+        k.smask = dsm;
+        k.cnt = dcnt;
+        k.f0 = df0;
+        k.f1 = df1;
+        k.lev = dlf;
+        hipLaunchKernelGGL((k_kahn<false, true>), dim3(n), dim3(1024), 0, st, k);
+        k.lev = dlr;
+        hipLaunchKernelGGL((k_kahn<true, true>), dim3(n), dim3(1024), 0, st, k);
         hipLaunchKernelGGL(k_trim_flags, dim3(grid), dim3(256), 0, st, total, dlf, dlr, dtr);
-        e = hipGetLastError();
+        return hipGetLastError();
+    };
+    e = launch_chunk(0);
+    for (int32_t a0 = 0; a0 < S; a0 += chunk) {
+        const int32_t n = std::min(chunk, S - a0);
         // one copy per array into pinned staging, then into each source's
         // own buffers for the host threads
         uint8_t* hm = (uint8_t*)hst;
@@ -609,12 +612,20 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             msg = std::string("GPU setup pass failed: ") + hipGetErrorString(e);
             break;
         }
-        for (int32_t k = 0; k < n; k++) {
-            Couplings& cp = buf[a0 + k];
-            cp.m.assign(hm + (size_t)k * N, hm + (size_t)(k + 1) * N);
-            cp.t.assign(ht + (size_t)k * N, ht + (size_t)(k + 1) * N);
-            cp.w.assign(hw + (size_t)k * N * 6, hw + (size_t)(k + 1) * N * 6);
-            cp.c.assign(hc + (size_t)k * N, hc + (size_t)(k + 1) * N);
+        // the next chunk's device work runs while this one is copied out of
+        // the staging (one host thread per source)
+        if (a0 + chunk < S) e = launch_chunk(a0 + chunk);
+        {
+            std::vector<std::thread> cps;
+            for (int32_t k = 0; k < n; k++)
+                cps.emplace_back([&, k]() {
+                    Couplings& cp = buf[a0 + k];
+                    cp.m.assign(hm + (size_t)k * N, hm + (size_t)(k + 1) * N);
+                    cp.t.assign(ht + (size_t)k * N, ht + (size_t)(k + 1) * N);
+                    cp.w.assign(hw + (size_t)k * N * 6, hw + (size_t)(k + 1) * N * 6);
+                    cp.c.assign(hc + (size_t)k * N, hc + (size_t)(k + 1) * N);
+                });
+            for (auto& t : cps) t.join();
         }
         for (int32_t k = 0; k < n && rc == FM_OK; k++)
             if (bad[a0 + k]) {
