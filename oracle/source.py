@@ -112,7 +112,7 @@ class PointSourceOperator:
         return self.op.N
 
 
-def assemble_point_source(dim, n1, n2, n3, G, X, T, s, xi, rho, rcv, rcv_w=None) -> PointSourceOperator:
+def assemble_point_source(dim, n1, n2, n3, G, X, T, s, xi, rho, rcv, rcv_w=None, stencil=6) -> PointSourceOperator:
     N = n1 * n2 * n3
     s = np.asarray(s, dtype=np.float64)
     X = np.asarray(X, dtype=np.float64).reshape(N, dim)
@@ -121,7 +121,7 @@ def assemble_point_source(dim, n1, n2, n3, G, X, T, s, xi, rho, rcv, rcv_w=None)
     x_src = np.sum(phi[:, None] * X[cn], axis=0)
     seeds = seed_nodes(dim, n1, n2, n3, xi, rho)
     # W with identity rows at the seeds (the src argument is one of them)
-    op = assemble(dim, n1, n2, n3, G, T, s, int(seeds[0]), None, None, identity_rows=seeds)
+    op = assemble(dim, n1, n2, n3, G, T, s, int(seeds[0]), None, None, identity_rows=seeds, stencil=stencil)
     # C: the Section 3.2 diagonal off the seeds, the seed derivative on them
     c = op.c.copy()
     c[seeds] = 0.0

@@ -3,7 +3,8 @@ calls): the host setup's W and c are bit-identical to the oracle's cube
 assembly (same FP64 operations in the same order), and its SCC partition,
 condensation levels and structural statistics match the oracle's graph
 diagnostics, on 2-D and 3-D deformed grids, the curved-wavefront fixture and
-c3; an unknown stencil value is rejected.
+c3, and with an off-grid point source (identity seed rows); an unknown
+stencil value is rejected.
 """
 import numpy as np
 import pytest
@@ -59,3 +60,23 @@ def test_unknown_stencil_is_rejected():
             fm.build_frozen_state(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T[0], wl.s, int(wl.src[0]), wl.rcv,
                                   stencil=bad)
         assert e.value.code == fm.binding.FM_EINVAL and "stencil" in str(e.value)
+
+
+def test_cube_point_source_matches_oracle():
+    from oracle import source as PS
+    wl = W.smooth_3d(17, 15, 9, topo_amp=0.1, with_T=False)
+    xi = np.array([[6.3, 7.1, 0.0], [11.6, 3.2, 2.5]])
+    W.eikonal_point(wl, xi, 1.5)
+    states = fm.build_frozen_states_pt(3, wl.n1, wl.n2, wl.n3, wl.G, wl.X, wl.T, wl.s, xi, 1.5, wl.rcv, stencil=26)
+    for a in range(2):
+        pso = PS.assemble_point_source(3, wl.n1, wl.n2, wl.n3, wl.G, wl.X, wl.T[a], wl.s, xi[a], 1.5, wl.rcv,
+                                       stencil=26)
+        rowptr, col, wv, c = states[a].export_operator()
+        Wo = pso.op.W.tocsr()
+        Wo.sort_indices()
+        assert np.array_equal(rowptr, Wo.indptr) and np.array_equal(col, Wo.indices)
+        assert np.array_equal(wv, Wo.data)
+        c_ref = pso.op.c.copy()
+        c_ref[pso.seeds] = 0.0
+        assert np.array_equal(c, c_ref)
+        assert states[a].stats()["n_seed"] == pso.seeds.size
