@@ -254,9 +254,11 @@ int fm_set_iterative_block_min(int32_t k_min);
  * nodes that lie on no path between cycles, and after the host's SCC search
  * over the remaining core, Kahn's elimination over the components gives the
  * longest-path levels of the condensation DAG in both directions (Section
- * 4.1).  Host threads factor the blocks and pack each state, overlapping
- * the device work of the next sources.  The states equal those of
- * fm_build_frozen_states_w (component ids included).
+ * 4.1), and the level-ordered records are written on the device in the
+ * host's format.  Host threads place the nodes in level order and factor
+ * the blocks, overlapping the device work of the next sources.  The states
+ * equal those of fm_build_frozen_states_w (component ids included); their
+ * records stay in device memory until a batch first uses them.
  *   T        device [S][N] traveltimes (8-byte aligned), e.g. fm_eikonal_solve's output
  *   s        host [N]; G in g on the host; src_nodes host [S]
  *   receivers as fm_build_frozen_states_w (host, [S][n_rcv][k_per_rcv], weights may be NULL)
@@ -264,7 +266,8 @@ int fm_set_iterative_block_min(int32_t k_min);
  * Device scratch of about min(S, nthreads) x N x 79 bytes (at most ~2 GB),
  * pinned host staging of the same chunk x N x 58 bytes, and per host thread
  * about 40 x N bytes of device memory and 18 x N bytes of pinned host memory
- * are allocated and freed inside the call.  Face stencil only (fm_grid.stencil
+ * are allocated and freed inside the call; each state holds its records
+ * (about 80 x N bytes) on the device from the call on.  Face stencil only (fm_grid.stencil
  * 0 or 6, else FM_EINVAL).  Errors: as fm_build_frozen_states_w (a T that is
  * not finite or not 0 at the source gives FM_EINVAL); FM_EHIP for a failed
  * HIP call.

@@ -93,6 +93,7 @@ struct DeviceState {
     const void* fwts32 = nullptr;
     const void* rwts32 = nullptr;
     const void* cal32 = nullptr;
+    size_t nwts[2] = {0, 0};     // doubles in the forward / reverse value records
     int device = -1;
 };
 

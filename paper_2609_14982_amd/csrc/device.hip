@@ -59,6 +59,14 @@ int put(char* base, size_t at, const std::vector<T>& v) {
 
 }  // namespace
 
+static void free_device_records(Packed& pk) {
+    for (int d = 0; d < 2; d++) {
+        if (pk.drec.meta[d]) (void)hipFree(pk.drec.meta[d]);
+        if (pk.drec.wts[d]) (void)hipFree(pk.drec.wts[d]);
+        pk.drec.meta[d] = pk.drec.wts[d] = nullptr;
+    }
+}
+
 int upload_state(HostState* st) {
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
@@ -69,14 +77,23 @@ int upload_state(HostState* st) {
     }
     const Packed& pk = st->pk;
     Arena ar;
-    size_t o_fmeta = ar.add<uint64_t>(pk.fmeta.size());
-    size_t o_fwts = ar.add<double>(pk.fwts.size());
+    // records packed on the device by the GPU setup pass are copied from there
+    const bool drec = pk.drec.meta[0] != nullptr;
+    if (drec && pk.drec.device != dev) {
+        set_error("the state's records were packed on device %d, not the current device %d", pk.drec.device, dev);
+        return FM_EINVAL;
+    }
+    const size_t n_fmeta = drec ? (size_t)st->N : pk.fmeta.size(), n_rmeta = drec ? (size_t)st->N : pk.rmeta.size();
+    const size_t n_fwts = drec ? (size_t)pk.drec.nwts[0] : pk.fwts.size();
+    const size_t n_rwts = drec ? (size_t)pk.drec.nwts[1] : pk.rwts.size();
+    size_t o_fmeta = ar.add<uint64_t>(n_fmeta);
+    size_t o_fwts = ar.add<double>(n_fwts);
     size_t o_flp = ar.add<int32_t>(pk.flvl_ptr.size());
     size_t o_fln = ar.add<int32_t>(pk.flvl_nsc.size());
     size_t o_fbp = ar.add<int32_t>(pk.fblk_ptr.size());
     size_t o_fbi = ar.add<int32_t>(pk.fblk_id.size());
-    size_t o_rmeta = ar.add<uint64_t>(pk.rmeta.size());
-    size_t o_rwts = ar.add<double>(pk.rwts.size());
+    size_t o_rmeta = ar.add<uint64_t>(n_rmeta);
+    size_t o_rwts = ar.add<double>(n_rwts);
     size_t o_rlp = ar.add<int32_t>(pk.rlvl_ptr.size());
     size_t o_rln = ar.add<int32_t>(pk.rlvl_nsc.size());
     size_t o_rbp = ar.add<int32_t>(pk.rblk_ptr.size());
@@ -136,14 +153,29 @@ int upload_state(HostState* st) {
     }
     char* b = (char*)ds->blob;
     int rc = FM_OK;
-    rc = rc ? rc : put(b, o_fmeta, pk.fmeta);
-    rc = rc ? rc : put(b, o_fwts, pk.fwts);
+    if (drec) {
+        const void* src[4] = {pk.drec.meta[0], pk.drec.wts[0], pk.drec.meta[1], pk.drec.wts[1]};
+        const size_t at[4] = {o_fmeta, o_fwts, o_rmeta, o_rwts};
+        const size_t bytes[4] = {8 * n_fmeta, 8 * n_fwts, 8 * n_rmeta, 8 * n_rwts};
+        for (int i = 0; i < 4 && rc == FM_OK; i++) {
+            const hipError_t ce = hipMemcpy(b + at[i], src[i], bytes[i], hipMemcpyDeviceToDevice);
+            if (ce != hipSuccess) {
+                set_error("copy of device-packed records failed: %s", hipGetErrorString(ce));
+                rc = FM_EHIP;
+            }
+        }
+    } else {
+        rc = rc ? rc : put(b, o_fmeta, pk.fmeta);
+        rc = rc ? rc : put(b, o_fwts, pk.fwts);
+    }
     rc = rc ? rc : put(b, o_flp, pk.flvl_ptr);
     rc = rc ? rc : put(b, o_fln, pk.flvl_nsc);
     rc = rc ? rc : put(b, o_fbp, pk.fblk_ptr);
     rc = rc ? rc : put(b, o_fbi, pk.fblk_id);
-    rc = rc ? rc : put(b, o_rmeta, pk.rmeta);
-    rc = rc ? rc : put(b, o_rwts, pk.rwts);
+    if (!drec) {
+        rc = rc ? rc : put(b, o_rmeta, pk.rmeta);
+        rc = rc ? rc : put(b, o_rwts, pk.rwts);
+    }
     rc = rc ? rc : put(b, o_rlp, pk.rlvl_ptr);
     rc = rc ? rc : put(b, o_rln, pk.rlvl_nsc);
     rc = rc ? rc : put(b, o_rbp, pk.rblk_ptr);
@@ -252,19 +284,36 @@ int upload_state(HostState* st) {
     d.n_rcv = (int32_t)pk.rcv_ptr.size() - 1;
     d.n_ent = (int32_t)pk.rcv_node.size();
     ds->device = dev;
+    ds->nwts[0] = n_fwts;
+    ds->nwts[1] = n_rwts;
     st->dev = ds;
+    if (drec) {
+        (void)hipDeviceSynchronize();   // the copies out of them are done
+        free_device_records(st->pk);
+    }
     return FM_OK;
+}
+
+__global__ void k_to_f32(const double* __restrict__ src, float* __restrict__ dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = (float)src[i];
 }
 
 static int upload_fp32(HostState* st) {
     DeviceState* ds = st->dev;
     if (ds->blob32) return FM_OK;
     const Packed& pk = st->pk;
-    std::vector<float> f(pk.fwts.begin(), pk.fwts.end());
-    std::vector<float> r(pk.rwts.begin(), pk.rwts.end());
+    // records packed on the device exist only there: converted there
+    const bool on_dev = pk.fwts.empty() && ds->nwts[0] > 0;
+    std::vector<float> f, r;
+    if (!on_dev) {
+        f.assign(pk.fwts.begin(), pk.fwts.end());
+        r.assign(pk.rwts.begin(), pk.rwts.end());
+    }
     std::vector<float> c(pk.cal_nat.begin(), pk.cal_nat.end());
     Arena ar;
-    size_t of = ar.add<float>(f.size()), orr = ar.add<float>(r.size()), oc = ar.add<float>(c.size());
+    size_t of = ar.add<float>(on_dev ? ds->nwts[0] : f.size()), orr = ar.add<float>(on_dev ? ds->nwts[1] : r.size()),
+           oc = ar.add<float>(c.size());
     size_t total = ar.add<char>(0) + 256;
     hipError_t e = hipMalloc(&ds->blob32, total);
     if (e != hipSuccess) {
@@ -273,8 +322,25 @@ static int upload_fp32(HostState* st) {
         return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
     }
     char* b = (char*)ds->blob32;
-    int rc = put(b, of, f);
-    rc = rc ? rc : put(b, orr, r);
+    int rc = FM_OK;
+    if (on_dev) {
+        const int64_t nn[2] = {(int64_t)ds->nwts[0], (int64_t)ds->nwts[1]};
+        const void* srcs[2] = {ds->d.fwts, ds->d.rwts};
+        const size_t offs[2] = {of, orr};
+        for (int i = 0; i < 2; i++) {
+            const int grid = (int)std::min<int64_t>((nn[i] + 255) / 256, 65535);
+            hipLaunchKernelGGL(k_to_f32, dim3(grid), dim3(256), 0, nullptr, (const double*)srcs[i],
+                               (float*)(b + offs[i]), nn[i]);
+        }
+        const hipError_t ce = hipGetLastError();
+        if (ce != hipSuccess) {
+            set_error("FP32 conversion of the records failed: %s", hipGetErrorString(ce));
+            return FM_EHIP;
+        }
+    } else {
+        rc = put(b, of, f);
+        rc = rc ? rc : put(b, orr, r);
+    }
     rc = rc ? rc : put(b, oc, c);
     if (rc) return rc;
     ds->fwts32 = b + of;
@@ -284,6 +350,7 @@ static int upload_fp32(HostState* st) {
 }
 
 void free_device_state(HostState* st) {
+    free_device_records(st->pk);
     if (!st->dev) return;
     if (st->dev->blob_nat) (void)hipFree(st->dev->blob_nat);
     if (st->dev->blob_nat32) (void)hipFree(st->dev->blob_nat32);

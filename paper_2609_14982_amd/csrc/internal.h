@@ -104,6 +104,15 @@ struct Packed {
     int64_t max_blk_rows = 0;          // most FP64 rows one block stages (k, or 3k iterative)
     // cube stencil only: overflow offset of each position's further weights
     std::vector<int32_t> fovf, rovf;
+    // records packed on the device by the GPU setup pass (fmeta / fwts /
+    // rmeta / rwts then stay empty): device buffers the state owns until its
+    // device state is built from them (index 0 forward, 1 reverse)
+    struct DeviceRecords {
+        void* meta[2] = {nullptr, nullptr};   // uint64 [N]
+        void* wts[2] = {nullptr, nullptr};    // double [N * 4 + overflow + 4]
+        int64_t nwts[2] = {0, 0};
+        int device = -1;
+    } drec;
     // off-grid point source (all empty for an on-grid source).  Seed node
     // seed_node[e] is an identity row whose right-hand side is
     // sum_i seed_w[i] ds[seed_col[i]] over i in [seed_ptr[e], seed_ptr[e+1]);
@@ -152,6 +161,13 @@ struct Assembled {
     int (*levels)(void* ctx, int64_t N, int32_t ncomp, const int32_t* comp, const int32_t* cptr,
                   const int32_t* cnodes, const uint32_t* pmask, const uint32_t* smask, int32_t* clev_f,
                   int32_t* clev_r) = nullptr;
+    // and the records: pack() writes one direction's meta words and value
+    // records (the host's format, bit for bit) on the device from the
+    // placement pos_of [N], the components, masks, weights [N][6] and
+    // calibration, rcv [N] marking receiver nodes (reverse direction)
+    int (*pack)(void* ctx, bool fwd, int64_t N, const int32_t* pos_of, const int32_t* comp, const uint32_t* pmask,
+                const uint32_t* smask, const double* w6, const double* cal, const uint8_t* rcv,
+                Packed::DeviceRecords* out) = nullptr;
     void* ctx = nullptr;
 };
 
@@ -234,6 +250,6 @@ void pack_natural(const HostState* st, bool fwd, std::vector<uint64_t>& meta, st
 
 // Device side (device.hip).
 int upload_state(HostState* st);
-void free_device_state(HostState* st);
+void free_device_state(HostState* st);   // also frees records packed on the device
 
 }  // namespace fm

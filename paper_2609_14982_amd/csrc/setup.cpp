@@ -92,6 +92,11 @@ inline bool has_nbr(const Grid& g, int64_t p, int slot) {
 
 inline int opposite(const Grid& g, int slot) { return g.stencil == 26 ? 25 - slot : slot ^ 1; }
 
+// a failure of the device packer (its message is set)
+struct DevicePackError {
+    int rc;
+};
+
 // Dense LU with partial pivoting (largest magnitude, ties to the lowest row),
 // in place on a row-major k x k matrix.  Returns the index of the first pivot
 // below tol, or -1.
@@ -799,6 +804,13 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         }
 
         // ---- 7: level-ordered packing ----
+        // receiver nodes (entries of nonzero weight), for records packed on the device
+        std::vector<uint8_t> rcvflag;
+        if (pre && pre->pack) {
+            rcvflag.assign(N, 0);
+            for (int64_t e = 0; e < (int64_t)n_rcv * K; e++)
+                if (!rcv_w || rcv_w[e] != 0.0) rcvflag[rcv[e]] = 1;
+        }
         // order of components inside a level: singletons (see below), then blocks
         auto pack_direction = [&](bool fwd, std::vector<uint64_t>& meta, std::vector<double>& wts,
                                   std::vector<int32_t>& lvl_ptr, std::vector<int32_t>& lvl_nsc,
@@ -867,6 +879,16 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
                 const int32_t v = (int32_t)p;
                 const int32_t l = clev[c];
                 pos_of[v] = skip(v) ? next_tail++ : many(v) ? next_many[l]++ : next_sc[l]++;
+            }
+            // records on the device (the GPU setup pass): same format, same bits
+            if (pre && pre->pack) {
+                meta.clear();
+                wts.clear();
+                ovf_pos.clear();
+                const int rc = pre->pack(pre->ctx, fwd, N, pos_of.data(), st->comp.data(), st->pmask.data(),
+                                         st->smask.data(), st->wrow.data(), st->cal.data(), rcvflag.data(), &pk.drec);
+                if (rc != FM_OK) throw DevicePackError{rc};
+                return;
             }
             // records: a fixed [c, w1, w2, w3] per position, further weights of
             // the rare nodes with more than three neighbours in an overflow area
@@ -997,7 +1019,7 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         std::vector<std::pair<int32_t, int32_t>> ent(n_ent);
         for (int32_t e = 0; e < n_ent; e++) {
             ent[e] = {rpos_of[pk.rcv_node[e]], e};
-            pk.rmeta[rpos_of[pk.rcv_node[e]]] |= kRcvFlag;
+            if (!pk.rmeta.empty()) pk.rmeta[rpos_of[pk.rcv_node[e]]] |= kRcvFlag;
         }
         std::sort(ent.begin(), ent.end());
         pk.rcv_pos.resize(n_ent);
@@ -1073,19 +1095,27 @@ int build_state(const fm_grid* g, const double* T, const double* s, int64_t src,
         S.f_vio = E ? (double)n_vio / (double)E : 0.0;
         S.f_cyc = (double)n_cyc / (double)N;
         S.f_unr = (double)n_unr / (double)N;
-        S.state_bytes = (int64_t)(pk.fmeta.size() + pk.rmeta.size()) * 8 +
-                        (int64_t)(pk.fwts.size() + pk.rwts.size() + 2 * pk.inv.size() + pk.cal_nat.size()) * 8 +
+        const int64_t n_meta = pk.drec.meta[0] ? 2 * N : (int64_t)(pk.fmeta.size() + pk.rmeta.size());
+        const int64_t n_wts = pk.drec.meta[0] ? pk.drec.nwts[0] + pk.drec.nwts[1]
+                                              : (int64_t)(pk.fwts.size() + pk.rwts.size());
+        S.state_bytes = n_meta * 8 + (n_wts + (int64_t)(2 * pk.inv.size() + pk.cal_nat.size())) * 8 +
                         (int64_t)(pk.sp_col.size() + pk.spt_col.size()) * 12 +
                         (int64_t)(pk.sp_ptr.size() + pk.spt_ptr.size()) * 4;
         S.n_seed = (int32_t)pk.seed_node.size();
         S.n_direct = 0;
         for (size_t r = 0; r + 1 < pk.d_ptr.size(); r++) S.n_direct += pk.d_ptr[r + 1] > pk.d_ptr[r];
         S.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    } catch (const DevicePackError& e) {
+        free_device_state(st);
+        delete st;
+        return e.rc;   // the packer set the message
     } catch (const std::bad_alloc&) {
+        free_device_state(st);
         delete st;
         set_error("out of host memory during setup");
         return FM_ENOMEM;
     } catch (const std::length_error& e) {
+        free_device_state(st);
         delete st;
         set_error("state too large for the packed format: %s", e.what());
         return FM_EINVAL;

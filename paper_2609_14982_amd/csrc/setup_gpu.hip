@@ -301,28 +301,225 @@ __global__ void k_trim_flags(int64_t total, const int32_t* __restrict__ lf, cons
 }
 
 // Per host thread: a stream, device buffers and pinned host staging for the
-// condensation levels of the states it finishes.
+// condensation levels and the records of the states it finishes.
 struct LevelCtx {
     SetupDims g;
+    int device = 0;
     hipStream_t stream = nullptr;
     int64_t cap = 0;             // N + the most nontrivial components seen
     int32_t *cid = nullptr, *bptr = nullptr, *bmem = nullptr, *cnt = nullptr, *f0 = nullptr, *f1 = nullptr,
             *lf = nullptr, *lr = nullptr;
     uint8_t *pm = nullptr, *sm = nullptr;
     char* host = nullptr;        // pinned: cid, masks, block lists in; levels out
+    // records: placement, components, weights, calibration, receiver flags,
+    // external masks, overflow counts and their block sums
+    int32_t *pos = nullptr, *comp = nullptr, *bsum = nullptr;
+    double *w6 = nullptr, *cal = nullptr;
+    uint8_t *rcv = nullptr, *extm = nullptr;
+    // the current source's couplings, kept on the device since the couplings
+    // pass (not owned)
+    const double *src_w6 = nullptr, *src_cal = nullptr;
+    const uint8_t* src_pm = nullptr;
     void release() {
         for (void* p : {(void*)cid, (void*)bptr, (void*)bmem, (void*)cnt, (void*)f0, (void*)f1, (void*)lf, (void*)lr,
-                        (void*)pm, (void*)sm})
+                        (void*)pm, (void*)sm, (void*)pos, (void*)comp, (void*)bsum, (void*)w6, (void*)cal, (void*)rcv,
+                        (void*)extm})
             if (p) (void)hipFree(p);
         if (host) (void)hipHostFree(host);
         if (stream) (void)hipStreamDestroy(stream);
         cid = bptr = bmem = cnt = f0 = f1 = lf = lr = nullptr;
         pm = sm = nullptr;
+        pos = comp = bsum = nullptr;
+        w6 = cal = nullptr;
+        rcv = extm = nullptr;
         host = nullptr;
         stream = nullptr;
         cap = 0;
     }
 };
+
+// ---- records on the device (the host's packing format, bit for bit) ----
+
+// External-neighbour masks (a block member lists only neighbours outside
+// its component) and the overflow count (neighbours past the third) at each
+// node's position.
+template <bool FWD>
+__global__ void k_pack_count(SetupDims g, const int32_t* __restrict__ pos, const int32_t* __restrict__ comp,
+                             const uint8_t* __restrict__ pm, const uint8_t* __restrict__ sm, uint8_t* __restrict__ extm,
+                             int32_t* __restrict__ cnt) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < g.N; v += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t full = FWD ? pm[v] : sm[v], m = 0;
+        const int32_t cv = comp[v];
+        while (full) {
+            const int slot = __builtin_ctz(full);
+            full &= full - 1u;
+            const int d = slot >> 1;
+            const int64_t u = (slot & 1) ? v + g.stride[d] : v - g.stride[d];
+            if (comp[u] != cv) m |= 1u << slot;
+        }
+        extm[v] = (uint8_t)m;
+        const int t = __builtin_popcount(m);
+        cnt[pos[v]] = t > 3 ? t - 3 : 0;
+    }
+}
+
+// Exclusive prefix sums of cnt in place, blocks of 1024 (block totals to bsum).
+__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t* __restrict__ cnt, int64_t n, int32_t* __restrict__ bsum) {
+    __shared__ int32_t t[1024];
+    const int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int32_t x = i < n ? cnt[i] : 0;
+    t[threadIdx.x] = x;
+    __syncthreads();
+    for (int o = 1; o < 1024; o <<= 1) {
+        const int32_t y = threadIdx.x >= (unsigned)o ? t[threadIdx.x - o] : 0;
+        __syncthreads();
+        t[threadIdx.x] += y;
+        __syncthreads();
+    }
+    if (i < n) cnt[i] = t[threadIdx.x] - x;
+    if (threadIdx.x == 1023) bsum[blockIdx.x] = t[1023];
+}
+
+// The block totals scanned by one workgroup (exclusive; the grand total after them).
+__global__ __launch_bounds__(1024) void k_scan_sums(int32_t* __restrict__ bsum, int32_t nb) {
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t b0 = 0; b0 < nb; b0 += 1024) {
+        __shared__ int32_t t[1024];
+        const int32_t i = b0 + (int32_t)threadIdx.x;
+        const int32_t x = i < nb ? bsum[i] : 0;
+        t[threadIdx.x] = x;
+        __syncthreads();
+        for (int o = 1; o < 1024; o <<= 1) {
+            const int32_t y = threadIdx.x >= (unsigned)o ? t[threadIdx.x - o] : 0;
+            __syncthreads();
+            t[threadIdx.x] += y;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + t[threadIdx.x] - x;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += t[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+// Meta words and value records: [c, w1, w2, w3] per position (unused
+// entries 0), further weights in the overflow area after the N records;
+// reverse records list successors u with weight w_{u,v} and mark receivers.
+template <bool FWD>
+__global__ void k_pack_write(SetupDims g, const int32_t* __restrict__ pos, const uint8_t* __restrict__ extm,
+                             const int32_t* __restrict__ off, const int32_t* __restrict__ bsum,
+                             const double* __restrict__ w6, const double* __restrict__ cal,
+                             const uint8_t* __restrict__ rcv, uint64_t* __restrict__ meta, double* __restrict__ wts) {
+    for (int64_t v = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; v < g.N; v += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = pos[v];
+        const uint32_t mask = extm[v];
+        const int64_t o = __builtin_popcount(mask) > 3 ? (int64_t)off[q] + bsum[q >> 10] : 0;
+        double* rec = wts + q * 4;
+        rec[0] = cal[v];
+        double r[3] = {0.0, 0.0, 0.0};
+        uint32_t m = mask;
+        for (int t = 0; m; t++) {
+            const int slot = __builtin_ctz(m);
+            m &= m - 1u;
+            const int d = slot >> 1;
+            const int64_t u = (slot & 1) ? v + g.stride[d] : v - g.stride[d];
+            const double w = FWD ? w6[v * 6 + slot] : w6[u * 6 + (slot ^ 1)];
+            if (t < 3) r[t] = w;
+            else wts[g.N * 4 + o + (t - 3)] = w;
+        }
+        rec[1] = r[0];
+        rec[2] = r[1];
+        rec[3] = r[2];
+        meta[q] = (uint64_t)(uint32_t)v | ((uint64_t)o << kOffShift) | ((uint64_t)mask << kMaskShift) |
+                  (!FWD && rcv[v] ? kRcvFlag : 0ull);
+    }
+}
+
+int device_pack(void* ctxp, bool fwd, int64_t N, const int32_t* pos_of, const int32_t* comp, const uint32_t* pmask,
+                const uint32_t* smask, const double* w6, const double* cal, const uint8_t* rcvflag,
+                Packed::DeviceRecords* out) {
+    LevelCtx& x = *static_cast<LevelCtx*>(ctxp);
+    hipError_t e = hipSuccess;
+    if (!x.stream) e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
+    const int64_t nb = (N + 1023) / 1024;
+    if (e == hipSuccess && !x.pos) {
+        e = hipMalloc(&x.pos, sizeof(int32_t) * (size_t)N);
+        if (e == hipSuccess) e = hipMalloc(&x.comp, sizeof(int32_t) * (size_t)N);
+        if (e == hipSuccess) e = hipMalloc(&x.bsum, sizeof(int32_t) * (size_t)(nb + 1));
+        if (e == hipSuccess && !x.src_w6) e = hipMalloc(&x.w6, sizeof(double) * 6 * (size_t)N);
+        if (e == hipSuccess && !x.src_cal) e = hipMalloc(&x.cal, sizeof(double) * (size_t)N);
+        if (e == hipSuccess) e = hipMalloc(&x.rcv, (size_t)N);
+        if (e == hipSuccess) e = hipMalloc(&x.extm, (size_t)N);
+        if (e == hipSuccess && !x.pm) e = hipMalloc(&x.pm, (size_t)N);
+        if (e == hipSuccess && !x.sm) e = hipMalloc(&x.sm, (size_t)N);
+        if (e == hipSuccess && !x.cnt) e = hipMalloc(&x.cnt, sizeof(int32_t) * (size_t)N);
+    }
+    hipStream_t s = x.stream;
+    const int d = fwd ? 0 : 1;
+    std::vector<uint8_t> m8;
+    const double* dw6 = x.src_w6 ? x.src_w6 : x.w6;
+    const double* dcal = x.src_cal ? x.src_cal : x.cal;
+    if (e == hipSuccess && fwd) {
+        // per state, with the forward direction (always packed first); the
+        // masks (made by the level pass) and the couplings are on the device
+        // already when the couplings pass kept them there
+        if (!x.src_pm) {
+            m8.resize(2 * (size_t)N);
+            for (int64_t v = 0; v < N; v++) {
+                m8[v] = (uint8_t)pmask[v];
+                m8[N + v] = (uint8_t)smask[v];
+            }
+            e = hipMemcpyAsync(x.pm, m8.data(), (size_t)N, hipMemcpyHostToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(x.sm, m8.data() + N, (size_t)N, hipMemcpyHostToDevice, s);
+        }
+        if (e == hipSuccess) e = hipMemcpyAsync(x.comp, comp, sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && !x.src_w6)
+            e = hipMemcpyAsync(x.w6, w6, sizeof(double) * 6 * (size_t)N, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess && !x.src_cal)
+            e = hipMemcpyAsync(x.cal, cal, sizeof(double) * (size_t)N, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(x.rcv, rcvflag, (size_t)N, hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(x.pos, pos_of, sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice, s);
+    const int grid = (int)std::min<int64_t>((N + 255) / 256, 65535);
+    if (e == hipSuccess) {
+        if (fwd) hipLaunchKernelGGL(k_pack_count<true>, dim3(grid), dim3(256), 0, s, x.g, x.pos, x.comp, x.pm, x.sm, x.extm, x.cnt);
+        else hipLaunchKernelGGL(k_pack_count<false>, dim3(grid), dim3(256), 0, s, x.g, x.pos, x.comp, x.pm, x.sm, x.extm, x.cnt);
+        hipLaunchKernelGGL(k_scan_blocks, dim3((unsigned)nb), dim3(1024), 0, s, x.cnt, N, x.bsum);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, x.bsum, (int32_t)nb);
+        e = hipGetLastError();
+    }
+    int32_t total = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&total, x.bsum + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && (int64_t)total > (int64_t)kOffMask + 1) {
+        set_error("state too large for the packed format: record overflow area too large");
+        return FM_EINVAL;
+    }
+    const int64_t nw = 4 * N + total + 4;
+    if (e == hipSuccess) e = hipMalloc(&out->meta[d], sizeof(uint64_t) * (size_t)N);
+    if (e == hipSuccess) e = hipMalloc(&out->wts[d], sizeof(double) * (size_t)nw);
+    if (e == hipSuccess) e = hipMemsetAsync((double*)out->wts[d] + (nw - 4), 0, 4 * sizeof(double), s);
+    if (e == hipSuccess) {
+        if (fwd)
+            hipLaunchKernelGGL(k_pack_write<true>, dim3(grid), dim3(256), 0, s, x.g, x.pos, x.extm, x.cnt, x.bsum, dw6,
+                               dcal, x.rcv, (uint64_t*)out->meta[d], (double*)out->wts[d]);
+        else
+            hipLaunchKernelGGL(k_pack_write<false>, dim3(grid), dim3(256), 0, s, x.g, x.pos, x.extm, x.cnt, x.bsum,
+                               dw6, dcal, x.rcv, (uint64_t*)out->meta[d], (double*)out->wts[d]);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        set_error("GPU setup pass (records): %s", hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? FM_ENOMEM : FM_EHIP;
+    }
+    out->nwts[d] = nw;
+    out->device = x.device;
+    return FM_OK;
+}
 
 int device_levels(void* ctxp, int64_t N, int32_t ncomp, const int32_t* comp, const int32_t* cptr, const int32_t* cnodes,
                   const uint32_t* pmask, const uint32_t* smask, int32_t* clev_f, int32_t* clev_r) {
@@ -378,17 +575,28 @@ int device_levels(void* ctxp, int64_t N, int32_t ncomp, const int32_t* comp, con
             h_bptr[b + 1] = h_bptr[b] + k;
             b++;
         }
-        for (int64_t v = 0; v < N; v++) {
-            h_pm[v] = (uint8_t)pmask[v];
-            h_sm[v] = (uint8_t)smask[v];
-        }
+        if (!x.src_pm)
+            for (int64_t v = 0; v < N; v++) {
+                h_pm[v] = (uint8_t)pmask[v];
+                h_sm[v] = (uint8_t)smask[v];
+            }
     }
     hipStream_t s = x.stream;
     e = hipMemcpyAsync(x.cid, h_cid, sizeof(int32_t) * (size_t)N, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(x.bptr, h_bptr, sizeof(int32_t) * ((size_t)nblk + 1), hipMemcpyHostToDevice, s);
     if (e == hipSuccess && nmem) e = hipMemcpyAsync(x.bmem, h_bmem, sizeof(int32_t) * (size_t)nmem, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(x.pm, h_pm, (size_t)N, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(x.sm, h_sm, (size_t)N, hipMemcpyHostToDevice, s);
+    if (x.src_pm) {
+        // the masks from the source's couplings on the device
+        const int grid = (int)std::min<int64_t>((N + 255) / 256, 65535);
+        if (e == hipSuccess) e = hipMemcpyAsync(x.pm, x.src_pm, (size_t)N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) {
+            hipLaunchKernelGGL(k_setup_smask, dim3(grid), dim3(256), 0, s, x.g, 1, x.pm, x.sm);
+            e = hipGetLastError();
+        }
+    } else {
+        if (e == hipSuccess) e = hipMemcpyAsync(x.pm, h_pm, (size_t)N, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(x.sm, h_sm, (size_t)N, hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) {
         KahnArgs k{};
         k.g = x.g;
@@ -492,6 +700,7 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
         if (hst) (void)hipHostFree(hst);
     };
     hipError_t e = hipGetDevice(&dev);
+    for (LevelCtx& x : lctx) x.device = dev;
     if (e == hipSuccess) e = hipMalloc(&dG, sizeof(double) * (size_t)N * d.ncomp_g);
     if (e == hipSuccess) e = hipMalloc(&ds, sizeof(double) * (size_t)N);
     if (e == hipSuccess) e = hipMalloc(&dw, sizeof(double) * 6 * (size_t)N * chunk);
@@ -518,6 +727,7 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     struct Couplings {
         std::vector<uint8_t> m, t;
         std::vector<double> w, c;
+        void* dev = nullptr;     // device copy of w [N][6], c [N], m [N] for the host thread's device work
     };
     std::vector<Couplings> buf(S);
     std::vector<fm_state*> res(S, nullptr);
@@ -548,7 +758,16 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             Assembled pre{buf[a].m.data(), buf[a].w.data(), buf[a].c.data(), (int64_t)nv[a]};
             pre.trim = buf[a].t.data();
             pre.levels = device_levels;
+            pre.pack = device_pack;
             pre.ctx = &lctx[id];
+            if (buf[a].dev) {
+                lctx[id].src_w6 = (const double*)buf[a].dev;
+                lctx[id].src_cal = lctx[id].src_w6 + (size_t)N * 6;
+                lctx[id].src_pm = (const uint8_t*)(lctx[id].src_cal + (size_t)N);
+            } else {
+                lctx[id].src_w6 = lctx[id].src_cal = nullptr;
+                lctx[id].src_pm = nullptr;
+            }
             fm_state* stt = nullptr;
             const int r = build_state(g, nullptr, s, src_nodes[a],
                                       n_rcv > 0 ? rcv_nodes + (size_t)a * per_src : nullptr,
@@ -559,6 +778,12 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             if (r != FM_OK) msgs[a] = fm_last_error();
             std::vector<uint8_t>().swap(buf[a].m);
             std::vector<uint8_t>().swap(buf[a].t);
+            if (buf[a].dev) {
+                (void)hipFree(buf[a].dev);
+                buf[a].dev = nullptr;
+            }
+            lctx[id].src_w6 = lctx[id].src_cal = nullptr;
+            lctx[id].src_pm = nullptr;
             std::vector<double>().swap(buf[a].w);
             std::vector<double>().swap(buf[a].c);
         }
@@ -612,9 +837,27 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             msg = std::string("GPU setup pass failed: ") + hipGetErrorString(e);
             break;
         }
+        // each source's couplings stay on the device for its host thread
+        // (their device work then needs no upload); without the memory for
+        // it the host thread uploads them
+        for (int32_t k = 0; k < n && e == hipSuccess; k++) {
+            void* p = nullptr;
+            if (hipMalloc(&p, (size_t)N * (6 * sizeof(double) + sizeof(double) + 1)) != hipSuccess) {
+                (void)hipGetLastError();
+                break;
+            }
+            buf[a0 + k].dev = p;
+            e = hipMemcpyAsync(p, dw + (size_t)k * N * 6, sizeof(double) * 6 * (size_t)N, hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync((double*)p + (size_t)N * 6, dc + (size_t)k * N, sizeof(double) * (size_t)N,
+                                   hipMemcpyDeviceToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync((double*)p + (size_t)N * 7, dm + (size_t)k * N, (size_t)N, hipMemcpyDeviceToDevice, st);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
         // the next chunk's device work runs while this one is copied out of
         // the staging (one host thread per source)
-        if (a0 + chunk < S) e = launch_chunk(a0 + chunk);
+        if (e == hipSuccess && a0 + chunk < S) e = launch_chunk(a0 + chunk);
         {
             std::vector<std::thread> cps;
             for (int32_t k = 0; k < n; k++)
@@ -651,6 +894,8 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             rc = rcs[a] != FM_OK ? rcs[a] : FM_EHIP;
             msg = "source " + std::to_string(a) + ": " + msgs[a];
         }
+    for (Couplings& cp : buf)
+        if (cp.dev) (void)hipFree(cp.dev);
     release();
     if (rc != FM_OK) {
         for (auto* p : res) fm_state_free(p);

@@ -6,7 +6,7 @@ host from them.
   nodes): W and c bit-identical to the oracle's assembly and to the host
   setup, the same SCC partition and identical levels in both directions,
   identical structure statistics, and J / J^T bit-identical to the states
-  of the host setup;
+  of the host setup in FP64 and FP32 (records packed on the device);
 * the singular fixture gives FM_ESINGULAR; a traveltime that is not finite
   or not 0 at the source gives FM_EINVAL;
 * c4 at full size (64 sources): identical statistics and operators on
@@ -65,20 +65,22 @@ def _check_workload(wl, S, B):
         groups = np.split(order, np.nonzero(np.diff(comp[order]))[0] + 1)
         mine = [np.sort(g) for g in groups if g.size > 1]
         assert diag.same_partition(mine, diag.scc_summary(op.W))
-    # the applies of both sets of states give the same bits
+    # the applies of both sets of states give the same bits (FP64 and the
+    # FP32 records, converted on the host or on the device)
     dev = torch.device("cuda:0")
-    ds = torch.from_numpy(seeded_ds(wl, B, 5100, S=S)).to(dev)
-    outs = []
-    for states in (host, gpu):
-        batch = fm.Batch(states, B, fm.FM_FP64)
-        x = torch.empty((S, wl.N, B), dtype=torch.float64, device=dev)
-        g = torch.empty((wl.N, B), dtype=torch.float64, device=dev)
-        batch.apply_J(ds, fm.FM_DS_PER_PAIR, x, fm.FM_OUT_NODES)
-        batch.apply_JT(x, fm.FM_W_NODES, g, fm.FM_JT_SUMMED)
-        batch.status()
-        outs.append((x, g))
-        batch.free()
-    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    for prec, dt in ((fm.FM_FP64, torch.float64), (fm.FM_FP32, torch.float32)):
+        ds = torch.from_numpy(seeded_ds(wl, B, 5100, S=S)).to(dev, dt)
+        outs = []
+        for states in (host, gpu):
+            batch = fm.Batch(states, B, prec)
+            x = torch.empty((S, wl.N, B), dtype=dt, device=dev)
+            g = torch.empty((wl.N, B), dtype=dt, device=dev)
+            batch.apply_J(ds, fm.FM_DS_PER_PAIR, x, fm.FM_OUT_NODES)
+            batch.apply_JT(x, fm.FM_W_NODES, g, fm.FM_JT_SUMMED)
+            batch.status()
+            outs.append((x, g))
+            batch.free()
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
 
 
 def test_c1_matches_host_and_oracle():
@@ -97,11 +99,7 @@ def test_curved_fixture_matches_host_and_oracle():
 def test_c3_matches_host_and_oracle():
     wl = W.config("c3")
     print(f"case gpu setup c3 101x101x51, S={wl.S}", flush=True)
-    host = states_for(fm, wl)
-    gpu = _gpu_states(wl)
-    for a in range(wl.S):
-        _same_state(gpu[a], host[a])
-    print(f"  blocks per source {[s.stats()['n_scc'] for s in gpu]}", flush=True)
+    _check_workload(wl, wl.S, 16)
 
 
 def test_singular_block_and_bad_traveltimes():
