@@ -193,12 +193,10 @@ __device__ __forceinline__ void frontier_push(int32_t* __restrict__ F, int* s_n,
 }
 
 template <bool REV, bool IDENT>
-__global__ __launch_bounds__(1024) void k_kahn(KahnArgs k) {
+__device__ __forceinline__ void kahn_run(const KahnArgs& k, int64_t off, int64_t moff) {
     const SetupDims& g = k.g;
     const int64_t N = g.N;
     const int32_t nc = (int32_t)N + (IDENT ? 0 : k.nblk);
-    const int64_t off = (int64_t)blockIdx.x * nc;
-    const int64_t moff = (int64_t)blockIdx.x * N;
     const uint8_t* __restrict__ inm = (REV ? k.smask : k.pmask) + moff;
     const uint8_t* __restrict__ outm = (REV ? k.pmask : k.smask) + moff;
     int32_t* __restrict__ cnt = k.cnt + off;
@@ -293,6 +291,21 @@ __global__ __launch_bounds__(1024) void k_kahn(KahnArgs k) {
     }
 }
 
+// One source per workgroup, its arrays at the workgroup's offset.
+template <bool REV, bool IDENT>
+__global__ __launch_bounds__(1024) void k_kahn(KahnArgs k) {
+    const int32_t nc = (int32_t)k.g.N + (IDENT ? 0 : k.nblk);
+    kahn_run<REV, IDENT>(k, (int64_t)blockIdx.x * nc, (int64_t)blockIdx.x * k.g.N);
+}
+
+// Several sources' eliminations over their components in one launch: one
+// workgroup per job, each with arrays of its own.
+template <bool REV>
+__global__ __launch_bounds__(1024) void k_kahn_jobs(const KahnArgs* __restrict__ jobs) {
+    const KahnArgs k = jobs[blockIdx.x];
+    kahn_run<REV, false>(k, 0, 0);
+}
+
 // Nodes removed by the forward (bit 0) and the reverse (bit 1) elimination.
 __global__ void k_trim_flags(int64_t total, const int32_t* __restrict__ lf, const int32_t* __restrict__ lr,
                              uint8_t* __restrict__ flags) {
@@ -300,9 +313,93 @@ __global__ void k_trim_flags(int64_t total, const int32_t* __restrict__ lf, cons
         flags[t] = (uint8_t)((lf[t] >= 0 ? 1 : 0) | (lr[t] >= 0 ? 2 : 0));
 }
 
+// The host threads' level eliminations, batched: each thread hands over
+// the arguments of its two eliminations (inputs already on the device) and
+// waits; the server launches every job pending at that moment in one launch
+// per direction, so that the small one-workgroup eliminations of many
+// sources run side by side instead of queueing behind each other.
+struct LevelServer {
+    struct Job {
+        KahnArgs f, r;
+        bool done = false;
+        hipError_t err = hipSuccess;
+    };
+    std::mutex mu;
+    std::condition_variable cv_job, cv_done;
+    std::vector<Job*> pending;
+    bool stop = false;
+    int device = 0;
+    std::thread th;
+    void run() {
+        hipStream_t st = nullptr;
+        KahnArgs* dargs = nullptr;
+        size_t cap = 0;
+        hipError_t e = hipSetDevice(device);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        for (;;) {
+            std::vector<Job*> batch;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                cv_job.wait(lk, [&]() { return stop || !pending.empty(); });
+                if (pending.empty()) break;
+                batch.swap(pending);
+            }
+            const size_t n = batch.size();
+            std::vector<KahnArgs> h(2 * n);
+            for (size_t i = 0; i < n; i++) {
+                h[i] = batch[i]->f;
+                h[n + i] = batch[i]->r;
+            }
+            if (e == hipSuccess && cap < 2 * n) {
+                if (dargs) (void)hipFree(dargs);
+                dargs = nullptr;
+                cap = std::max<size_t>(2 * n, 32);
+                e = hipMalloc(&dargs, sizeof(KahnArgs) * cap);
+            }
+            if (e == hipSuccess) e = hipMemcpyAsync(dargs, h.data(), sizeof(KahnArgs) * 2 * n, hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) {
+                hipLaunchKernelGGL(k_kahn_jobs<false>, dim3((unsigned)n), dim3(1024), 0, st, dargs);
+                hipLaunchKernelGGL(k_kahn_jobs<true>, dim3((unsigned)n), dim3(1024), 0, st, dargs + n);
+                e = hipGetLastError();
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            {
+                std::lock_guard<std::mutex> lk(mu);
+                for (Job* j : batch) {
+                    j->err = e;
+                    j->done = true;
+                }
+            }
+            cv_done.notify_all();
+        }
+        if (dargs) (void)hipFree(dargs);
+        if (st) (void)hipStreamDestroy(st);
+    }
+    hipError_t submit(Job& j) {
+        std::unique_lock<std::mutex> lk(mu);
+        pending.push_back(&j);
+        cv_job.notify_one();
+        cv_done.wait(lk, [&]() { return j.done; });
+        return j.err;
+    }
+    void start(int dev) {
+        device = dev;
+        th = std::thread([this]() { run(); });
+    }
+    void finish() {
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            stop = true;
+        }
+        cv_job.notify_all();
+        if (th.joinable()) th.join();
+    }
+};
+
 // Per host thread: a stream, device buffers and pinned host staging for the
 // condensation levels and the records of the states it finishes.
 struct LevelCtx {
+    LevelServer* server = nullptr;
     SetupDims g;
     int device = 0;
     hipStream_t stream = nullptr;
@@ -609,11 +706,22 @@ int device_levels(void* ctxp, int64_t N, int32_t ncomp, const int32_t* comp, con
         k.cnt = x.cnt;
         k.f0 = x.f0;
         k.f1 = x.f1;
-        k.lev = x.lf;
-        hipLaunchKernelGGL((k_kahn<false, false>), dim3(1), dim3(1024), 0, s, k);
-        k.lev = x.lr;
-        hipLaunchKernelGGL((k_kahn<true, false>), dim3(1), dim3(1024), 0, s, k);
-        e = hipGetLastError();
+        if (x.server) {
+            // inputs on the device first, then the batched eliminations
+            e = hipStreamSynchronize(s);
+            LevelServer::Job job;
+            job.f = k;
+            job.f.lev = x.lf;
+            job.r = k;
+            job.r.lev = x.lr;
+            if (e == hipSuccess) e = x.server->submit(job);
+        } else {
+            k.lev = x.lf;
+            hipLaunchKernelGGL((k_kahn<false, false>), dim3(1), dim3(1024), 0, s, k);
+            k.lev = x.lr;
+            hipLaunchKernelGGL((k_kahn<true, false>), dim3(1), dim3(1024), 0, s, k);
+            e = hipGetLastError();
+        }
     }
     // the inputs in the staging area are consumed once the kernels have run
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -691,7 +799,11 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     char* hst = nullptr;         // pinned staging of one chunk's couplings and trim flags
     int dev = 0;
     std::vector<LevelCtx> lctx(nt);
-    for (LevelCtx& x : lctx) x.g = d;
+    LevelServer server;
+    for (LevelCtx& x : lctx) {
+        x.g = d;
+        x.server = &server;
+    }
     auto release = [&]() {
         for (void* p : {(void*)dG, (void*)ds, (void*)dw, (void*)dc, (void*)dm, (void*)dsrc, (void*)dnv, (void*)dbad,
                         (void*)dsm, (void*)dtr, (void*)dcnt, (void*)df0, (void*)df1, (void*)dlf, (void*)dlr})
@@ -730,6 +842,9 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
         void* dev = nullptr;     // device copy of w [N][6], c [N], m [N] for the host thread's device work
     };
     std::vector<Couplings> buf(S);
+    // device copies of the couplings, recycled between sources
+    std::mutex pool_mu;
+    std::vector<void*> pool_free, pool_all;
     std::vector<fm_state*> res(S, nullptr);
     std::vector<unsigned long long> nv(S);
     std::vector<int> bad(S);
@@ -779,7 +894,9 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             std::vector<uint8_t>().swap(buf[a].m);
             std::vector<uint8_t>().swap(buf[a].t);
             if (buf[a].dev) {
-                (void)hipFree(buf[a].dev);
+                // back to the pool (a hipFree here would wait for the whole device)
+                std::lock_guard<std::mutex> lk(pool_mu);
+                pool_free.push_back(buf[a].dev);
                 buf[a].dev = nullptr;
             }
             lctx[id].src_w6 = lctx[id].src_cal = nullptr;
@@ -788,6 +905,7 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
             std::vector<double>().swap(buf[a].c);
         }
     };
+    server.start(dev);
     std::vector<std::thread> th;
     for (int i = 0; i < nt; i++) th.emplace_back(worker, i);
     int rc = FM_OK;
@@ -842,9 +960,20 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
         // it the host thread uploads them
         for (int32_t k = 0; k < n && e == hipSuccess; k++) {
             void* p = nullptr;
-            if (hipMalloc(&p, (size_t)N * (6 * sizeof(double) + sizeof(double) + 1)) != hipSuccess) {
-                (void)hipGetLastError();
-                break;
+            {
+                std::lock_guard<std::mutex> lk(pool_mu);
+                if (!pool_free.empty()) {
+                    p = pool_free.back();
+                    pool_free.pop_back();
+                }
+            }
+            if (!p) {
+                if (hipMalloc(&p, (size_t)N * (6 * sizeof(double) + sizeof(double) + 1)) != hipSuccess) {
+                    (void)hipGetLastError();
+                    break;
+                }
+                std::lock_guard<std::mutex> lk(pool_mu);
+                pool_all.push_back(p);
             }
             buf[a0 + k].dev = p;
             e = hipMemcpyAsync(p, dw + (size_t)k * N * 6, sizeof(double) * 6 * (size_t)N, hipMemcpyDeviceToDevice, st);
@@ -889,13 +1018,13 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     }
     cv.notify_all();
     for (auto& t : th) t.join();
+    server.finish();
     for (int32_t a = 0; a < S && rc == FM_OK; a++)
         if (res[a] == nullptr || rcs[a] != FM_OK) {
             rc = rcs[a] != FM_OK ? rcs[a] : FM_EHIP;
             msg = "source " + std::to_string(a) + ": " + msgs[a];
         }
-    for (Couplings& cp : buf)
-        if (cp.dev) (void)hipFree(cp.dev);
+    for (void* p : pool_all) (void)hipFree(p);
     release();
     if (rc != FM_OK) {
         for (auto* p : res) fm_state_free(p);
