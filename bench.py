@@ -396,6 +396,15 @@ def main():
     tT = np.array([e[0].elapsed_time(e[1]) for e in eT[1:]])
     log(f"eager applies ({reps} each): J {tJ.mean():.3f} ms (median {np.median(tJ):.3f}), "
         f"J^T {tT.mean():.3f} ms (median {np.median(tT):.3f})")
+    # the node split's placement in the last launch: sources whose workgroups
+    # all ran on one XCD exchange their node values through one L2 (the
+    # others paid device-scope fences at every level)
+    placement = None
+    if batch.tuning()["split"] > 1:
+        xm = batch.split_info()
+        one = int(sum(1 for m in xm if bin(int(m) & 0xFFFFFFFF).count("1") == 1))
+        placement = {"sources_on_one_xcd": one, "sources": int(len(xm))}
+        log(f"node split placement: {one} of {len(xm)} sources on one XCD")
 
     # roofline of the dominant kernel: the primal sweep (one launch per apply_J,
     # between a counter reset of S words and the receiver gather of S*R*B
@@ -417,6 +426,7 @@ def main():
             "bytes_layout_broadcast_once": layout_bytes(stats, B, vbytes, vbytes, broadcast_once=True),
             "launch_ms": round(float(tJ.mean()), 4), "launch_ms_median": round(float(np.median(tJ)), 4),
             "launches_timed": reps,
+            "placement": placement,
             "transpose_GBs_incl_source_sum": round(gbs_T, 1)}
     # what a plain device copy sustains on this GPU (2 GiB read + 2 GiB
     # written per copy), and the primal kernel's counted bytes per second

@@ -3,7 +3,8 @@ calls): the host setup's W and c are bit-identical to the oracle's cube
 assembly (same FP64 operations in the same order), and its SCC partition,
 condensation levels and structural statistics match the oracle's graph
 diagnostics, on 2-D and 3-D deformed grids, the curved-wavefront fixture and
-c3, and with an off-grid point source (identity seed rows); an unknown
+c3, on degenerate grids (3 x 3, a 200 x 3 strip, 3 x 3 x 3, a 3 x 3 x 40
+column), and with an off-grid point source (identity seed rows); an unknown
 stencil value is rejected.
 """
 import numpy as np
@@ -43,6 +44,24 @@ def test_cube_setup_matches_oracle_deformed_3d():
     wl = _cube(W.smooth_3d(25, 23, 13, topo_amp=0.2))
     st, op = _compare_operator(wl)
     _compare_graph(st, op, wl.T[0])
+
+
+@pytest.mark.parametrize("case", ["3x3", "strip", "3x3x3", "column"])
+def test_cube_setup_matches_oracle_degenerate(case):
+    """The smallest grids and a strip and column a few nodes wide: most nodes
+    are boundary nodes, so most rows take the projected (one-sided) form."""
+    make = {
+        "3x3": lambda: W.grids.deformed_2d(3, 3, 7001, 0.0, 0, S=1, B=16, R=2, name="3x3"),
+        "strip": lambda: W.grids.deformed_2d(200, 3, 7002, 0.1, 1, S=2, B=16, R=7, name="strip 200x3"),
+        "3x3x3": lambda: W.grids.deformed_3d(3, 3, 3, 7003, 1, 1, 16, 2, 2, name="3x3x3"),
+        "column": lambda: W.grids.deformed_3d(3, 3, 40, 7004, 1, 1, 16, 1, 1, name="column 3x3x40"),
+    }
+    wl = make[case]()
+    W.eikonal(wl)
+    _cube(wl)
+    for a in range(wl.S):
+        st, op = _compare_operator(wl, a)
+        _compare_graph(st, op, wl.T[a])
 
 
 @pytest.mark.slow

@@ -189,6 +189,31 @@ def test_repeated_applies_reuse_counters(curved):
     batch.free()
 
 
+@pytest.mark.parametrize("tuning", [{"split": 8, "threads": 256, "unroll": 3},
+                                    {"balance": 3, "threads": 256, "unroll": 3}], ids=["uniform", "balanced"])
+def test_split_placement_report(multi2d, tuning):
+    """fm_batch_split_info reports, per source, the XCDs its workgroups ran on
+    in the last apply: a non-empty set of the 8 XCDs; the rhs-group kernel has
+    no such report."""
+    wl, states, ops = multi2d
+    B = 16
+    dev = torch.device("cuda:0")
+    batch = fm.Batch(states, B, fm.FM_FP64, tuning=tuning)
+    ds = torch.from_numpy(seeded_ds(wl, B, 1400)).to(dev)
+    o = torch.empty((wl.S, wl.N, B), device=dev, dtype=torch.float64)
+    batch.apply_J(ds, fm.FM_DS_PER_PAIR, o, fm.FM_OUT_NODES)
+    batch.status()
+    xm = batch.split_info().astype(np.int64) & 0xFFFFFFFF
+    one = sum(1 for m in xm if bin(int(m)).count("1") == 1)
+    print(f"  {tuning}: masks {[hex(int(m)) for m in xm]}, {one} of {wl.S} sources on one XCD", flush=True)
+    assert xm.shape == (wl.S,) and np.all(xm != 0) and np.all(xm < 256)
+    batch.free()
+    b1 = fm.Batch(states, B, fm.FM_FP64, tuning={"split": 1})
+    with pytest.raises(fm.FmError):
+        b1.split_info()
+    b1.free()
+
+
 def test_autotune_picks_a_measured_schedule(curved, tmp_path):
     """The schedule search measures the rhs-group kernel and every node-split
     shape that fits, returns the fastest, and that schedule reproduces the
