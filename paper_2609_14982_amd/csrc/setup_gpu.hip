@@ -298,12 +298,23 @@ __global__ __launch_bounds__(1024) void k_kahn(KahnArgs k) {
     kahn_run<REV, IDENT>(k, (int64_t)blockIdx.x * nc, (int64_t)blockIdx.x * k.g.N);
 }
 
+// Trimming of n sources in one launch: workgroups [0, n) run the forward
+// eliminations, [n, 2n) the reverse ones (each direction with counters and
+// frontiers of its own, so the two run side by side).
+__global__ __launch_bounds__(1024) void k_kahn_trim(KahnArgs kf, KahnArgs kr, int32_t n) {
+    const bool rev = (int32_t)blockIdx.x >= n;
+    const int64_t off = (int64_t)(rev ? blockIdx.x - n : blockIdx.x) * kf.g.N;
+    if (rev) kahn_run<true, true>(kr, off, off);
+    else kahn_run<false, true>(kf, off, off);
+}
+
 // Several sources' eliminations over their components in one launch: one
-// workgroup per job, each with arrays of its own.
-template <bool REV>
-__global__ __launch_bounds__(1024) void k_kahn_jobs(const KahnArgs* __restrict__ jobs) {
+// workgroup per job, each with arrays of its own; jobs [0, n) forward,
+// [n, 2n) reverse.
+__global__ __launch_bounds__(1024) void k_kahn_jobs(const KahnArgs* __restrict__ jobs, int32_t n) {
     const KahnArgs k = jobs[blockIdx.x];
-    kahn_run<REV, false>(k, 0, 0);
+    if ((int32_t)blockIdx.x >= n) kahn_run<true, false>(k, 0, 0);
+    else kahn_run<false, false>(k, 0, 0);
 }
 
 // Nodes removed by the forward (bit 0) and the reverse (bit 1) elimination.
@@ -358,8 +369,8 @@ struct LevelServer {
             }
             if (e == hipSuccess) e = hipMemcpyAsync(dargs, h.data(), sizeof(KahnArgs) * 2 * n, hipMemcpyHostToDevice, st);
             if (e == hipSuccess) {
-                hipLaunchKernelGGL(k_kahn_jobs<false>, dim3((unsigned)n), dim3(1024), 0, st, dargs);
-                hipLaunchKernelGGL(k_kahn_jobs<true>, dim3((unsigned)n), dim3(1024), 0, st, dargs + n);
+                hipLaunchKernelGGL(k_kahn_jobs, dim3((unsigned)(2 * n)), dim3(1024), 0, st, (const KahnArgs*)dargs,
+                                   (int32_t)n);
                 e = hipGetLastError();
             }
             if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -406,6 +417,7 @@ struct LevelCtx {
     int64_t cap = 0;             // N + the most nontrivial components seen
     int32_t *cid = nullptr, *bptr = nullptr, *bmem = nullptr, *cnt = nullptr, *f0 = nullptr, *f1 = nullptr,
             *lf = nullptr, *lr = nullptr;
+    int32_t *cnt_r = nullptr, *f0_r = nullptr, *f1_r = nullptr;   // the reverse elimination's own
     uint8_t *pm = nullptr, *sm = nullptr;
     char* host = nullptr;        // pinned: cid, masks, block lists in; levels out
     // records: placement, components, weights, calibration, receiver flags,
@@ -419,12 +431,14 @@ struct LevelCtx {
     const uint8_t* src_pm = nullptr;
     void release() {
         for (void* p : {(void*)cid, (void*)bptr, (void*)bmem, (void*)cnt, (void*)f0, (void*)f1, (void*)lf, (void*)lr,
+                        (void*)cnt_r, (void*)f0_r, (void*)f1_r,
                         (void*)pm, (void*)sm, (void*)pos, (void*)comp, (void*)bsum, (void*)w6, (void*)cal, (void*)rcv,
                         (void*)extm})
             if (p) (void)hipFree(p);
         if (host) (void)hipHostFree(host);
         if (stream) (void)hipStreamDestroy(stream);
         cid = bptr = bmem = cnt = f0 = f1 = lf = lr = nullptr;
+        cnt_r = f0_r = f1_r = nullptr;
         pm = sm = nullptr;
         pos = comp = bsum = nullptr;
         w6 = cal = nullptr;
@@ -638,7 +652,7 @@ int device_levels(void* ctxp, int64_t N, int32_t ncomp, const int32_t* comp, con
         x.release();
         e = hipStreamCreateWithFlags(&x.stream, hipStreamNonBlocking);
         x.cap = cap;
-        for (int32_t** p : {&x.cid, &x.bmem, &x.cnt, &x.f0, &x.f1, &x.lf, &x.lr})
+        for (int32_t** p : {&x.cid, &x.bmem, &x.cnt, &x.f0, &x.f1, &x.lf, &x.lr, &x.cnt_r, &x.f0_r, &x.f1_r})
             if (e == hipSuccess) e = hipMalloc(p, sizeof(int32_t) * (size_t)cap);
         if (e == hipSuccess) e = hipMalloc(&x.bptr, sizeof(int32_t) * ((size_t)cap + 1));
         if (e == hipSuccess) e = hipMalloc(&x.pm, (size_t)N);
@@ -713,6 +727,9 @@ int device_levels(void* ctxp, int64_t N, int32_t ncomp, const int32_t* comp, con
             job.f = k;
             job.f.lev = x.lf;
             job.r = k;
+            job.r.cnt = x.cnt_r;
+            job.r.f0 = x.f0_r;
+            job.r.f1 = x.f1_r;
             job.r.lev = x.lr;
             if (e == hipSuccess) e = x.server->submit(job);
         } else {
@@ -788,11 +805,13 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     // couplings at most); host threads finish the states of one chunk while
     // the device computes the next
     // (couplings 57 bytes per node, the eliminations' masks, counters,
-    // frontiers and levels 22 more)
+    // frontiers and levels 22 more, the reverse elimination's own counters
+    // and frontiers 12 more outside this budget)
     const int32_t chunk = (int32_t)std::max<int64_t>(1, std::min<int64_t>(nt, (int64_t)(2LL << 30) / (N * 79)));
     double *dG = nullptr, *ds = nullptr, *dw = nullptr, *dc = nullptr;
     uint8_t *dm = nullptr, *dsm = nullptr, *dtr = nullptr;
     int32_t *dcnt = nullptr, *df0 = nullptr, *df1 = nullptr, *dlf = nullptr, *dlr = nullptr;
+    int32_t *dcnt_r = nullptr, *df0_r = nullptr, *df1_r = nullptr;
     int64_t* dsrc = nullptr;
     unsigned long long* dnv = nullptr;
     int* dbad = nullptr;
@@ -806,7 +825,8 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     }
     auto release = [&]() {
         for (void* p : {(void*)dG, (void*)ds, (void*)dw, (void*)dc, (void*)dm, (void*)dsrc, (void*)dnv, (void*)dbad,
-                        (void*)dsm, (void*)dtr, (void*)dcnt, (void*)df0, (void*)df1, (void*)dlf, (void*)dlr})
+                        (void*)dsm, (void*)dtr, (void*)dcnt, (void*)df0, (void*)df1, (void*)dlf, (void*)dlr,
+                        (void*)dcnt_r, (void*)df0_r, (void*)df1_r})
             if (p) (void)hipFree(p);
         for (LevelCtx& x : lctx) x.release();
         if (hst) (void)hipHostFree(hst);
@@ -820,7 +840,7 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
     if (e == hipSuccess) e = hipMalloc(&dm, (size_t)N * chunk);
     if (e == hipSuccess) e = hipMalloc(&dsm, (size_t)N * chunk);
     if (e == hipSuccess) e = hipMalloc(&dtr, (size_t)N * chunk);
-    for (int32_t** p : {&dcnt, &df0, &df1, &dlf, &dlr})
+    for (int32_t** p : {&dcnt, &df0, &df1, &dlf, &dlr, &dcnt_r, &df0_r, &df1_r})
         if (e == hipSuccess) e = hipMalloc(p, sizeof(int32_t) * (size_t)N * chunk);
     if (e == hipSuccess) e = hipHostMalloc((void**)&hst, (size_t)N * chunk * (2 + 7 * sizeof(double)));
     if (e == hipSuccess) e = hipMalloc(&dsrc, sizeof(int64_t) * S);
@@ -920,17 +940,20 @@ extern "C" int fm_build_frozen_states_gpu(const fm_grid* g, int32_t S, const dou
         // trimming: Kahn's elimination forward and backward, one workgroup
         // per source; the nodes neither removes hold every cycle
         hipLaunchKernelGGL(k_setup_smask, dim3(grid), dim3(256), 0, st, d, n, dm, dsm);
-        KahnArgs k{};
-        k.g = d;
-        k.pmask = dm;
-        k.smask = dsm;
-        k.cnt = dcnt;
-        k.f0 = df0;
-        k.f1 = df1;
-        k.lev = dlf;
-        hipLaunchKernelGGL((k_kahn<false, true>), dim3(n), dim3(1024), 0, st, k);
-        k.lev = dlr;
-        hipLaunchKernelGGL((k_kahn<true, true>), dim3(n), dim3(1024), 0, st, k);
+        KahnArgs kf{};
+        kf.g = d;
+        kf.pmask = dm;
+        kf.smask = dsm;
+        kf.cnt = dcnt;
+        kf.f0 = df0;
+        kf.f1 = df1;
+        kf.lev = dlf;
+        KahnArgs kr = kf;
+        kr.cnt = dcnt_r;
+        kr.f0 = df0_r;
+        kr.f1 = df1_r;
+        kr.lev = dlr;
+        hipLaunchKernelGGL(k_kahn_trim, dim3((unsigned)(2 * n)), dim3(1024), 0, st, kf, kr, n);
         hipLaunchKernelGGL(k_trim_flags, dim3(grid), dim3(256), 0, st, total, dlf, dlr, dtr);
         return hipGetLastError();
     };
