@@ -247,6 +247,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sources", type=int, default=4)
     ap.add_argument("--no-sweep", action="store_true", help="skip the directional-sweeping comparison")
+    ap.add_argument("--no-gpu-setup", action="store_true",
+                    help="skip timing the GPU setup pass on the same traveltimes (outside the timed region)")
     ap.add_argument("--roofline-reps", type=int, default=20, help="eager J and J^T launches timed for the roofline")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of a known size (HBM counter calibration)")
@@ -312,6 +314,24 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+
+    setup_gpu = None
+    if args.stencil == 6 and not args.no_gpu_setup:
+        # the same states from the GPU setup pass, timed for the record (the
+        # applies below use the host-built states; the two give the same bits)
+        Td = torch.from_numpy(np.ascontiguousarray(wl.T)).to(dev)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        gstates = fm.build_frozen_states_gpu(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, Td, wl.s, wl.src, wl.rcv)
+        torch.cuda.synchronize()
+        tg = time.perf_counter() - t1
+        keys = ("N", "E", "n_scc", "largest_scc", "levels_fwd", "levels_rev", "sum_k2")
+        same = all(g.stats()[k] == h[k] for g, h in zip(gstates, stats) for k in keys)
+        for gs in gstates:
+            gs.free()
+        del gstates, Td
+        setup_gpu = {"seconds": round(tg, 2), "same_structure_as_host": bool(same)}
+        log(f"setup (GPU pass, same traveltimes): {tg:.2f}s; structure {'matches' if same else 'DIFFERS from'} the host's")
 
     prec = fm.FM_FP64 if args.precision == "fp64" else fm.FM_FP32
     dt = torch.float64 if prec == fm.FM_FP64 else torch.float32
@@ -529,6 +549,7 @@ def main():
                                         for t, ms in tune_table] if tune_table else None),
                    "grid": [wl.n1, wl.n2, wl.n3], "sources": S, "rhs": B, "receivers": R,
                    "setup_s": round(setup_wall, 2),
+                   "setup_gpu_pass": setup_gpu,
                    "levels_fwd_max": max(s["levels_fwd"] for s in stats),
                    "n_scc_total": sum(s["n_scc"] for s in stats),
                    "largest_scc": max(s["largest_scc"] for s in stats),
