@@ -247,40 +247,72 @@ __device__ __forceinline__ void kahn_run(const KahnArgs& k, int64_t off, int64_t
     }
     __syncthreads();
     int cur = s_n;
+    // KU frontier entries per thread with their loads in flight together
+    // (entries, then masks, then the neighbours' component ids, then the
+    // counter decrements), so that a round takes a few memory round trips
+    // whatever the frontier's size
+    constexpr int KU = 4;
     for (int32_t r = 0; cur > 0; r++) {
         __syncthreads();
         if (threadIdx.x == 0) s_n = 0;
         __syncthreads();
-        for (int i = threadIdx.x; i - (int)threadIdx.x < cur; i += blockDim.x) {
-            const bool live = i < cur;
-            const int32_t c = live ? F[i] : 0;
-            if (live) lev[c] = r;
-            int32_t j = -1, j1 = live ? 0 : -1;
-            if (live && c >= N) {
-                j = k.bptr[c - N];
-                j1 = k.bptr[c - N + 1];
+        const int step = (int)blockDim.x * KU;
+        for (int base = 0; base < cur; base += step) {
+            int32_t c[KU];
+            bool live[KU];
+#pragma unroll
+            for (int u = 0; u < KU; u++) {
+                const int i = base + u * (int)blockDim.x + (int)threadIdx.x;
+                live[u] = i < cur;
+                c[u] = live[u] ? F[i] : 0;
             }
-            // one member per step, every lane of the wave at the same pushes
-            for (;;) {
-                const bool has = j < j1;
-                if (!__any(has)) break;
-                int32_t cu[6];
-                bool ready[6];
+            uint32_t mk[KU];
 #pragma unroll
-                for (int slot = 0; slot < 6; slot++) ready[slot] = false;
-                if (has) {
-                    const int64_t m = j < 0 ? c : k.bmem[j];
-                    nbr_ids(m, outm[m], cu);
+            for (int u = 0; u < KU; u++) {
+                if (live[u]) lev[c[u]] = r;
+                mk[u] = (live[u] && c[u] < N) ? (uint32_t)outm[c[u]] : 0u;     // singletons here, blocks below
+            }
+            int32_t cu[KU][6];
 #pragma unroll
-                    for (int slot = 0; slot < 6; slot++)
-                        if (cu[slot] >= 0 && cu[slot] != c) ready[slot] = atomicSub(cnt + cu[slot], 1) == 1;
-                } else {
+            for (int u = 0; u < KU; u++) nbr_ids(c[u], mk[u], cu[u]);
+            bool ready[KU][6];
 #pragma unroll
-                    for (int slot = 0; slot < 6; slot++) cu[slot] = 0;
+            for (int u = 0; u < KU; u++)
+#pragma unroll
+                for (int slot = 0; slot < 6; slot++)
+                    ready[u][slot] = cu[u][slot] >= 0 && cu[u][slot] != c[u] && atomicSub(cnt + cu[u][slot], 1) == 1;
+#pragma unroll
+            for (int u = 0; u < KU; u++)
+#pragma unroll
+                for (int slot = 0; slot < 6; slot++) frontier_push(Fn, &s_n, ready[u][slot], cu[u][slot]);
+            // nontrivial components: one member per step, every lane of the
+            // wave at the same pushes
+            for (int u = 0; u < KU; u++) {
+                const bool blk = live[u] && c[u] >= N;
+                if (!__any(blk)) continue;
+                int32_t j = blk ? k.bptr[c[u] - N] : 0;
+                const int32_t j1 = blk ? k.bptr[c[u] - N + 1] : 0;
+                for (;;) {
+                    const bool has = j < j1;
+                    if (!__any(has)) break;
+                    int32_t cb[6];
+                    bool rb[6];
+#pragma unroll
+                    for (int slot = 0; slot < 6; slot++) {
+                        cb[slot] = 0;
+                        rb[slot] = false;
+                    }
+                    if (has) {
+                        const int64_t m = k.bmem[j];
+                        nbr_ids(m, outm[m], cb);
+#pragma unroll
+                        for (int slot = 0; slot < 6; slot++)
+                            rb[slot] = cb[slot] >= 0 && cb[slot] != c[u] && atomicSub(cnt + cb[slot], 1) == 1;
+                    }
+#pragma unroll
+                    for (int slot = 0; slot < 6; slot++) frontier_push(Fn, &s_n, rb[slot], cb[slot]);
+                    j++;
                 }
-#pragma unroll
-                for (int slot = 0; slot < 6; slot++) frontier_push(Fn, &s_n, ready[slot], cu[slot]);
-                j++;
             }
         }
         __syncthreads();
