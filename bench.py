@@ -265,7 +265,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; a run on several GPUs is not part of it "
+        print(json.dumps({"error": "bench.py measures one GPU; the path has no multi-GPU mode "
                                    "(--gpus must be 1)", "n_gpus": args.gpus}))
         sys.exit(2)
 
