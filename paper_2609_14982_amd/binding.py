@@ -462,7 +462,7 @@ class Batch:
         self.S = len(self.states)
         self.B = int(B)
         self.precision = precision
-        self.N = self.states[0].N
+        self.N = self.states[0].N if self.states else 0     # no states: the library reports it
         self.dtype = torch.float64 if precision == FM_FP64 else torch.float32
         arr = (C.c_void_p * self.S)(*[st.ptr.value for st in self.states])
         tun = None

@@ -183,6 +183,22 @@ def test_apply_argument_errors(c1):
     with pytest.raises(fm.FmError):
         fm.Batch(states, 3, fm.FM_FP64, tuning={"rhs_per_group": 2})
     batch.free()
+    # empty batches: no states, no right-hand sides
+    with pytest.raises(fm.FmError, match="at least one state"):
+        fm.Batch([], 16, fm.FM_FP64)
+    with pytest.raises(fm.FmError, match="B must be"):
+        fm.Batch(states, 0, fm.FM_FP64)
+    # states without receivers: node outputs work, receiver modes are refused
+    bare = fm.build_frozen_states(wl.dim, wl.n1, wl.n2, wl.n3, wl.G, wl.T, wl.s, wl.src)
+    b0 = fm.Batch(bare, 1, fm.FM_FP64)
+    assert b0.R == 0
+    b0.apply_J(x, fm.FM_DS_PER_PAIR, x.clone(), fm.FM_OUT_NODES)
+    b0.status()
+    y = x.clone()
+    with pytest.raises(fm.FmError, match="no receivers"):
+        fm.binding._check(fm.load().fm_apply_J(b0._ptr, fm.binding.C.c_void_p(x.data_ptr()), fm.FM_DS_PER_PAIR,
+                                               fm.binding.C.c_void_p(y.data_ptr()), fm.FM_OUT_RECEIVERS))
+    b0.free()
 
 
 def _sweep_run(states, B, direction, inp, in_mode, out_mode):
