@@ -1,6 +1,7 @@
-"""The GPU setup pass (fm_build_frozen_states_gpu): couplings of every
-source computed on the device (Sections 3.1-3.2), the rest of Phase I on the
-host from them.
+"""The GPU setup pass (fm_build_frozen_states_gpu): couplings, trimming,
+condensation levels and records of every source on the device (Sections
+3.1-3.2, 3.5, 4.1), the SCC search on the trimmed core and the block factors
+on host threads.
 
 * c1 (2-D), the curved fixture (six SCCs) and c3 (3-D, blocks up to 693
   nodes): W and c bit-identical to the oracle's assembly and to the host
@@ -10,7 +11,9 @@ host from them.
 * the singular fixture gives FM_ESINGULAR; a traveltime that is not finite
   or not 0 at the source gives FM_EINVAL;
 * c4 at full size (64 sources): identical statistics and operators on
-  sampled sources, and the setup time beside the host's.
+  sampled sources, the benchmarked apply (J from a broadcast block to the
+  receivers, J^T from the receivers to the source sum, balanced split)
+  bit-identical on both sets of states, and the setup time beside the host's.
 """
 import os
 import time
@@ -144,3 +147,25 @@ def test_c4_full_size_setup_time():
         assert sa == sb, a
     for a in (0, 23):
         _same_state(gpu[a], host[a])
+    # the benchmarked apply (broadcast model block to the receivers, receiver
+    # data back to the source sum) on both sets of states, at the schedule the
+    # search picks on this workload: the same bits
+    dev = torch.device("cuda:0")
+    B, R = 16, wl.rcv.shape[0]
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(5200)
+    p = torch.randn((wl.N, B), device=dev, dtype=torch.float64, generator=gen)
+    y = torch.randn((wl.S, R, B), device=dev, dtype=torch.float64, generator=gen)
+    outs = []
+    for states in (host, gpu):
+        batch = fm.Batch(states, B, fm.FM_FP64, tuning={"balance": 3, "threads": 256, "unroll": 3})
+        d = torch.empty((wl.S, R, B), device=dev, dtype=torch.float64)
+        g = torch.empty((wl.N, B), device=dev, dtype=torch.float64)
+        batch.apply_J(p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS)
+        batch.apply_JT(y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED)
+        batch.status()
+        outs.append((d, g))
+        batch.free()
+        torch.cuda.empty_cache()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    print("  benchmarked apply: host and GPU-pass states give the same bits", flush=True)
