@@ -11,6 +11,10 @@ assembly (oracle.assembly.cube_couplings), through the C ABI.
 * c3 at full size (101 x 101 x 51, 8 sources x 16 rhs) with the cube
   stencil: J and per-source J^T on three sampled sources against the
   oracle's converged Gauss-Seidel sweeping, and the pairing over all sources.
+* the benchmark's workload (201 x 201 x 101, 64 sources x 16 rhs) with the
+  cube stencil at the balanced split: J to nodes and receivers and
+  per-source J^T on four sampled sources against the oracle's sweeping, the
+  pairing over all sources.
 * The GPU setup pass and the sweeping baseline refuse cube-stencil states,
   and a batch cannot mix stencils.
 """
@@ -219,3 +223,64 @@ def test_point_sources_with_cube_stencil():
         ed, eg = rel_l2_pairs(d, ref_d), rel_l2(g, ref_g)
         print(f"  {tuning}: J {ed:.2e}, J^T {eg:.2e}", flush=True)
         assert ed <= TOL64 and eg <= TOL64
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_c4_full_size_cube():
+    """The benchmark's workload (201 x 201 x 101, 64 sources x 16 rhs, 400
+    receivers) with the cube stencil, all 64 states in one batch at the
+    balanced split with 256-thread workgroups: J from a broadcast block to
+    every node and to the receivers, and per-source J^T from receiver data,
+    on sampled sources (fewest and most block entries, deepest and shallowest
+    forward schedules, the middle and the last source) against the oracle's
+    converged Gauss-Seidel sweeping at 1e-11;
+    the transpose pairing over all sources."""
+    wl = W.config("c4")
+    wl.stencil = 26
+    S, B, R, N = wl.S, wl.B, wl.rcv.shape[0], wl.N
+    print(f"case cube stencil c4 201x201x101, S={S}, B={B}: building", flush=True)
+    states = states_for(fm, wl)
+    st = [s.stats() for s in states]
+    k2 = np.array([s["sum_k2"] for s in st])
+    lf = np.array([s["levels_fwd"] for s in st])
+    sample = sorted({int(np.argmin(k2)), int(np.argmax(k2)), int(np.argmax(lf)), int(np.argmin(lf)), S // 2, S - 1})
+    print(f"  sampled sources {sample}: sum k^2 {k2[sample].tolist()}, levels fwd {lf[sample].tolist()}", flush=True)
+    rng = np.random.default_rng(4600)
+    p = W.smooth_noise(wl, B, rng)
+    y = rng.standard_normal((S, R, B))
+    dev = torch.device("cuda:0")
+    batch = fm.Batch(states, B, fm.FM_FP64, tuning={"balance": 3, "threads": 256, "unroll": 3})
+    used = batch.tuning()
+    print(f"  schedule {used}", flush=True)
+    assert used["split"] > 1
+    d_p = torch.from_numpy(p).to(dev)
+    d_y = torch.from_numpy(y).to(dev)
+    idx = torch.tensor(sample, device=dev)
+    big = torch.empty((S, N, B), dtype=torch.float64, device=dev)
+    batch.apply_J(d_p, fm.FM_DS_BROADCAST, big, fm.FM_OUT_NODES)
+    batch.status()
+    xn = big.index_select(0, idx).cpu().numpy()
+    d = torch.empty((S, R, B), dtype=torch.float64, device=dev)
+    batch.apply_J(d_p, fm.FM_DS_BROADCAST, d, fm.FM_OUT_RECEIVERS)
+    batch.apply_JT(d_y, fm.FM_W_RECEIVERS, big, fm.FM_JT_PER_SOURCE)
+    g = torch.empty((N, B), dtype=torch.float64, device=dev)
+    batch.apply_JT(d_y, fm.FM_W_RECEIVERS, g, fm.FM_JT_SUMMED)
+    batch.status()
+    gn = big.index_select(0, idx).cpu().numpy()
+    d, g = d.cpu().numpy(), g.cpu().numpy()
+    del big
+    batch.free()
+    torch.cuda.empty_cache()
+    threads = min(16, os.cpu_count() or 1)
+    for i, a in enumerate(sample):
+        op = assemble_workload(wl, a)
+        xo = O.gs_solve(op, op.W, op.c[:, None] * p, nthreads=threads)
+        r = O.solve.scatter_receivers(op, y[a])
+        lam = O.gs_solve(op, op.WT(), r, nthreads=threads)
+        e = (rel_l2_pairs(xn[i:i + 1], xo[None]), rel_l2_pairs(d[a:a + 1], xo[wl.rcv][None]),
+             rel_l2_pairs(gn[i:i + 1], (op.c[:, None] * lam)[None]))
+        print(f"  source {a}: J nodes {e[0]:.2e}, J receivers {e[1]:.2e}, J^T {e[2]:.2e}", flush=True)
+        assert max(e) <= TOL64
+    for k in range(B):
+        assert _pairing(d[..., k], y[..., k], p[:, k], g[:, k]) <= TOL_ADJ
