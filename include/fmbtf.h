@@ -263,10 +263,12 @@ int fm_set_iterative_block_min(int32_t k_min);
  *   s        host [N]; G in g on the host; src_nodes host [S]
  *   receivers as fm_build_frozen_states_w (host, [S][n_rcv][k_per_rcv], weights may be NULL)
  *   nthreads host threads; hip_stream the stream of the device work (NULL: null stream)
- * Device scratch of about min(S, nthreads) x N x 79 bytes (at most ~2 GB),
- * pinned host staging of the same chunk x N x 58 bytes, and per host thread
- * about 40 x N bytes of device memory and 18 x N bytes of pinned host memory
- * are allocated and freed inside the call; each state holds its records
+ * Device scratch of about min(S, nthreads) x N x 91 bytes (at most ~2.3 GB),
+ * pinned host staging of the same chunk x N x 58 bytes, per host thread
+ * about 52 x N bytes of device memory and 18 x N bytes of pinned host
+ * memory, and a recycled pool of per-source couplings (57 x N bytes each,
+ * one per source in flight) are allocated and freed inside the call; each
+ * state holds its records
  * (about 80 x N bytes) on the device from the call on.  Face stencil only (fm_grid.stencil
  * 0 or 6, else FM_EINVAL).  Errors: as fm_build_frozen_states_w (a T that is
  * not finite or not 0 at the source gives FM_EINVAL); FM_EHIP for a failed
