@@ -265,7 +265,7 @@ int fm_set_iterative_block_min(int32_t k_min);
  *   nthreads host threads; hip_stream the stream of the device work (NULL: null stream)
  * Device scratch of about min(S, nthreads) x N x 91 bytes (at most ~2.3 GB),
  * pinned host staging of the same chunk x N x 58 bytes, per host thread
- * about 52 x N bytes of device memory and 18 x N bytes of pinned host
+ * about 56 x N bytes of device memory and 18 x N bytes of pinned host
  * memory, and a recycled pool of per-source couplings (57 x N bytes each,
  * one per source in flight) are allocated and freed inside the call; each
  * state holds its records
